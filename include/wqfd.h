@@ -1,0 +1,145 @@
+/*
+ * wqfd — weighted-quadrature row assembly for cut tensor-product B-spline meshes (gfx950).
+ *
+ * C ABI of libwqfd.so.  Method: Marussig, "Fast formation and assembly for spline-based
+ * 3D fictitious domain methods".  Mass and stiffness matrices of a degree-p, C^{p-1},
+ * open-uniform-knot tensor B-spline background mesh (identity map, Section 2) cut by a
+ * level-set domain, assembled row by row (one row per test function, Section 1) with
+ * sum factorization and weighted quadrature (WQ, Section 1 and Section 2.2 step 1);
+ * the regular part of each cut test function's support uses discontinuous weighted
+ * quadrature (DWQ, Section 2.2 steps 2-6 and Eq. (1)); the rest of its support is
+ * integrated element by element with Gauss rules on interior elements and octree
+ * sub-cells on cut elements.
+ *
+ * Conventions shared by every entry point
+ *  - Return value: WQ_OK (0) or a negative wq_status; a human-readable message for the
+ *    last failure on the calling thread is returned by wq_last_error().
+ *  - Argument errors (null pointers where data is required, dtype/which mismatch) are
+ *    detected before any device work is enqueued; nothing is written in that case.
+ *  - Device pointers (kappa, vals_*, G_*, dkappa) are caller-owned, contiguous, and must
+ *    hold the documented number of elements of the value type (double for WQ_F64,
+ *    float for WQ_F32).  The library never frees caller memory.
+ *  - Every call except wq_build_rules is asynchronous on the given HIP stream
+ *    (hipStream_t passed as void*; NULL = the default stream).  A rules handle is
+ *    immutable after wq_build_rules, so calls on different streams may share it.
+ *  - Value dtypes: kappa, the matrix values, the cotangents and dkappa all use the
+ *    selected dtype.  WQ rules, classification and octree geometry are always FP64;
+ *    the FP32 path rounds each FP64 table entry once and accumulates in FP32.
+ */
+#ifndef WQFD_H
+#define WQFD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    WQ_OK = 0,
+    WQ_EINVAL = -1,       /* invalid argument (message says which) */
+    WQ_ENOMEM = -2,       /* device allocation failed */
+    WQ_EHIP = -3,         /* HIP runtime error (message has the HIP error string) */
+    WQ_ESINGULAR = -4,    /* a WQ exactness system was rank deficient */
+    WQ_EUNSUPPORTED = -5  /* valid request outside this build's limits (e.g. p > 6) */
+} wq_status;
+
+typedef enum { WQ_F64 = 0, WQ_F32 = 1 } wq_dtype;
+
+enum { WQ_MASS = 1u, WQ_STIFF = 2u };   /* 'which' bit mask */
+
+/* Background mesh: nel[d] uniform elements on [lo[d], hi[d]], degree 1 <= p <= 6, open
+ * knot vectors with maximal smoothness C^{p-1} (Section 1, Section 2). */
+typedef struct {
+    int32_t nel[3];
+    int32_t degree;
+    double lo[3], hi[3];
+} wq_mesh;
+
+/* Domain Omega = {phi < 0} (Section 2.1: Omega^v, interface Gamma).
+ * kind 0: no cut.  1: plane phi = (n.x - r0)/|n|.  2: ball phi = |x - c| - r0.
+ * 3: torus around the axis through c parallel to z, major radius r0, minor r1. */
+typedef struct {
+    int32_t kind;
+    double c[3], n[3], r0, r1;
+} wq_levelset;
+
+typedef struct {
+    int32_t octree_levels;   /* depth of the cut-element octree, 0..5 (default 3) */
+    int32_t flags;           /* reserved, must be 0 */
+} wq_options;
+
+typedef struct wq_rules wq_rules;   /* opaque; owns its device buffers */
+
+/* Read-only views of a rules handle (device pointers owned by the handle, valid until
+ * wq_rules_free). */
+typedef struct {
+    int64_t n_active;        /* matrix dimension: active (non-exterior) functions */
+    int64_t nnz;             /* entries per matrix */
+    int64_t n_rows_interior; /* interior test functions (all support in Omega) */
+    int64_t n_rows_cut;      /* cut test functions */
+    int64_t n_rows_split;    /* cut functions that have a DWQ box */
+    int64_t n_dwq_rules;     /* distinct one-sided 1D DWQ rules */
+    int64_t n_kappa;         /* kappa slots = n_grid + n_block + n_octree */
+    int64_t n_grid;          /* WQ tensor grid X1 x X2 x X3, lexicographic */
+    int64_t n_block;         /* element Gauss blocks, (p+1)^3 per block element */
+    int64_t n_octree;        /* octree points, (p+1)^3 per octree leaf */
+    int64_t n_block_elems;   /* elements carrying a Gauss block */
+    int64_t n_cut_elems;     /* cut elements */
+    int64_t n_cells;         /* octree leaves */
+    int64_t n_line_blocks;   /* interior row blocks of the fast kernel */
+    int32_t grid_dims[3];    /* |X_d| */
+    int32_t nfun[3];         /* functions per direction, nel[d] + p */
+    const int64_t* row_ptr;        /* (n_active+1) CSR row pointer */
+    const int32_t* col_idx;        /* (nnz) active column indices, ascending per row */
+    const int32_t* active_to_lex;  /* (n_active) lexicographic function index, first index slowest */
+    const double* kappa_xyz;       /* (n_kappa, 3) slot coordinates */
+    const double* octree_w;        /* (n_octree) octree weights (0 outside Omega) */
+    const int32_t* block_elems;    /* (n_block_elems) lexicographic element index per block */
+    const int8_t* fun_class;       /* (nfun product) 0 exterior, 1 interior, 2 cut */
+    const int8_t* elem_class;      /* (nel product) 0 exterior, 1 interior, 2 cut */
+    const int32_t* split;          /* (n_rows_cut, 4) d, s, high, rule (-1: no box) per cut row */
+    const int32_t* cut_rows;       /* (n_rows_cut) active index of each cut row */
+} wq_rules_info;
+
+/* Builds everything that does not depend on kappa (Section 2.2 steps 1-6, Section 2.1):
+ * Gauss rules, the WQ point layout (two Gauss points per inner element, all p+1 in the
+ * boundary elements), 1D WQ rules for mass (00) and stiffness (11) by FP64 min-norm
+ * solves, element/function classification, the CSR pattern (row I holds every active J
+ * with max_d |I_d - J_d| <= p), DWQ splits and one-sided rules, element Gauss blocks,
+ * octree cells and the kappa slot layout.  Synchronous: returns once the handle is ready.
+ * opts may be NULL (octree_levels = 3).  On success *out receives a new handle. */
+int wq_build_rules(const wq_mesh* mesh, const wq_levelset* ls, const wq_options* opts,
+                   void* stream, wq_rules** out);
+
+int wq_rules_info_get(const wq_rules* rules, wq_rules_info* out);
+
+/* Row assembly (Section 1: sum factorization + weighted quadrature + row loop; Section
+ * 2.2 DWQ for cut rows).  For every interior row writes the full WQ row; for every cut
+ * row with a DWQ box writes the box part; every other cut row is set to zero.  All nnz
+ * entries of each requested matrix are OVERWRITTEN.
+ * kappa: (n_kappa) values at the slots.  vals_mass / vals_stiff: (nnz) outputs; each may
+ * be NULL iff its bit is absent from which. */
+int wq_assemble_rows(const wq_rules* rules, int dtype, uint32_t which, const void* kappa,
+                     void* vals_mass, void* vals_stiff, void* stream);
+
+/* Cut part of Eq. (1): element Gauss on the interior elements of each cut row's support
+ * outside its DWQ box, and octree Gauss on every cut element.  ACCUMULATES into the
+ * values (call after wq_assemble_rows on the same stream). */
+int cut_assemble(const wq_rules* rules, int dtype, uint32_t which, const void* kappa,
+                 void* vals_mass, void* vals_stiff, void* stream);
+
+/* Adjoint of rows + cut parts: for L = sum_IJ (G_mass_IJ M_IJ + G_stiff_IJ K_IJ),
+ * dkappa[slot] = dL/dkappa(slot), summed over every use of the slot.  dkappa (n_kappa) is
+ * OVERWRITTEN.  G_mass / G_stiff: (nnz) cotangents on the pattern; each may be NULL iff
+ * its bit is absent from which. */
+int wq_assemble_adjoint(const wq_rules* rules, int dtype, uint32_t which, const void* G_mass,
+                        const void* G_stiff, void* dkappa, void* stream);
+
+void wq_rules_free(wq_rules* rules);
+const char* wq_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WQFD_H */

@@ -1,0 +1,178 @@
+"""Python face of libwqfd: rules handles, assembly calls and the autograd function.
+
+PyTorch supplies device memory and the current stream; all computation happens in the HIP
+library behind the C ABI of include/wqfd.h.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import sys
+
+import torch
+
+from . import _lib as L
+
+_DT = {torch.float64: L.WQ_F64, torch.float32: L.WQ_F32}
+
+
+def _stream_handle(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _need(t, n, dtype, device, name):
+    if t is None:
+        return
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous() and t.numel() == n and t.device == device):
+        raise ValueError(f"{name}: expected a contiguous {dtype} tensor of {n} elements on {device}, "
+                         f"got {tuple(t.shape)} {t.dtype} on {t.device}")
+
+
+class Rules:
+    """Kappa-independent data of one mesh + domain (built on the GPU, FP64)."""
+
+    def __init__(self, nel, degree, levelset=None, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), octree_levels=3,
+                 device=None):
+        lib = L.load()
+        if isinstance(nel, int):
+            nel = (nel, nel, nel)
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        mesh = L.WqMesh((C.c_int32 * 3)(*nel), int(degree), (C.c_double * 3)(*lo), (C.c_double * 3)(*hi))
+        ls = L.WqLevelset()
+        if levelset is not None:
+            ls.kind = int(levelset.kind)
+            ls.c = (C.c_double * 3)(*levelset.c)
+            ls.n = (C.c_double * 3)(*levelset.n)
+            ls.r0, ls.r1 = float(levelset.r0), float(levelset.r1)
+        opts = L.WqOptions(int(octree_levels), 0)
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            L.check(lib.wq_build_rules(C.byref(mesh), C.byref(ls), C.byref(opts),
+                                       C.c_void_p(_stream_handle(self.device)), C.byref(h)))
+        self._h = h
+        self.degree = int(degree)
+        self.nel = tuple(nel)
+        info = L.WqRulesInfo()
+        L.check(lib.wq_rules_info_get(h, C.byref(info)))
+        self._info = info
+        for k in ("n_active", "nnz", "n_rows_interior", "n_rows_cut", "n_rows_split", "n_dwq_rules", "n_kappa",
+                  "n_grid", "n_block", "n_octree", "n_block_elems", "n_cut_elems", "n_cells", "n_line_blocks"):
+            setattr(self, k, int(getattr(info, k)))
+        self.grid_dims = tuple(info.grid_dims)
+        self.nfun = tuple(info.nfun)
+
+    @classmethod
+    def from_workload(cls, wl, device=None):
+        return cls(wl.nel, wl.degree, wl.levelset, wl.lo, wl.hi, wl.octree_levels, device)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if sys.is_finalizing():
+            return
+        if h is not None and h.value:
+            L.load().wq_rules_free(h)
+            self._h = None
+
+    # --- read-only views (copied into torch tensors) ---------------------------------
+    def _view(self, field, n, dtype, shape=None):
+        out = torch.empty(n, dtype=dtype, device=self.device)
+        ptr = getattr(self._info, field)
+        if n > 0:
+            hip = L.hip_runtime()
+            with torch.cuda.device(self.device):
+                rc = hip.hipMemcpyAsync(C.c_void_p(out.data_ptr()), C.c_void_p(ptr), out.numel() * out.element_size(),
+                                        3, C.c_void_p(_stream_handle(self.device)))
+            if rc != 0:
+                raise RuntimeError(f"hipMemcpyAsync failed ({rc})")
+        return out if shape is None else out.view(*shape)
+
+    def row_ptr(self):
+        return self._view("row_ptr", self.n_active + 1, torch.int64)
+
+    def col_idx(self):
+        return self._view("col_idx", self.nnz, torch.int32)
+
+    def active_to_lex(self):
+        return self._view("active_to_lex", self.n_active, torch.int32)
+
+    def kappa_xyz(self):
+        return self._view("kappa_xyz", 3 * self.n_kappa, torch.float64, (self.n_kappa, 3))
+
+    def octree_w(self):
+        return self._view("octree_w", self.n_octree, torch.float64)
+
+    def block_elems(self):
+        return self._view("block_elems", self.n_block_elems, torch.int32)
+
+    def fun_class(self):
+        return self._view("fun_class", self.nfun[0] * self.nfun[1] * self.nfun[2], torch.int8)
+
+    def elem_class(self):
+        return self._view("elem_class", self.nel[0] * self.nel[1] * self.nel[2], torch.int8)
+
+    def split(self):
+        return self._view("split", 4 * self.n_rows_cut, torch.int32, (self.n_rows_cut, 4))
+
+    def cut_rows(self):
+        return self._view("cut_rows", self.n_rows_cut, torch.int32)
+
+    # --- assembly -----------------------------------------------------------------------
+    def _call(self, fn, kappa, vm, vk, which):
+        dtype = kappa.dtype
+        if dtype not in _DT:
+            raise ValueError(f"unsupported dtype {dtype}")
+        _need(kappa, self.n_kappa, dtype, self.device, "kappa")
+        _need(vm, self.nnz, dtype, self.device, "vals_mass")
+        _need(vk, self.nnz, dtype, self.device, "vals_stiff")
+        L.check(fn(self._h, _DT[dtype], int(which), _ptr(kappa), _ptr(vm), _ptr(vk),
+                   C.c_void_p(_stream_handle(self.device))))
+
+    def assemble_rows(self, kappa, vals_mass=None, vals_stiff=None, which=None):
+        which = which if which is not None else (L.WQ_MASS if vals_mass is not None else 0) | \
+            (L.WQ_STIFF if vals_stiff is not None else 0)
+        self._call(L.load().wq_assemble_rows, kappa, vals_mass, vals_stiff, which)
+
+    def cut_assemble(self, kappa, vals_mass=None, vals_stiff=None, which=None):
+        which = which if which is not None else (L.WQ_MASS if vals_mass is not None else 0) | \
+            (L.WQ_STIFF if vals_stiff is not None else 0)
+        self._call(L.load().cut_assemble, kappa, vals_mass, vals_stiff, which)
+
+    def assemble(self, kappa, which=L.WQ_MASS | L.WQ_STIFF):
+        """Whole matrices: rows, then the cut part. Returns (M values or None, K values or None)."""
+        vm = torch.empty(self.nnz, dtype=kappa.dtype, device=self.device) if which & L.WQ_MASS else None
+        vk = torch.empty(self.nnz, dtype=kappa.dtype, device=self.device) if which & L.WQ_STIFF else None
+        self.assemble_rows(kappa, vm, vk, which)
+        self.cut_assemble(kappa, vm, vk, which)
+        return vm, vk
+
+    def adjoint(self, g_mass=None, g_stiff=None, out=None):
+        """dL/dkappa over all slots for L = <G_mass, M> + <G_stiff, K>."""
+        ref = g_mass if g_mass is not None else g_stiff
+        which = (L.WQ_MASS if g_mass is not None else 0) | (L.WQ_STIFF if g_stiff is not None else 0)
+        dk = torch.empty(self.n_kappa, dtype=ref.dtype, device=self.device) if out is None else out
+        _need(dk, self.n_kappa, ref.dtype, self.device, "dkappa")
+        _need(g_mass, self.nnz, ref.dtype, self.device, "G_mass")
+        _need(g_stiff, self.nnz, ref.dtype, self.device, "G_stiff")
+        L.check(L.load().wq_assemble_adjoint(self._h, _DT[ref.dtype], which, _ptr(g_mass), _ptr(g_stiff), _ptr(dk),
+                                             C.c_void_p(_stream_handle(self.device))))
+        return dk
+
+
+class WQAssemble(torch.autograd.Function):
+    """(M, K) = assembly(kappa); backward returns dL/dkappa through the adjoint kernels."""
+
+    @staticmethod
+    def forward(ctx, kappa, rules: Rules):
+        vm, vk = rules.assemble(kappa.contiguous(), L.WQ_MASS | L.WQ_STIFF)
+        ctx.rules = rules
+        return vm, vk
+
+    @staticmethod
+    def backward(ctx, gm, gk):
+        rules = ctx.rules
+        gm = gm.contiguous() if gm is not None else None
+        gk = gk.contiguous() if gk is not None else None
+        return rules.adjoint(gm, gk), None

@@ -1,0 +1,567 @@
+// Adjoint of the assembly: for L = sum_IJ (GM_IJ M_IJ + GK_IJ K_IJ), dL/dkappa at every slot.
+//
+// Every part of the forward is linear in kappa with a tensor-product structure, so the
+// adjoint runs the same contractions transposed: the cotangent row (j1, j2, j3) is
+// contracted with the direction-1 weights, then direction 2, then direction 3, and the
+// result is added into dkappa at the quadrature points (atomics where several rows share a
+// point).  The cotangents carry one value per pattern entry, like the matrices.
+#include "rows.h"
+
+template <typename T> __device__ inline const T* wt_tab(const DevRules& R, int d);
+template <> __device__ inline const double* wt_tab<double>(const DevRules& R, int d) { return R.Wt64[d]; }
+template <> __device__ inline const float* wt_tab<float>(const DevRules& R, int d) { return R.Wt32[d]; }
+template <typename T> __device__ inline const T* dwq_tab(const DevRules& R);
+template <> __device__ inline const double* dwq_tab<double>(const DevRules& R) { return R.dwq_Wt64; }
+template <> __device__ inline const float* dwq_tab<float>(const DevRules& R) { return R.dwq_Wt32; }
+
+__device__ inline int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ inline void unlex3a(int64_t k, const int* n, int* I) {
+    I[2] = (int)(k % n[2]);
+    I[1] = (int)((k / n[2]) % n[1]);
+    I[0] = (int)(k / ((int64_t)n[1] * n[2]));
+}
+
+__device__ inline void wave_sync_a() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T>
+__global__ void k_fill(T* p, int64_t n, T v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// ----------------------------------------------------------------------------------------
+// interior rows (line blocks), transposed stages 3 -> 2 -> 1
+// ----------------------------------------------------------------------------------------
+template <typename T, int P, int WHICH, int RB>
+struct AdjCfg {
+    static constexpr int M = 2 * P + 1, NW = 4 * P, MM = M * M;
+    static constexpr int GT = ((MM + 63) / 64) * 64;
+    static constexpr int NT = GT >= 256 ? GT : 256;
+    static constexpr int NG = NT / GT;
+    static constexpr int NQ1 = 2 * RB + 4 * P;
+    static constexpr int QC = P <= 4 ? 8 : 4;             // q1 chunk of the stage-2/1 pass
+    static constexpr bool STIFF = (WHICH & 2) != 0, MASS = (WHICH & 1) != 0;
+};
+
+template <typename T, int P, int WHICH, int RB>
+__global__ void __launch_bounds__((AdjCfg<T, P, WHICH, RB>::NT))
+k_adj_interior(DevRules R, const T* __restrict__ gm, const T* __restrict__ gk, T* __restrict__ dk) {
+    using C = AdjCfg<T, P, WHICH, RB>;
+    constexpr int M = C::M, NW = C::NW, MM = C::MM, QC = C::QC;
+    __shared__ T s_a0[C::NQ1 * MM];
+    __shared__ T s_a1[C::STIFF ? C::NQ1 * MM : 1];
+    __shared__ T s_b[2][QC * NW * M];
+    __shared__ T s_w2[2 * M * NW], s_w3[2 * M * NW];
+    const int4 blk = R.lblocks[blockIdx.x];
+    const int i1s = blk.x, i2 = blk.y, i3 = blk.z, nrows = blk.w;
+    const T* W1 = wt_tab<T>(R, 0);
+    const T* W2 = wt_tab<T>(R, 1) + (int64_t)i2 * 2 * M * NW;
+    const T* W3 = wt_tab<T>(R, 2) + (int64_t)i3 * 2 * M * NW;
+    for (int k = threadIdx.x; k < 2 * M * NW; k += C::NT) { s_w2[k] = W2[k]; s_w3[k] = W3[k]; }
+    const int qbase = R.xs[0][i1s];
+    const int i1e = i1s + nrows - 1;
+    const int nq1 = R.xs[0][i1e] + R.nwin[0][i1e] - qbase;
+    for (int k = threadIdx.x; k < nq1 * MM; k += C::NT) {
+        s_a0[k] = 0;
+        if (C::STIFF) s_a1[k] = 0;
+    }
+    const int xs2 = R.xs[1][i2], nw2 = R.nwin[1][i2];
+    const int xs3 = R.xs[2][i3], nw3 = R.nwin[2][i3];
+    const int nx2 = R.nx[1], nx3 = R.nx[2];
+    __syncthreads();
+    // stage 3^T
+    const int grp = uni(threadIdx.x / C::GT);
+    const int c = threadIdx.x % C::GT;
+    const int jj2 = c / M, jj3 = c % M;
+    const int p = P;
+    const int lo2 = i2 - p < 0 ? p - i2 : 0, hi2 = i2 + p > R.nfun[1] - 1 ? R.nfun[1] - 1 - i2 + p : 2 * p;
+    const int lo3 = i3 - p < 0 ? p - i3 : 0, hi3 = i3 + p > R.nfun[2] - 1 ? R.nfun[2] - 1 - i3 + p : 2 * p;
+    const int m2 = hi2 - lo2 + 1, m3 = hi3 - lo3 + 1;
+    const bool live = c < MM && jj2 >= lo2 && jj2 <= hi2 && jj3 >= lo3 && jj3 <= hi3;
+    const int64_t nl = (int64_t)R.nfun[1] * R.nfun[2];
+    for (int r = grp; r < nrows; r += C::NG) {
+        const int i1 = uni(i1s + r);
+        const int ra = uni(R.lex2act[(int64_t)i1 * nl + (int64_t)i2 * R.nfun[2] + i3]);
+        const int64_t base = R.row_ptr[ra];
+        const int off = uni(R.xs[0][i1] - qbase);
+        const int nw1 = uni(R.nwin[0][i1]);
+        const int lo1 = i1 - p < 0 ? p - i1 : 0, hi1 = i1 + p > R.nfun[0] - 1 ? R.nfun[0] - 1 - i1 + p : 2 * p;
+        T g0[M], g1[M];
+#pragma unroll
+        for (int jj1 = 0; jj1 < M; ++jj1) {
+            g0[jj1] = 0; g1[jj1] = 0;
+            if (live && jj1 >= lo1 && jj1 <= hi1) {
+                const int64_t o = base + ((int64_t)(jj1 - lo1) * m2 + (jj2 - lo2)) * m3 + (jj3 - lo3);
+                if (C::MASS) g0[jj1] = gm[o];
+                if (C::STIFF) g1[jj1] = gk[o];
+            }
+        }
+        const T* w10 = W1 + (int64_t)i1 * 2 * M * NW;
+        const T* w11 = w10 + M * NW;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) {
+            if (q >= nw1) break;
+            T a0 = 0, a1 = 0;
+#pragma unroll
+            for (int jj1 = 0; jj1 < M; ++jj1) {
+                const T w0 = w10[jj1 * NW + q];
+                if (C::MASS) a0 += w0 * g0[jj1];
+                if (C::STIFF) { a0 += w11[jj1 * NW + q] * g1[jj1]; a1 += w0 * g1[jj1]; }
+            }
+            if (live) {
+                atomicAdd(&s_a0[(off + q) * MM + c], a0);
+                if (C::STIFF) atomicAdd(&s_a1[(off + q) * MM + c], a1);
+            }
+        }
+    }
+    __syncthreads();
+    // stages 2^T and 1^T by chunks of q1
+    for (int q1c = 0; q1c < nq1; q1c += QC) {
+        const int nqc = nq1 - q1c < QC ? nq1 - q1c : QC;
+        for (int it = threadIdx.x; it < nqc * M; it += C::NT) {
+            const int ql = it / M, j3 = it % M;
+            const int q1 = q1c + ql;
+            T b0[NW], b1[NW];
+#pragma unroll
+            for (int q2 = 0; q2 < NW; ++q2) { b0[q2] = 0; b1[q2] = 0; }
+#pragma unroll
+            for (int j2 = 0; j2 < M; ++j2) {
+                const T a0 = s_a0[q1 * MM + j2 * M + j3];
+                const T a1 = C::STIFF ? s_a1[q1 * MM + j2 * M + j3] : (T)0;
+#pragma unroll
+                for (int q2 = 0; q2 < NW; ++q2) {
+                    if (q2 < nw2) {
+                        b0[q2] += s_w2[j2 * NW + q2] * a0;
+                        if (C::STIFF) { b0[q2] += s_w2[(M + j2) * NW + q2] * a1; b1[q2] += s_w2[j2 * NW + q2] * a1; }
+                    }
+                }
+            }
+#pragma unroll
+            for (int q2 = 0; q2 < NW; ++q2) {
+                if (q2 < nw2) {
+                    s_b[0][(ql * NW + q2) * M + j3] = b0[q2];
+                    if (C::STIFF) s_b[1][(ql * NW + q2) * M + j3] = b1[q2];
+                }
+            }
+        }
+        __syncthreads();
+        for (int it = threadIdx.x; it < nqc * nw2; it += C::NT) {
+            const int ql = it / nw2, q2 = it % nw2;
+            T bb0[M], bb1[M];
+#pragma unroll
+            for (int j3 = 0; j3 < M; ++j3) {
+                bb0[j3] = s_b[0][(ql * NW + q2) * M + j3];
+                bb1[j3] = C::STIFF ? s_b[1][(ql * NW + q2) * M + j3] : (T)0;
+            }
+            T* dst = dk + ((int64_t)(qbase + q1c + ql) * nx2 + xs2 + q2) * nx3 + xs3;
+            for (int q3 = 0; q3 < nw3; ++q3) {
+                T v = 0;
+#pragma unroll
+                for (int j3 = 0; j3 < M; ++j3) {
+                    v += s_w3[j3 * NW + q3] * bb0[j3];
+                    if (C::STIFF) v += s_w3[(M + j3) * NW + q3] * bb1[j3];
+                }
+                atomicAdd(&dst[q3], v);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ----------------------------------------------------------------------------------------
+// cut rows with a DWQ box: transposed stages C -> B -> A, kappa slots through slot_of
+// ----------------------------------------------------------------------------------------
+template <typename T, int P, int WHICH>
+__global__ void __launch_bounds__(256)
+k_adj_cut(DevRules R, const T* __restrict__ gm, const T* __restrict__ gk, T* __restrict__ dk) {
+    constexpr int M = 2 * P + 1, NW = 4 * P, NDQ = P * (P + 1), MM = M * M, M3 = M * M * M;
+    constexpr int NA = NDQ > NW ? NDQ : NW;
+    constexpr bool MASS = (WHICH & 1) != 0, STIFF = (WHICH & 2) != 0;
+    __shared__ T s_w[3][2 * M * NA];
+    __shared__ int s_y[3][NA];
+    __shared__ int s_n[3];
+    __shared__ T s_g[2][M3];                      // cotangent window [v][jC][jB][jA]
+    __shared__ T s_c[2][NW * MM];                 // [v][qC][jB jA]
+    const int64_t cr = blockIdx.x;
+    const int4 sp = R.split[cr];
+    if (sp.x < 0) return;
+    const int ra = R.cut_rows[cr];
+    int I[3];
+    unlex3a(R.act2lex[ra], R.nfun, I);
+    const int dA = sp.x, dB = dA == 0 ? 1 : 0, dC = dA == 2 ? 1 : 2;
+    const int dirs[3] = {dA, dB, dC};
+    for (int sl = 0; sl < 3; ++sl) {
+        const int d = dirs[sl];
+        if (sl == 0) {
+            const int r = sp.w;
+            const int np = R.dwq_np[r];
+            const T* W = dwq_tab<T>(R) + (int64_t)r * 2 * M * NDQ;
+            for (int k = threadIdx.x; k < 2 * M * NA; k += 256) {
+                const int q = k % NA, row = k / NA;
+                s_w[sl][k] = q < NDQ ? W[row * NDQ + q] : (T)0;
+            }
+            for (int q = threadIdx.x; q < NA; q += 256) s_y[sl][q] = q < np ? R.dwq_y[(int64_t)r * NDQ + q] : 0;
+            if (threadIdx.x == 0) s_n[sl] = np;
+        } else {
+            const int i = I[d];
+            const int xs = R.xs[d][i], nw = R.nwin[d][i];
+            const T* W = wt_tab<T>(R, d) + (int64_t)i * 2 * M * NW;
+            for (int k = threadIdx.x; k < 2 * M * NA; k += 256) {
+                const int q = k % NA, row = k / NA;
+                s_w[sl][k] = q < NW ? W[row * NW + q] : (T)0;
+            }
+            for (int q = threadIdx.x; q < NA; q += 256) s_y[sl][q] = q < nw ? R.x2y[d][xs + q] : 0;
+            if (threadIdx.x == 0) s_n[sl] = nw;
+        }
+    }
+    // gather the cotangent row into the local window, ordered [jC][jB][jA]
+    const int32_t* pos = R.pos_map + cr * (int64_t)M3;
+    const int64_t rb = R.row_ptr[ra];
+    for (int k = threadIdx.x; k < M3; k += 256) {
+        const int jj0 = k / (M * M), jj1 = (k / M) % M, jj2 = k % M;
+        const int jj[3] = {jj0, jj1, jj2};
+        const int o = pos[k];
+        const int l = (jj[dC] * M + jj[dB]) * M + jj[dA];
+        s_g[0][l] = (o >= 0 && MASS) ? gm[rb + o] : (T)0;
+        s_g[1][l] = (o >= 0 && STIFF) ? gk[rb + o] : (T)0;
+    }
+    __syncthreads();
+    const int nA = s_n[0], nB = s_n[1], nC = s_n[2];
+    // C^T: C0[qC][jB jA] = sum_jC W_C^0 GM + W_C^1 GK; C1 = sum_jC W_C^0 GK
+    for (int it = threadIdx.x; it < nC * MM; it += 256) {
+        const int qC = it / MM, cc = it % MM;
+        T c0 = 0, c1 = 0;
+        for (int jC = 0; jC < M; ++jC) {
+            const T w0 = s_w[2][jC * NA + qC];
+            if (MASS) c0 += w0 * s_g[0][jC * MM + cc];
+            if (STIFF) { c0 += s_w[2][(M + jC) * NA + qC] * s_g[1][jC * MM + cc]; c1 += w0 * s_g[1][jC * MM + cc]; }
+        }
+        s_c[0][qC * MM + cc] = c0;
+        if (STIFF) s_c[1][qC * MM + cc] = c1;
+    }
+    __syncthreads();
+    // B^T and A^T per (qC, qB): b[jA] = sum_jB W_B C; dk(qA, qB, qC) += sum_jA W_A b
+    for (int it = threadIdx.x; it < nC * nB; it += 256) {
+        const int qC = it / nB, qB = it % nB;
+        T b0[M], b1[M];
+#pragma unroll
+        for (int jA = 0; jA < M; ++jA) {
+            T s0 = 0, s1 = 0;
+            for (int jB = 0; jB < M; ++jB) {
+                const T w0 = s_w[1][jB * NA + qB];
+                const T c0 = s_c[0][qC * MM + jB * M + jA];
+                s0 += w0 * c0;
+                if (STIFF) {
+                    const T c1 = s_c[1][qC * MM + jB * M + jA];
+                    s0 += s_w[1][(M + jB) * NA + qB] * c1;
+                    s1 += w0 * c1;
+                }
+            }
+            b0[jA] = s0; b1[jA] = s1;
+        }
+        int y[3];
+        y[dB] = s_y[1][qB]; y[dC] = s_y[2][qC];
+        for (int qA = 0; qA < nA; ++qA) {
+            y[dA] = s_y[0][qA];
+            T v = 0;
+#pragma unroll
+            for (int jA = 0; jA < M; ++jA) {
+                v += s_w[0][jA * NA + qA] * b0[jA];
+                if (STIFF) v += s_w[0][(M + jA) * NA + qA] * b1[jA];
+            }
+            atomicAdd(&dk[slot_of(R, y[0], y[1], y[2])], v);
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------------------
+// remainder elements (element Gauss) of cut rows
+// ----------------------------------------------------------------------------------------
+template <typename T, int P, int WHICH>
+__global__ void __launch_bounds__(256)
+k_adj_remainder(DevRules R, const int32_t* __restrict__ box, const T* __restrict__ gm, const T* __restrict__ gk,
+                T* __restrict__ dk) {
+    constexpr int P1 = P + 1, NP = P1 * P1 * P1, M = 2 * P + 1, M3 = M * M * M, NWAVE = 4;
+    constexpr bool MASS = (WHICH & 1) != 0, STIFF = (WHICH & 2) != 0;
+    __shared__ T s_g[2][M3];
+    __shared__ T s_w[NWAVE][3][2][P1 * P1];
+    __shared__ T s_c[NWAVE][2][NP];
+    __shared__ T s_b[NWAVE][2][NP];
+    const int64_t cr = blockIdx.x;
+    const int ra = R.cut_rows[cr];
+    int I[3];
+    unlex3a(R.act2lex[ra], R.nfun, I);
+    const int32_t* pos = R.pos_map + cr * (int64_t)M3;
+    const int64_t rb = R.row_ptr[ra];
+    for (int k = threadIdx.x; k < M3; k += 256) {
+        const int o = pos[k];
+        s_g[0][k] = (o >= 0 && MASS) ? gm[rb + o] : (T)0;
+        s_g[1][k] = (o >= 0 && STIFF) ? gk[rb + o] : (T)0;
+    }
+    int lo[3], hi[3], blo[3], bhi[3];
+    const bool has_box = R.split[cr].x >= 0;
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = I[d] - P < 0 ? 0 : I[d] - P;
+        hi[d] = I[d] < R.nel[d] - 1 ? I[d] : R.nel[d] - 1;
+        blo[d] = box[cr * 6 + 2 * d];
+        bhi[d] = box[cr * 6 + 2 * d + 1];
+    }
+    __syncthreads();
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int n2 = hi[1] - lo[1] + 1, n3 = hi[2] - lo[2] + 1;
+    const int ne = (hi[0] - lo[0] + 1) * n2 * n3;
+    for (int k = wave; k < ne; k += NWAVE) {
+        const int e[3] = {lo[0] + k / (n2 * n3), lo[1] + (k / n3) % n2, lo[2] + k % n3};
+        const int64_t eid = ((int64_t)e[0] * R.nel[1] + e[1]) * R.nel[2] + e[2];
+        if (R.ecls[eid] != CLS_IN) continue;
+        if (has_box && e[0] >= blo[0] && e[0] <= bhi[0] && e[1] >= blo[1] && e[1] <= bhi[1] && e[2] >= blo[2] &&
+            e[2] <= bhi[2])
+            continue;
+        for (int t = lane; t < 3 * 2 * P1 * P1; t += 64) {
+            const int d = t / (2 * P1 * P1), a = (t / (P1 * P1)) % 2, kk = (t / P1) % P1, g = t % P1;
+            const int64_t y = (int64_t)e[d] * P1 + g;
+            const double* tab = a ? R.dBval[d] : R.Bval[d];
+            const double om = R.gw[g] * R.h[d] * 0.5;
+            s_w[wave][d][a][kk * P1 + g] = (T)(om * tab[y * P1 + (I[d] - e[d])] * tab[y * P1 + kk]);
+        }
+        wave_sync_a();
+        // 1^T: C[v][g1][k2][k3] = sum_k1 W1[k1][g1] G[k1][k2][k3]
+        for (int t = lane; t < NP; t += 64) {
+            const int g1 = t / (P1 * P1), k23 = t % (P1 * P1);
+            const int k2 = k23 / P1, k3 = k23 % P1;
+            T c0 = 0, c1 = 0;
+            for (int k1 = 0; k1 < P1; ++k1) {
+                const int jj = ((e[0] + k1 - I[0] + P) * M + (e[1] + k2 - I[1] + P)) * M + (e[2] + k3 - I[2] + P);
+                const T w0 = s_w[wave][0][0][k1 * P1 + g1];
+                if (MASS) c0 += w0 * s_g[0][jj];
+                if (STIFF) { c0 += s_w[wave][0][1][k1 * P1 + g1] * s_g[1][jj]; c1 += w0 * s_g[1][jj]; }
+            }
+            s_c[wave][0][t] = c0;
+            if (STIFF) s_c[wave][1][t] = c1;
+        }
+        wave_sync_a();
+        // 2^T: B[v][g1][g2][k3]
+        for (int t = lane; t < NP; t += 64) {
+            const int g1 = t / (P1 * P1), g2 = (t / P1) % P1, k3 = t % P1;
+            T b0 = 0, b1 = 0;
+            for (int k2 = 0; k2 < P1; ++k2) {
+                const T c0 = s_c[wave][0][(g1 * P1 + k2) * P1 + k3];
+                const T w0 = s_w[wave][1][0][k2 * P1 + g2];
+                b0 += w0 * c0;
+                if (STIFF) {
+                    const T c1 = s_c[wave][1][(g1 * P1 + k2) * P1 + k3];
+                    b0 += s_w[wave][1][1][k2 * P1 + g2] * c1;
+                    b1 += w0 * c1;
+                }
+            }
+            s_b[wave][0][t] = b0;
+            if (STIFF) s_b[wave][1][t] = b1;
+        }
+        wave_sync_a();
+        // 3^T: dk(g1, g2, g3)
+        for (int t = lane; t < NP; t += 64) {
+            const int g12 = t / P1, g3 = t % P1;
+            T v = 0;
+            for (int k3 = 0; k3 < P1; ++k3) {
+                v += s_w[wave][2][0][k3 * P1 + g3] * s_b[wave][0][g12 * P1 + k3];
+                if (STIFF) v += s_w[wave][2][1][k3 * P1 + g3] * s_b[wave][1][g12 * P1 + k3];
+            }
+            const int g1 = g12 / P1, g2 = g12 % P1;
+            atomicAdd(&dk[slot_of(R, e[0] * P1 + g1, e[1] * P1 + g2, e[2] * P1 + g3)], v);
+        }
+        wave_sync_a();
+    }
+}
+
+// ----------------------------------------------------------------------------------------
+// octree cut elements: dk_g = w_g sum_ab (GM_ab phi_a phi_b + GK_ab grad phi_a . grad phi_b)
+// ----------------------------------------------------------------------------------------
+template <int P> struct OctAdjCfg {
+    static constexpr int P1 = P + 1, NP = P1 * P1 * P1, P2 = P1 * P1;
+    static constexpr int NT = ((NP + 63) / 64) * 64;
+    static constexpr int AG = P <= 4 ? P1 : (P == 5 ? 3 : 4);
+    static constexpr int NAG = (P1 + AG - 1) / AG;
+};
+
+template <typename T, int P, int WHICH>
+__global__ void __launch_bounds__(OctAdjCfg<P>::NT)
+k_adj_octree(DevRules R, const int32_t* __restrict__ act2cut, const T* __restrict__ gm, const T* __restrict__ gk,
+             T* __restrict__ dk) {
+    using C = OctAdjCfg<P>;
+    constexpr int P1 = C::P1, NP = C::NP, P2 = C::P2, AG = C::AG, M = 2 * P + 1;
+    constexpr bool MASS = (WHICH & 1) != 0, STIFF = (WHICH & 2) != 0;
+    __shared__ double s_phi[3][2][P1][P1];
+    __shared__ T s_pp[3][2][P2][P1];
+    __shared__ T s_q[2][P1 * NP];                    // [v][g1][b2 a3 b3]
+    __shared__ T s_r[2][P2 * P2];                    // [v][g1 g2][a3 b3]
+    const int ce = blockIdx.x / (P1 * C::NAG);
+    const int a2 = (blockIdx.x / C::NAG) % P1;
+    const int ag0 = (blockIdx.x % C::NAG) * AG;
+    const int64_t eid = R.cut_elems[ce];
+    int e[3];
+    unlex3a(eid, R.nel, e);
+    const int t = threadIdx.x;
+    const bool own = t < NP;
+    const int b2 = t / P2, a3 = (t / P1) % P1, b3 = t % P1;
+    // cotangents of this thread's (a1 in group, b1) x (b2, a3, b3) entries
+    T gmv[AG][P1], gkv[AG][P1];
+#pragma unroll
+    for (int i = 0; i < AG; ++i) {
+        const int a1 = ag0 + i;
+#pragma unroll
+        for (int b1 = 0; b1 < P1; ++b1) { gmv[i][b1] = 0; gkv[i][b1] = 0; }
+        if (!own || a1 >= P1) continue;
+        const int64_t alex = ((int64_t)(e[0] + a1) * R.nfun[1] + (e[1] + a2)) * R.nfun[2] + (e[2] + a3);
+        const int ra = R.lex2act[alex];
+        const int cr = act2cut[ra];
+        const int32_t* pos = R.pos_map + (int64_t)cr * M * M * M;
+        const int64_t rb = R.row_ptr[ra];
+#pragma unroll
+        for (int b1 = 0; b1 < P1; ++b1) {
+            const int o = pos[((b1 - a1 + P) * M + (b2 - a2 + P)) * M + (b3 - a3 + P)];
+            if (o < 0) continue;
+            if (MASS) gmv[i][b1] = gm[rb + o];
+            if (STIFF) gkv[i][b1] = gk[rb + o];
+        }
+    }
+    const int64_t oct0 = R.n_grid + R.n_block;
+    const int cb = R.cell_begin[ce], cend = R.cell_begin[ce + 1];
+    for (int cell = cb; cell < cend; ++cell) {
+        if (t < 3 * P1) {
+            const int d = t / P1, g = t % P1;
+            const int scale = 1 << R.cell_depth[cell];
+            const double size = R.h[d] / scale;
+            const double x = R.cell_lo[(int64_t)cell * 3 + d] + (1.0 + R.gxi[g]) / 2.0 * size;
+            double kn[2 * WQ_PMAX + 2];
+            for (int k = 0; k < 2 * P + 2; ++k) {
+                int kk = e[d] + k - P;
+                kk = kk < 0 ? 0 : (kk > R.nel[d] ? R.nel[d] : kk);
+                kn[k] = R.lo[d] + (double)kk * R.h[d];
+            }
+            double N[WQ_PMAX + 1], dN[WQ_PMAX + 1];
+            basis_funs(kn, P, P, x, N, dN);
+            for (int k = 0; k <= P; ++k) { s_phi[d][0][k][g] = N[k]; s_phi[d][1][k][g] = dN[k]; }
+        }
+        __syncthreads();
+        for (int k = t; k < 3 * 2 * P2 * P1; k += C::NT) {
+            const int d = k / (2 * P2 * P1), v = (k / (P2 * P1)) % 2, ab = (k / P1) % P2, g = k % P1;
+            s_pp[d][v][ab][g] = (T)(s_phi[d][v][ab / P1][g] * s_phi[d][v][ab % P1][g]);
+        }
+        __syncthreads();
+        // C^T: Q0[g1][c2] = sum_{a1,b1} pp1[0] GM + pp1[1] GK; Q1 = sum pp1[0] GK
+        if (own) {
+#pragma unroll
+            for (int g1 = 0; g1 < P1; ++g1) {
+                T q0 = 0, q1 = 0;
+#pragma unroll
+                for (int i = 0; i < AG; ++i) {
+                    const int a1 = ag0 + i;
+                    if (a1 >= P1) break;
+#pragma unroll
+                    for (int b1 = 0; b1 < P1; ++b1) {
+                        const T w0 = s_pp[0][0][a1 * P1 + b1][g1];
+                        if (MASS) q0 += w0 * gmv[i][b1];
+                        if (STIFF) { q0 += s_pp[0][1][a1 * P1 + b1][g1] * gkv[i][b1]; q1 += w0 * gkv[i][b1]; }
+                    }
+                }
+                s_q[0][g1 * NP + t] = q0;
+                if (STIFF) s_q[1][g1 * NP + t] = q1;
+            }
+        }
+        __syncthreads();
+        // B^T: R0[g1 g2][a3 b3] = sum_b2 pp2[0][a2 b2][g2] Q0 + pp2[1] Q1; R1 = sum pp2[0] Q1
+        for (int k = t; k < P2 * P2; k += C::NT) {
+            const int g12 = k / P2, ab3 = k % P2;
+            const int g1 = g12 / P1, g2 = g12 % P1;
+            T r0 = 0, r1 = 0;
+#pragma unroll
+            for (int bb2 = 0; bb2 < P1; ++bb2) {
+                const T q0 = s_q[0][g1 * NP + bb2 * P2 + ab3];
+                const T w0 = s_pp[1][0][a2 * P1 + bb2][g2];
+                r0 += w0 * q0;
+                if (STIFF) {
+                    const T q1 = s_q[1][g1 * NP + bb2 * P2 + ab3];
+                    r0 += s_pp[1][1][a2 * P1 + bb2][g2] * q1;
+                    r1 += w0 * q1;
+                }
+            }
+            s_r[0][k] = r0;
+            if (STIFF) s_r[1][k] = r1;
+        }
+        __syncthreads();
+        // A^T: dk_g += w_g sum_{a3 b3} pp3[.][a3 b3][g3] R[.][g1 g2][a3 b3]
+        const int64_t pbase = (int64_t)cell * NP;
+        for (int k = t; k < NP; k += C::NT) {
+            const int g12 = k / P1, g3 = k % P1;
+            T v = 0;
+#pragma unroll
+            for (int ab3 = 0; ab3 < P2; ++ab3) {
+                v += s_pp[2][0][ab3][g3] * s_r[0][g12 * P2 + ab3];
+                if (STIFF) v += s_pp[2][1][ab3][g3] * s_r[1][g12 * P2 + ab3];
+            }
+            const T w = (T)R.oct_w[pbase + k];
+            if (w != (T)0) atomicAdd(&dk[oct0 + pbase + k], w * v);
+        }
+        __syncthreads();
+    }
+}
+
+// ----------------------------------------------------------------------------------------
+// host launchers
+// ----------------------------------------------------------------------------------------
+template <typename T, int P, int WHICH>
+static void launch_adj_p(const wq_rules* H, const T* gm, const T* gk, T* dk, hipStream_t s) {
+    const DevRules& R = H->R;
+    if (R.n_lblocks > 0) {
+        if constexpr (P <= 4) {
+            using C = AdjCfg<T, P, WHICH, 16>;
+            hipLaunchKernelGGL((k_adj_interior<T, P, WHICH, 16>), dim3((unsigned)R.n_lblocks), dim3(C::NT), 0, s, R, gm, gk, dk);
+        } else {
+            using C = AdjCfg<T, P, WHICH, 8>;
+            hipLaunchKernelGGL((k_adj_interior<T, P, WHICH, 8>), dim3((unsigned)R.n_lblocks), dim3(C::NT), 0, s, R, gm, gk, dk);
+        }
+    }
+    if (R.n_cut > 0) {
+        hipLaunchKernelGGL((k_adj_cut<T, P, WHICH>), dim3((unsigned)R.n_cut), dim3(256), 0, s, R, gm, gk, dk);
+        hipLaunchKernelGGL((k_adj_remainder<T, P, WHICH>), dim3((unsigned)R.n_cut), dim3(256), 0, s, R, H->box, gm, gk, dk);
+    }
+    if (R.n_cut_elems > 0) {
+        using C = OctAdjCfg<P>;
+        hipLaunchKernelGGL((k_adj_octree<T, P, WHICH>), dim3((unsigned)(R.n_cut_elems * C::P1 * C::NAG)), dim3(C::NT), 0, s, R,
+                           H->act2cut, gm, gk, dk);
+    }
+}
+
+template <typename T, int P>
+static void launch_adj_w(const wq_rules* H, uint32_t which, const T* gm, const T* gk, T* dk, hipStream_t s) {
+    if (which == 1) launch_adj_p<T, P, 1>(H, gm, gk, dk, s);
+    else if (which == 2) launch_adj_p<T, P, 2>(H, gm, gk, dk, s);
+    else launch_adj_p<T, P, 3>(H, gm, gk, dk, s);
+}
+
+template <typename T>
+void launch_adjoint(const wq_rules* H, uint32_t which, const T* gm, const T* gk, T* dk, hipStream_t s) {
+    const int64_t n = H->R.n_kappa;
+    if (n > 0) hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, dk, n, (T)0);
+    if (H->nnz == 0) return;
+    switch (H->R.p) {
+        case 1: launch_adj_w<T, 1>(H, which, gm, gk, dk, s); break;
+        case 2: launch_adj_w<T, 2>(H, which, gm, gk, dk, s); break;
+        case 3: launch_adj_w<T, 3>(H, which, gm, gk, dk, s); break;
+        case 4: launch_adj_w<T, 4>(H, which, gm, gk, dk, s); break;
+        case 5: launch_adj_w<T, 5>(H, which, gm, gk, dk, s); break;
+        case 6: launch_adj_w<T, 6>(H, which, gm, gk, dk, s); break;
+    }
+}
+
+#ifndef WQ_ONLY_F32
+template void launch_adjoint<double>(const wq_rules*, uint32_t, const double*, const double*, double*, hipStream_t);
+#endif
+#ifndef WQ_ONLY_F64
+template void launch_adjoint<float>(const wq_rules*, uint32_t, const float*, const float*, float*, hipStream_t);
+#endif

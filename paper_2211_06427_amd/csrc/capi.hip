@@ -1,0 +1,140 @@
+// C ABI of libwqfd: argument validation, dispatch by dtype, error reporting.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "rows.h"
+
+static thread_local char g_err[1024] = "";
+
+int wq_set_error(int code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+static int check_launch(const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return wq_set_error(WQ_EHIP, "%s: kernel launch failed: %s", what, hipGetErrorString(e));
+    return WQ_OK;
+}
+
+static int check_values(const wq_rules* r, int dtype, uint32_t which, const void* kappa, const void* a,
+                        const void* b, const char* what) {
+    if (!r) return wq_set_error(WQ_EINVAL, "%s: rules handle is NULL", what);
+    if (dtype != WQ_F64 && dtype != WQ_F32) return wq_set_error(WQ_EINVAL, "%s: unknown dtype %d", what, dtype);
+    if (which == 0 || (which & ~3u)) return wq_set_error(WQ_EINVAL, "%s: which must be a non-empty subset of MASS|STIFF", what);
+    if (!kappa) return wq_set_error(WQ_EINVAL, "%s: kappa is NULL", what);
+    if ((which & WQ_MASS) && !a) return wq_set_error(WQ_EINVAL, "%s: mass output requested but pointer is NULL", what);
+    if ((which & WQ_STIFF) && !b) return wq_set_error(WQ_EINVAL, "%s: stiffness output requested but pointer is NULL", what);
+    return WQ_OK;
+}
+
+extern "C" {
+
+const char* wq_last_error(void) { return g_err; }
+
+int wq_build_rules(const wq_mesh* mesh, const wq_levelset* ls, const wq_options* opts, void* stream, wq_rules** out) {
+    if (!mesh || !ls || !out) return wq_set_error(WQ_EINVAL, "wq_build_rules: mesh, levelset and out must be non-NULL");
+    *out = nullptr;
+    if (mesh->degree < 1) return wq_set_error(WQ_EINVAL, "wq_build_rules: degree must be >= 1 (got %d)", mesh->degree);
+    if (mesh->degree > WQ_PMAX)
+        return wq_set_error(WQ_EUNSUPPORTED, "wq_build_rules: degree %d exceeds the supported maximum %d", mesh->degree, WQ_PMAX);
+    int64_t nf = 1, ne = 1;
+    for (int d = 0; d < 3; ++d) {
+        if (mesh->nel[d] < 1) return wq_set_error(WQ_EINVAL, "wq_build_rules: nel[%d] must be >= 1", d);
+        if (!(std::isfinite(mesh->lo[d]) && std::isfinite(mesh->hi[d]) && mesh->lo[d] < mesh->hi[d]))
+            return wq_set_error(WQ_EINVAL, "wq_build_rules: need finite lo[%d] < hi[%d]", d, d);
+        ne *= mesh->nel[d];
+        nf *= mesh->nel[d] + mesh->degree;
+    }
+    if (nf >= ((int64_t)1 << 31) || ne >= ((int64_t)1 << 31))
+        return wq_set_error(WQ_EUNSUPPORTED, "wq_build_rules: mesh too large for 32-bit function indices");
+    if (ls->kind < 0 || ls->kind > 3) return wq_set_error(WQ_EINVAL, "wq_build_rules: unknown level-set kind %d", ls->kind);
+    if (ls->kind == 1 && !(ls->n[0] != 0 || ls->n[1] != 0 || ls->n[2] != 0))
+        return wq_set_error(WQ_EINVAL, "wq_build_rules: plane normal is zero");
+    if (ls->kind == 2 && !(ls->r0 > 0)) return wq_set_error(WQ_EINVAL, "wq_build_rules: ball radius must be > 0");
+    if (ls->kind == 3 && !(ls->r1 > 0 && ls->r0 > 0)) return wq_set_error(WQ_EINVAL, "wq_build_rules: torus radii must be > 0");
+    wq_options o = {3, 0};
+    if (opts) o = *opts;
+    if (o.octree_levels < 0 || o.octree_levels > 5)
+        return wq_set_error(WQ_EINVAL, "wq_build_rules: octree_levels must be in 0..5 (got %d)", o.octree_levels);
+    if (o.flags != 0) return wq_set_error(WQ_EINVAL, "wq_build_rules: flags must be 0");
+    return build_rules(mesh, ls, &o, (hipStream_t)stream, out);
+}
+
+int wq_rules_info_get(const wq_rules* r, wq_rules_info* out) {
+    if (!r || !out) return wq_set_error(WQ_EINVAL, "wq_rules_info_get: NULL argument");
+    memset(out, 0, sizeof(*out));
+    const DevRules& R = r->R;
+    out->n_active = r->n_active;
+    out->nnz = r->nnz;
+    out->n_rows_interior = r->n_interior_rows;
+    out->n_rows_cut = r->n_cut;
+    out->n_rows_split = r->n_split;
+    out->n_dwq_rules = r->n_dwq;
+    out->n_kappa = R.n_kappa;
+    out->n_grid = R.n_grid;
+    out->n_block = R.n_block;
+    out->n_octree = r->n_oct;
+    out->n_block_elems = r->n_block_elems;
+    out->n_cut_elems = R.n_cut_elems;
+    out->n_cells = R.n_cells;
+    out->n_line_blocks = R.n_lblocks;
+    for (int d = 0; d < 3; ++d) { out->grid_dims[d] = R.nx[d]; out->nfun[d] = R.nfun[d]; }
+    out->row_ptr = R.row_ptr;
+    out->col_idx = R.col_idx;
+    out->active_to_lex = R.act2lex;
+    out->kappa_xyz = r->kappa_xyz;
+    out->octree_w = R.oct_w;
+    out->block_elems = r->block_elems;
+    out->fun_class = R.fcls;
+    out->elem_class = R.ecls;
+    out->split = (const int32_t*)R.split;
+    out->cut_rows = R.cut_rows;
+    return WQ_OK;
+}
+
+int wq_assemble_rows(const wq_rules* r, int dtype, uint32_t which, const void* kappa, void* vm, void* vk, void* stream) {
+    int st = check_values(r, dtype, which, kappa, vm, vk, "wq_assemble_rows");
+    if (st) return st;
+    if (r->nnz == 0) return WQ_OK;
+    if (dtype == WQ_F64)
+        launch_rows<double>(r, which, (const double*)kappa, (double*)vm, (double*)vk, (hipStream_t)stream);
+    else
+        launch_rows<float>(r, which, (const float*)kappa, (float*)vm, (float*)vk, (hipStream_t)stream);
+    return check_launch("wq_assemble_rows");
+}
+
+int cut_assemble(const wq_rules* r, int dtype, uint32_t which, const void* kappa, void* vm, void* vk, void* stream) {
+    int st = check_values(r, dtype, which, kappa, vm, vk, "cut_assemble");
+    if (st) return st;
+    if (r->nnz == 0) return WQ_OK;
+    if (dtype == WQ_F64)
+        launch_cut<double>(r, which, (const double*)kappa, (double*)vm, (double*)vk, (hipStream_t)stream);
+    else
+        launch_cut<float>(r, which, (const float*)kappa, (float*)vm, (float*)vk, (hipStream_t)stream);
+    return check_launch("cut_assemble");
+}
+
+int wq_assemble_adjoint(const wq_rules* r, int dtype, uint32_t which, const void* gm, const void* gk, void* dk,
+                        void* stream) {
+    int st = check_values(r, dtype, which, dk, gm, gk, "wq_assemble_adjoint");
+    if (st) return st;
+    if (dtype == WQ_F64)
+        launch_adjoint<double>(r, which, (const double*)gm, (const double*)gk, (double*)dk, (hipStream_t)stream);
+    else
+        launch_adjoint<float>(r, which, (const float*)gm, (const float*)gk, (float*)dk, (hipStream_t)stream);
+    return check_launch("wq_assemble_adjoint");
+}
+
+void wq_rules_free(wq_rules* r) {
+    if (!r) return;
+    (void)hipDeviceSynchronize();
+    delete r;
+}
+
+}  // extern "C"

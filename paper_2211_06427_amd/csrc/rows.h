@@ -1,0 +1,11 @@
+// Launchers of the assembly kernels (each defined in its own translation unit).
+#pragma once
+
+#include "rules.h"
+
+template <typename T>
+void launch_rows(const wq_rules* H, uint32_t which, const T* kappa, T* vm, T* vk, hipStream_t s);
+template <typename T>
+void launch_cut(const wq_rules* H, uint32_t which, const T* kappa, T* vm, T* vk, hipStream_t s);
+template <typename T>
+void launch_adjoint(const wq_rules* H, uint32_t which, const T* gm, const T* gk, T* dk, hipStream_t s);

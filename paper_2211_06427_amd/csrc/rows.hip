@@ -1,0 +1,327 @@
+// Row assembly by sum factorization over weighted-quadrature rules (Section 1: sum
+// factorization, weighted quadrature and the row loop; Section 2.2 for DWQ rows).
+//
+// Interior rows: one workgroup per line block of up to RB consecutive interior rows along
+// direction 1 (fixed i2, i3).  Stages 1-2 contract directions 3 and 2 once for the whole
+// block into an LDS slab T2[q1][j2 j3]; stage 3 contracts direction 1 per row, one lane per
+// (j2, j3) column, with the row's direction-1 weights read as wave-uniform scalars, and
+// stores each row's (2p+1)^3 values with coalesced writes.
+//
+// Cut rows: one workgroup per cut row.  Rows with a DWQ box use the one-sided rule in the
+// split direction and the standard rules in the others (kappa gathered through the slot
+// map); rows without a box are zeroed (their support is handled by cut_assemble).
+#include "rows.h"
+
+template <typename T> __device__ inline const T* wt_table(const DevRules& R, int d);
+template <> __device__ inline const double* wt_table<double>(const DevRules& R, int d) { return R.Wt64[d]; }
+template <> __device__ inline const float* wt_table<float>(const DevRules& R, int d) { return R.Wt32[d]; }
+template <typename T> __device__ inline const T* dwq_table(const DevRules& R);
+template <> __device__ inline const double* dwq_table<double>(const DevRules& R) { return R.dwq_Wt64; }
+template <> __device__ inline const float* dwq_table<float>(const DevRules& R) { return R.dwq_Wt32; }
+
+__device__ inline int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// ----------------------------------------------------------------------------------------
+// interior rows
+// ----------------------------------------------------------------------------------------
+template <typename T, int P, int WHICH, int RB>
+struct RowCfg {
+    static constexpr int M = 2 * P + 1, NW = 4 * P, MM = M * M;
+    static constexpr int GT = ((MM + 63) / 64) * 64;       // threads per stage-3 row group
+    static constexpr int NT = GT >= 256 ? GT : 256;        // threads per block
+    static constexpr int NG = NT / GT;                     // row groups
+    static constexpr int NQ1 = 2 * RB + 4 * P;             // q1 slab bound
+    static constexpr bool STIFF = (WHICH & 2) != 0;
+    static constexpr bool MASS = (WHICH & 1) != 0;
+};
+
+template <typename T, int P, int WHICH, int RB>
+__global__ void __launch_bounds__((RowCfg<T, P, WHICH, RB>::NT))
+k_rows_interior(DevRules R, const T* __restrict__ kappa, T* __restrict__ vm, T* __restrict__ vk) {
+    using C = RowCfg<T, P, WHICH, RB>;
+    constexpr int M = C::M, NW = C::NW, MM = C::MM;
+    __shared__ T s_t00[C::NQ1 * MM];
+    __shared__ T s_ts[C::STIFF ? C::NQ1 * MM : 1];
+    __shared__ T s_w2[2 * M * NW], s_w3[2 * M * NW];
+
+    const int4 blk = R.lblocks[blockIdx.x];
+    const int i1s = blk.x, i2 = blk.y, i3 = blk.z, nrows = blk.w;
+    const T* W1 = wt_table<T>(R, 0);
+    const T* W2 = wt_table<T>(R, 1) + (int64_t)i2 * 2 * M * NW;
+    const T* W3 = wt_table<T>(R, 2) + (int64_t)i3 * 2 * M * NW;
+    for (int k = threadIdx.x; k < 2 * M * NW; k += C::NT) { s_w2[k] = W2[k]; s_w3[k] = W3[k]; }
+    const int qbase = R.xs[0][i1s];
+    const int i1e = i1s + nrows - 1;
+    const int nq1 = R.xs[0][i1e] + R.nwin[0][i1e] - qbase;
+    const int xs2 = R.xs[1][i2], nw2 = R.nwin[1][i2];
+    const int xs3 = R.xs[2][i3], nw3 = R.nwin[2][i3];
+    const int nx2 = R.nx[1], nx3 = R.nx[2];
+    __syncthreads();
+
+    // stages 1-2: one item per (q1, j3)
+    for (int it = threadIdx.x; it < nq1 * M; it += C::NT) {
+        const int q1 = it / M, j3 = it % M;
+        const T* kap = kappa + ((int64_t)(qbase + q1) * nx2 + xs2) * nx3 + xs3;
+        T t0[NW], t1[NW];
+#pragma unroll
+        for (int q2 = 0; q2 < NW; ++q2) {
+            T a0 = 0, a1 = 0;
+            if (q2 < nw2) {
+#pragma unroll
+                for (int q3 = 0; q3 < NW; ++q3) {
+                    if (q3 < nw3) {
+                        T kv = kap[(int64_t)q2 * nx3 + q3];
+                        a0 += s_w3[j3 * NW + q3] * kv;
+                        if (C::STIFF) a1 += s_w3[(M + j3) * NW + q3] * kv;
+                    }
+                }
+            }
+            t0[q2] = a0; t1[q2] = a1;
+        }
+#pragma unroll
+        for (int j2 = 0; j2 < M; ++j2) {
+            T m0 = 0, ms = 0;
+#pragma unroll
+            for (int q2 = 0; q2 < NW; ++q2) {
+                if (q2 < nw2) {
+                    m0 += s_w2[j2 * NW + q2] * t0[q2];
+                    if (C::STIFF) ms += s_w2[(M + j2) * NW + q2] * t0[q2] + s_w2[j2 * NW + q2] * t1[q2];
+                }
+            }
+            s_t00[q1 * MM + j2 * M + j3] = m0;
+            if (C::STIFF) s_ts[q1 * MM + j2 * M + j3] = ms;
+        }
+    }
+    __syncthreads();
+
+    // stage 3: row groups of GT lanes, one lane per (j2, j3)
+    const int grp = uniform(threadIdx.x / C::GT);
+    const int c = threadIdx.x % C::GT;
+    const int jj2 = c / M, jj3 = c % M;
+    const int p = P;
+    const int I2 = i2, I3 = i3;
+    const int lo2 = I2 - p < 0 ? p - I2 : 0, hi2 = I2 + p > R.nfun[1] - 1 ? R.nfun[1] - 1 - I2 + p : 2 * p;
+    const int lo3 = I3 - p < 0 ? p - I3 : 0, hi3 = I3 + p > R.nfun[2] - 1 ? R.nfun[2] - 1 - I3 + p : 2 * p;
+    const int m2 = hi2 - lo2 + 1, m3 = hi3 - lo3 + 1;
+    const bool live = c < MM && jj2 >= lo2 && jj2 <= hi2 && jj3 >= lo3 && jj3 <= hi3;
+    const int64_t nl = (int64_t)R.nfun[1] * R.nfun[2];
+    for (int r = grp; r < nrows; r += C::NG) {
+        const int i1 = uniform(i1s + r);
+        const int ra = uniform(R.lex2act[(int64_t)i1 * nl + (int64_t)I2 * R.nfun[2] + I3]);
+        const int64_t base = R.row_ptr[ra];
+        const int off = uniform(R.xs[0][i1] - qbase);
+        const int nw1 = uniform(R.nwin[0][i1]);
+        const int lo1 = i1 - p < 0 ? p - i1 : 0, hi1 = i1 + p > R.nfun[0] - 1 ? R.nfun[0] - 1 - i1 + p : 2 * p;
+        T t00[NW], ts[NW];
+#pragma unroll
+        for (int q = 0; q < NW; ++q) {
+            t00[q] = 0; ts[q] = 0;
+            if (live && q < nw1) {
+                t00[q] = s_t00[(off + q) * MM + c];
+                if (C::STIFF) ts[q] = s_ts[(off + q) * MM + c];
+            }
+        }
+        const T* w10 = W1 + (int64_t)i1 * 2 * M * NW;
+        const T* w11 = w10 + M * NW;
+        const int8_t* qlo = R.qlo[0] + i1 * M;
+        const int8_t* qhi = R.qhi[0] + i1 * M;
+#pragma unroll
+        for (int jj1 = 0; jj1 < M; ++jj1) {
+            if (jj1 < lo1 || jj1 > hi1) continue;
+            const int qa = qlo[jj1], qb = qhi[jj1];
+            T am = 0, ak = 0;
+#pragma unroll
+            for (int q = 0; q < NW; ++q) {
+                if (q >= qa && q < qb) {
+                    const T a = w10[jj1 * NW + q];
+                    if (C::MASS) am += a * t00[q];
+                    if (C::STIFF) ak += w11[jj1 * NW + q] * t00[q] + a * ts[q];
+                }
+            }
+            if (live) {
+                const int64_t o = base + ((int64_t)(jj1 - lo1) * m2 + (jj2 - lo2)) * m3 + (jj3 - lo3);
+                if (C::MASS) vm[o] = am;
+                if (C::STIFF) vk[o] = ak;
+            }
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------------------
+// cut rows (general kernel): contraction order A (split direction first), B, C
+// ----------------------------------------------------------------------------------------
+template <typename T, int P, int WHICH>
+struct CutCfg {
+    static constexpr int M = 2 * P + 1, NW = 4 * P, NDQ = P * (P + 1), MM = M * M;
+    static constexpr int NT = 256;
+    static constexpr bool STIFF = (WHICH & 2) != 0;
+    static constexpr bool MASS = (WHICH & 1) != 0;
+};
+
+template <typename T, int P, int WHICH>
+__global__ void __launch_bounds__(256)
+k_rows_cut(DevRules R, const T* __restrict__ kappa, T* __restrict__ vm, T* __restrict__ vk) {
+    using C = CutCfg<T, P, WHICH>;
+    constexpr int M = C::M, NW = C::NW, NDQ = C::NDQ, MM = C::MM;
+    constexpr int NA = NDQ > NW ? NDQ : NW;        // the split direction may hold a DWQ rule
+    __shared__ T s_w[3][2 * M * NA];
+    __shared__ int s_y[3][NA];
+    __shared__ int s_n[3];
+    constexpr int QCH = (32768 / (NW * M * 2 * (int)sizeof(T))) < NW ? (32768 / (NW * M * 2 * (int)sizeof(T))) : NW;
+    __shared__ T s_t1[2 * QCH * NW * M];            // [v][qC in chunk][qB][jA]
+    __shared__ T s_t2[2 * NW * MM];                 // [v][qC][jB jA]
+
+    const int64_t cr = blockIdx.x;
+    const int ra = R.cut_rows[cr];
+    const int4 sp = R.split[cr];
+    const int64_t rb = R.row_ptr[ra], re = R.row_ptr[ra + 1];
+    if (sp.x < 0) {
+        for (int64_t k = rb + threadIdx.x; k < re; k += C::NT) {
+            if (C::MASS) vm[k] = 0;
+            if (C::STIFF) vk[k] = 0;
+        }
+        return;
+    }
+    const int lex = R.act2lex[ra];
+    int I[3];
+    I[2] = lex % R.nfun[2]; I[1] = (lex / R.nfun[2]) % R.nfun[1]; I[0] = lex / (R.nfun[1] * R.nfun[2]);
+    // contraction order: A = split direction, then the other two ascending
+    const int dA = sp.x, dB = dA == 0 ? 1 : 0, dC = dA == 2 ? 1 : 2;
+    const int dirs[3] = {dA, dB, dC};
+    // rules into LDS: s_w[slot][a][jj][q] with q stride NA
+    for (int sl = 0; sl < 3; ++sl) {
+        const int d = dirs[sl];
+        if (sl == 0) {
+            const int r = sp.w;
+            const int np = R.dwq_np[r];
+            const T* W = dwq_table<T>(R) + (int64_t)r * 2 * M * NDQ;
+            for (int k = threadIdx.x; k < 2 * M * NA; k += C::NT) {
+                const int q = k % NA, row = k / NA;
+                s_w[sl][k] = q < NDQ ? W[row * NDQ + q] : (T)0;
+            }
+            for (int q = threadIdx.x; q < NA; q += C::NT) s_y[sl][q] = q < np ? R.dwq_y[(int64_t)r * NDQ + q] : 0;
+            if (threadIdx.x == 0) s_n[sl] = np;
+        } else {
+            const int i = I[d];
+            const int xs = R.xs[d][i], nw = R.nwin[d][i];
+            const T* W = wt_table<T>(R, d) + (int64_t)i * 2 * M * NW;
+            for (int k = threadIdx.x; k < 2 * M * NA; k += C::NT) {
+                const int q = k % NA, row = k / NA;
+                s_w[sl][k] = q < NW ? W[row * NW + q] : (T)0;
+            }
+            for (int q = threadIdx.x; q < NA; q += C::NT) s_y[sl][q] = q < nw ? R.x2y[d][xs + q] : 0;
+            if (threadIdx.x == 0) s_n[sl] = nw;
+        }
+    }
+    __syncthreads();
+    const int nA = s_n[0], nB = s_n[1], nCc = s_n[2];
+    for (int qc0 = 0; qc0 < nCc; qc0 += QCH) {
+        const int nch = nCc - qc0 < QCH ? nCc - qc0 : QCH;
+        // stage A: T1[v][qC][qB][jA] = sum_qA W_A^v[jA][qA] kappa(qA, qB, qC)
+        for (int it = threadIdx.x; it < nch * nB; it += C::NT) {
+            const int qCl = it / nB, qB = it % nB;
+            int y[3];
+            y[dB] = s_y[1][qB]; y[dC] = s_y[2][qc0 + qCl];
+            T a0[M], a1[M];
+#pragma unroll
+            for (int j = 0; j < M; ++j) { a0[j] = 0; a1[j] = 0; }
+            for (int qA = 0; qA < nA; ++qA) {
+                y[dA] = s_y[0][qA];
+                const T kv = kappa[slot_of(R, y[0], y[1], y[2])];
+#pragma unroll
+                for (int j = 0; j < M; ++j) {
+                    a0[j] += s_w[0][j * NA + qA] * kv;
+                    if (C::STIFF) a1[j] += s_w[0][(M + j) * NA + qA] * kv;
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                s_t1[((0 * QCH + qCl) * NW + qB) * M + j] = a0[j];
+                if (C::STIFF) s_t1[((1 * QCH + qCl) * NW + qB) * M + j] = a1[j];
+            }
+        }
+        __syncthreads();
+        // stage B: T2_00[qC][jB jA] = sum_qB W_B^0 T1_0; T2_s = sum W_B^1 T1_0 + W_B^0 T1_1
+        for (int it = threadIdx.x; it < nch * M; it += C::NT) {
+            const int qCl = it / M, jA = it % M;
+            const int qC = qc0 + qCl;
+            for (int jB = 0; jB < M; ++jB) {
+                T m0 = 0, ms = 0;
+                for (int qB = 0; qB < nB; ++qB) {
+                    const T t0 = s_t1[((0 * QCH + qCl) * NW + qB) * M + jA];
+                    m0 += s_w[1][jB * NA + qB] * t0;
+                    if (C::STIFF) ms += s_w[1][(M + jB) * NA + qB] * t0 + s_w[1][jB * NA + qB] * s_t1[((1 * QCH + qCl) * NW + qB) * M + jA];
+                }
+                s_t2[(0 * NW + qC) * MM + jB * M + jA] = m0;
+                if (C::STIFF) s_t2[(1 * NW + qC) * MM + jB * M + jA] = ms;
+            }
+        }
+        __syncthreads();
+    }
+    // stage C: one thread per (jB, jA); out[jC][jB][jA]
+    const int32_t* pos = R.pos_map + cr * (int64_t)M * M * M;
+    for (int cc = threadIdx.x; cc < MM; cc += C::NT) {
+        const int jB = cc / M, jA = cc % M;
+        for (int jC = 0; jC < M; ++jC) {
+            T am = 0, ak = 0;
+            for (int qC = 0; qC < nCc; ++qC) {
+                const T t0 = s_t2[(0 * NW + qC) * MM + cc];
+                const T a = s_w[2][jC * NA + qC];
+                if (C::MASS) am += a * t0;
+                if (C::STIFF) ak += s_w[2][(M + jC) * NA + qC] * t0 + a * s_t2[(1 * NW + qC) * MM + cc];
+            }
+            int jj[3];
+            jj[dA] = jA; jj[dB] = jB; jj[dC] = jC;
+            const int k = pos[(jj[0] * M + jj[1]) * M + jj[2]];
+            if (k >= 0) {
+                if (C::MASS) vm[rb + k] = am;
+                if (C::STIFF) vk[rb + k] = ak;
+            }
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------------------
+// host launchers
+// ----------------------------------------------------------------------------------------
+template <typename T, int P, int WHICH>
+static void launch_rows_p(const wq_rules* H, const T* kappa, T* vm, T* vk, hipStream_t s) {
+    const DevRules& R = H->R;
+    if (R.n_lblocks > 0) {
+        if constexpr (P <= 4) {
+            using C = RowCfg<T, P, WHICH, 16>;
+            hipLaunchKernelGGL((k_rows_interior<T, P, WHICH, 16>), dim3((unsigned)R.n_lblocks), dim3(C::NT), 0, s, R, kappa, vm, vk);
+        } else {
+            using C = RowCfg<T, P, WHICH, 8>;
+            hipLaunchKernelGGL((k_rows_interior<T, P, WHICH, 8>), dim3((unsigned)R.n_lblocks), dim3(C::NT), 0, s, R, kappa, vm, vk);
+        }
+    }
+    if (R.n_cut > 0)
+        hipLaunchKernelGGL((k_rows_cut<T, P, WHICH>), dim3((unsigned)R.n_cut), dim3(256), 0, s, R, kappa, vm, vk);
+}
+
+template <typename T, int P>
+static void launch_rows_w(const wq_rules* H, uint32_t which, const T* kappa, T* vm, T* vk, hipStream_t s) {
+    if (which == 1) launch_rows_p<T, P, 1>(H, kappa, vm, vk, s);
+    else if (which == 2) launch_rows_p<T, P, 2>(H, kappa, vm, vk, s);
+    else launch_rows_p<T, P, 3>(H, kappa, vm, vk, s);
+}
+
+template <typename T>
+void launch_rows(const wq_rules* H, uint32_t which, const T* kappa, T* vm, T* vk, hipStream_t s) {
+    switch (H->R.p) {
+        case 1: launch_rows_w<T, 1>(H, which, kappa, vm, vk, s); break;
+        case 2: launch_rows_w<T, 2>(H, which, kappa, vm, vk, s); break;
+        case 3: launch_rows_w<T, 3>(H, which, kappa, vm, vk, s); break;
+        case 4: launch_rows_w<T, 4>(H, which, kappa, vm, vk, s); break;
+        case 5: launch_rows_w<T, 5>(H, which, kappa, vm, vk, s); break;
+        case 6: launch_rows_w<T, 6>(H, which, kappa, vm, vk, s); break;
+    }
+}
+
+#ifndef WQ_ONLY_F32
+template void launch_rows<double>(const wq_rules*, uint32_t, const double*, double*, double*, hipStream_t);
+#endif
+#ifndef WQ_ONLY_F64
+template void launch_rows<float>(const wq_rules*, uint32_t, const float*, float*, float*, hipStream_t);
+#endif
