@@ -1,0 +1,207 @@
+#!/usr/bin/env python3
+"""Throughput of weighted-quadrature row assembly on one MI355X.
+
+A step is one pass of the whole assembly for one coefficient field: wq_assemble_rows
+(interior rows by line-blocked sum factorization, cut rows with DWQ boxes) followed by
+cut_assemble (element Gauss remainders and octree cut cells), forming the mass and the
+stiffness matrix on the fixed CSR pattern.  The rules handle (Gauss rule, WQ/DWQ rules,
+classification, pattern, octree) is built once before the timed region, and kappa is
+resident in device memory.
+
+Prints one JSON line.  Default workload: 48^3 elements, p=4, domain {x+y+z < 1.6},
+kappa = exp of a seeded Gaussian random field.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "assembled nnz/s at p=4, 48³ cut cube: FP64 vs FP32 path at ≤2e-6 rel err"
+PEAK = {"hbm_GBps": 8000.0, "fp64_TFLOPs": 78.6, "fp32_TFLOPs": 157.3}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="plane48_p4")
+    ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--skip-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=48, help="rows in the oracle's timed sample")
+    return ap.parse_args()
+
+
+def timed(fn, n, torch):
+    """Mean duration (ms) of fn over n calls, HIP events on the current stream."""
+    s = torch.cuda.Event(enable_timing=True)
+    e = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s.record()
+    for _ in range(n):
+        fn()
+    e.record()
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) / n
+
+
+def row_scaled_err(a, b, row_ptr, torch):
+    """max over rows of max|a-b| / max|b| (b is the reference)."""
+    rows = torch.repeat_interleave(torch.arange(len(row_ptr) - 1, device=a.device), torch.diff(row_ptr))
+    d = torch.zeros(len(row_ptr) - 1, dtype=torch.float64, device=a.device)
+    m = torch.zeros_like(d)
+    d.scatter_reduce_(0, rows, (a.double() - b.double()).abs(), "amax")
+    m.scatter_reduce_(0, rows, b.double().abs(), "amax")
+    ok = m > 0
+    return float((d[ok] / m[ok]).max()) if bool(ok.any()) else 0.0
+
+
+def cpu_baseline(wl, nrows):
+    """The oracle (unchanged) on a seeded sample of rows; nnz/s over both matrices."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import workloads as W
+    from oracle.assemble import Problem, kappa_numpy
+    P = Problem(wl)
+    rows = W.sample_indices(7, P.dom.n_active, nrows)
+    rp = P.row_ptr()
+    nnz = int(sum(rp[r + 1] - rp[r] for r in rows))
+    kap = kappa_numpy(wl)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        P.assemble_rows(rows, kap)
+        dt = time.perf_counter() - t0
+    return {"value": 2 * nnz / dt, "unit": "nnz/s", "cores": 1, "kind": "oracle",
+            "sample": f"{nrows} seeded rows of {P.dom.n_active} (all row classes), {nnz} entries per matrix, "
+                      f"mass+stiffness, {dt:.1f} s single-threaded; rule setup excluded"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the row assembly is not "
+              f"distributed in this build.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import workloads as W
+    from paper_2211_06427_amd import Rules
+    wl = W.workload(args.workload)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+
+    t0 = time.perf_counter()
+    R = Rules.from_workload(wl)
+    torch.cuda.synchronize()
+    build_cold_ms = (time.perf_counter() - t0) * 1e3
+    t0 = time.perf_counter()
+    R2 = Rules.from_workload(wl)
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - t0) * 1e3
+    del R2
+
+    k64 = W.kappa_at(wl, R.kappa_xyz())
+    kap = {"f64": k64, "f32": k64.float()}
+    dt = {"f64": torch.float64, "f32": torch.float32}
+    main_dt = args.dtype
+    vals = {k: (torch.empty(R.nnz, dtype=dt[k], device=dev), torch.empty(R.nnz, dtype=dt[k], device=dev))
+            for k in ("f64", "f32")}
+
+    def step(k):
+        vm, vk = vals[k]
+        R.assemble_rows(kap[k], vm, vk)
+        R.cut_assemble(kap[k], vm, vk)
+
+    # --- the timed region: K steps of the main dtype ---------------------------------
+    # HIP events on the launch stream bracket the two passes of every step, so the rows
+    # pass and the cut pass durations are measured inside the timed region.
+    for _ in range(args.warmup):
+        step(main_dt)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    vm_main, vk_main = vals[main_dt]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record()
+        R.assemble_rows(kap[main_dt], vm_main, vk_main)
+        ev[i][1].record()
+        R.cut_assemble(kap[main_dt], vm_main, vk_main)
+        ev[i][2].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = wall * 1e3 / args.steps
+    n_mat = 2
+    value = n_mat * R.nnz / (wall / args.steps)
+    timed_rows_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / args.steps
+    timed_cut_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / args.steps
+
+    # --- breakdown (outside the timed region) ----------------------------------------
+    nrep = max(3, min(args.steps, 10))
+    parts = {}
+    for k in ("f64", "f32"):
+        vm, vk = vals[k]
+        step(k)
+        parts[k] = {
+            "step_ms": timed(lambda: step(k), nrep, torch),
+            "rows_ms": timed(lambda: R.assemble_rows(kap[k], vm, vk), nrep, torch),
+            "cut_ms": timed(lambda: R.cut_assemble(kap[k], vm, vk), nrep, torch),
+        }
+        g = torch.ones(R.nnz, dtype=dt[k], device=dev)
+        parts[k]["adjoint_ms"] = timed(lambda: R.adjoint(g, g), nrep, torch)
+    step("f64")
+    step("f32")
+    torch.cuda.synchronize()
+    rp = R.row_ptr()
+    err32 = {"mass": row_scaled_err(vals["f32"][0], vals["f64"][0], rp, torch),
+             "stiff": row_scaled_err(vals["f32"][1], vals["f64"][1], rp, torch)}
+
+    # --- roofline of the dominant pass of the main dtype (durations from the timed region)
+    esz = 8 if main_dt == "f64" else 4
+    rows_bytes = R.nnz * n_mat * esz + R.n_grid * esz          # values written once + kappa grid read once
+    rows_roof = {"bound": "hbm", "kernel": "wq_assemble_rows", "achieved": rows_bytes / (timed_rows_ms * 1e-3) / 1e9,
+                 "peak": PEAK["hbm_GBps"], "unit": "GB/s", "traffic": None}
+    rows_roof["frac"] = rows_roof["achieved"] / PEAK["hbm_GBps"]
+    P1 = wl.degree + 1
+    # sum-factorized octree local matrices (mass + stiffness) per leaf, FMA = 2 flop:
+    # stage A 2 P1^5, stage B 3 P1^5, stage C 3 P1^6
+    cut_flop = 2 * R.n_cells * (5 * P1 ** 5 + 3 * P1 ** 6)
+    peak = PEAK["fp64_TFLOPs"] if main_dt == "f64" else PEAK["fp32_TFLOPs"]
+    cut_roof = {"bound": "alu", "kernel": "cut_assemble", "achieved": cut_flop / (timed_cut_ms * 1e-3) / 1e12,
+                "peak": peak, "unit": "TFLOP/s", "traffic": None}
+    cut_roof["frac"] = cut_roof["achieved"] / peak
+    roof, other = (rows_roof, cut_roof) if timed_rows_ms >= timed_cut_ms else (cut_roof, rows_roof)
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "nnz/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": main_dt, "data": "synthetic",
+        "config": {"workload": wl.name, "nel": list(wl.nel), "degree": wl.degree, "domain": "x+y+z<1.6",
+                   "kappa": "exp(seeded Gaussian random field, 8 modes/axis, sigma 0.5)", "matrices": "mass+stiffness",
+                   "octree_levels": wl.octree_levels, "n_active": R.n_active, "nnz_per_matrix": R.nnz,
+                   "parallelism": "single GPU"},
+        "roofline": roof,
+        "roofline_other_pass": other,
+        "timed_pass_ms": {"wq_assemble_rows": timed_rows_ms, "cut_assemble": timed_cut_ms},
+        "breakdown_ms": parts,
+        "fp32_over_fp64": parts["f64"]["step_ms"] / parts["f32"]["step_ms"],
+        "fp32_rows_over_fp64_rows": parts["f64"]["rows_ms"] / parts["f32"]["rows_ms"],
+        "adjoint_over_forward": {k: parts[k]["adjoint_ms"] / parts[k]["step_ms"] for k in parts},
+        "fp32_rel_err_vs_fp64": err32,
+        "build_rules_ms": {"cold": build_cold_ms, "warm": build_ms},
+    }
+    if not args.skip_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_rows)
+        out["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -42,14 +42,18 @@ k_rows_interior(DevRules R, const T* __restrict__ kappa, T* __restrict__ vm, T* 
     constexpr int M = C::M, NW = C::NW, MM = C::MM;
     __shared__ T s_t00[C::NQ1 * MM];
     __shared__ T s_ts[C::STIFF ? C::NQ1 * MM : 1];
-    __shared__ T s_w2[2 * M * NW], s_w3[2 * M * NW];
+    constexpr int NWP = NW + 1;                 // padded row stride of the staged weights
+    __shared__ T s_w2[2 * M * NWP], s_w3[2 * M * NWP];
 
     const int4 blk = R.lblocks[blockIdx.x];
     const int i1s = blk.x, i2 = blk.y, i3 = blk.z, nrows = blk.w;
     const T* W1 = wt_table<T>(R, 0);
     const T* W2 = wt_table<T>(R, 1) + (int64_t)i2 * 2 * M * NW;
     const T* W3 = wt_table<T>(R, 2) + (int64_t)i3 * 2 * M * NW;
-    for (int k = threadIdx.x; k < 2 * M * NW; k += C::NT) { s_w2[k] = W2[k]; s_w3[k] = W3[k]; }
+    for (int k = threadIdx.x; k < 2 * M * NW; k += C::NT) {
+        s_w2[(k / NW) * NWP + k % NW] = W2[k];
+        s_w3[(k / NW) * NWP + k % NW] = W3[k];
+    }
     const int qbase = R.xs[0][i1s];
     const int i1e = i1s + nrows - 1;
     const int nq1 = R.xs[0][i1e] + R.nwin[0][i1e] - qbase;
@@ -58,38 +62,34 @@ k_rows_interior(DevRules R, const T* __restrict__ kappa, T* __restrict__ vm, T* 
     const int nx2 = R.nx[1], nx3 = R.nx[2];
     __syncthreads();
 
-    // stages 1-2: one item per (q1, j3)
+    // stages 1-2: one item per (q1, j3).  For each q2 the direction-3 sums T1_a(q1,q2,j3)
+    // are formed and immediately folded into the direction-2 sums over all j2, so only
+    // the 2M stage-2 accumulators stay live.
     for (int it = threadIdx.x; it < nq1 * M; it += C::NT) {
         const int q1 = it / M, j3 = it % M;
         const T* kap = kappa + ((int64_t)(qbase + q1) * nx2 + xs2) * nx3 + xs3;
-        T t0[NW], t1[NW];
+        T m0[M], ms[M];
 #pragma unroll
-        for (int q2 = 0; q2 < NW; ++q2) {
+        for (int j2 = 0; j2 < M; ++j2) { m0[j2] = 0; ms[j2] = 0; }
+        for (int q2 = 0; q2 < nw2; ++q2) {
+            const T* kq = kap + (int64_t)q2 * nx3;
             T a0 = 0, a1 = 0;
-            if (q2 < nw2) {
-#pragma unroll
-                for (int q3 = 0; q3 < NW; ++q3) {
-                    if (q3 < nw3) {
-                        T kv = kap[(int64_t)q2 * nx3 + q3];
-                        a0 += s_w3[j3 * NW + q3] * kv;
-                        if (C::STIFF) a1 += s_w3[(M + j3) * NW + q3] * kv;
-                    }
-                }
+            for (int q3 = 0; q3 < nw3; ++q3) {
+                const T kv = kq[q3];
+                a0 += s_w3[j3 * NWP + q3] * kv;
+                if (C::STIFF) a1 += s_w3[(M + j3) * NWP + q3] * kv;
             }
-            t0[q2] = a0; t1[q2] = a1;
+#pragma unroll
+            for (int j2 = 0; j2 < M; ++j2) {
+                const T w0 = s_w2[j2 * NWP + q2];
+                m0[j2] += w0 * a0;
+                if (C::STIFF) ms[j2] += s_w2[(M + j2) * NWP + q2] * a0 + w0 * a1;
+            }
         }
 #pragma unroll
         for (int j2 = 0; j2 < M; ++j2) {
-            T m0 = 0, ms = 0;
-#pragma unroll
-            for (int q2 = 0; q2 < NW; ++q2) {
-                if (q2 < nw2) {
-                    m0 += s_w2[j2 * NW + q2] * t0[q2];
-                    if (C::STIFF) ms += s_w2[(M + j2) * NW + q2] * t0[q2] + s_w2[j2 * NW + q2] * t1[q2];
-                }
-            }
-            s_t00[q1 * MM + j2 * M + j3] = m0;
-            if (C::STIFF) s_ts[q1 * MM + j2 * M + j3] = ms;
+            s_t00[q1 * MM + j2 * M + j3] = m0[j2];
+            if (C::STIFF) s_ts[q1 * MM + j2 * M + j3] = ms[j2];
         }
     }
     __syncthreads();
@@ -123,25 +123,45 @@ k_rows_interior(DevRules R, const T* __restrict__ kappa, T* __restrict__ vm, T* 
         }
         const T* w10 = W1 + (int64_t)i1 * 2 * M * NW;
         const T* w11 = w10 + M * NW;
-        const int8_t* qlo = R.qlo[0] + i1 * M;
-        const int8_t* qhi = R.qhi[0] + i1 * M;
+        // A row whose window has two points in each of its p+1 elements (no boundary
+        // element) has W1[jj1][q] != 0 only for q in [2 max(0, jj1-p), 2 (min(p, jj1)+1)):
+        // that range is a compile-time constant.  Other rows loop over the padded window.
+        const bool regular = nw1 == 2 * P + 2 && lo1 == 0 && hi1 == 2 * P;
+        if (regular) {
 #pragma unroll
-        for (int jj1 = 0; jj1 < M; ++jj1) {
-            if (jj1 < lo1 || jj1 > hi1) continue;
-            const int qa = qlo[jj1], qb = qhi[jj1];
-            T am = 0, ak = 0;
+            for (int jj1 = 0; jj1 < M; ++jj1) {
+                const int qa = 2 * (jj1 - P > 0 ? jj1 - P : 0);
+                const int qb = 2 * ((jj1 < P ? jj1 : P) + 1);
+                T am = 0, ak = 0;
 #pragma unroll
-            for (int q = 0; q < NW; ++q) {
-                if (q >= qa && q < qb) {
+                for (int q = 0; q < 2 * P + 2; ++q) {
+                    if (q >= qa && q < qb) {
+                        const T a = w10[jj1 * NW + q];
+                        if (C::MASS) am += a * t00[q];
+                        if (C::STIFF) ak += w11[jj1 * NW + q] * t00[q] + a * ts[q];
+                    }
+                }
+                if (live) {
+                    const int64_t o = base + ((int64_t)jj1 * m2 + (jj2 - lo2)) * m3 + (jj3 - lo3);
+                    if (C::MASS) vm[o] = am;
+                    if (C::STIFF) vk[o] = ak;
+                }
+            }
+        } else {
+#pragma unroll 1
+            for (int jj1 = lo1; jj1 <= hi1; ++jj1) {
+                T am = 0, ak = 0;
+#pragma unroll
+                for (int q = 0; q < NW; ++q) {
                     const T a = w10[jj1 * NW + q];
                     if (C::MASS) am += a * t00[q];
                     if (C::STIFF) ak += w11[jj1 * NW + q] * t00[q] + a * ts[q];
                 }
-            }
-            if (live) {
-                const int64_t o = base + ((int64_t)(jj1 - lo1) * m2 + (jj2 - lo2)) * m3 + (jj3 - lo3);
-                if (C::MASS) vm[o] = am;
-                if (C::STIFF) vk[o] = ak;
+                if (live) {
+                    const int64_t o = base + ((int64_t)(jj1 - lo1) * m2 + (jj2 - lo2)) * m3 + (jj3 - lo3);
+                    if (C::MASS) vm[o] = am;
+                    if (C::STIFF) vk[o] = ak;
+                }
             }
         }
     }
