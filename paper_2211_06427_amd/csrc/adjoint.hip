@@ -386,128 +386,141 @@ template <int P> struct OctAdjCfg {
     static constexpr int NT = ((NP + 63) / 64) * 64;
     static constexpr int AG = P <= 4 ? P1 : (P == 5 ? 3 : 4);
     static constexpr int NAG = (P1 + AG - 1) / AG;
+    static constexpr int KR = (P2 * P2 + NT - 1) / NT;
 };
 
+template <typename T> __device__ inline const T* oct_tab_a(const DevRules& R, int d);
+template <> __device__ inline const double* oct_tab_a<double>(const DevRules& R, int d) { return R.oct_pp64[d]; }
+template <> __device__ inline const float* oct_tab_a<float>(const DevRules& R, int d) { return R.oct_pp32[d]; }
+
+// One workgroup per cut element (it owns the element's octree slots, so dkappa is updated
+// without atomics).  For each a2 (and group of a1) the cotangent block is contracted with
+// direction 1 once per x-group, with direction 2 once per column, and with direction 3 per
+// leaf, following the same leaf order as the forward kernel.
 template <typename T, int P, int WHICH>
 __global__ void __launch_bounds__(OctAdjCfg<P>::NT)
 k_adj_octree(DevRules R, const int32_t* __restrict__ act2cut, const T* __restrict__ gm, const T* __restrict__ gk,
              T* __restrict__ dk) {
     using C = OctAdjCfg<P>;
-    constexpr int P1 = C::P1, NP = C::NP, P2 = C::P2, AG = C::AG, M = 2 * P + 1;
+    constexpr int P1 = C::P1, NP = C::NP, P2 = C::P2, AG = C::AG, M = 2 * P + 1, NT = C::NT, KR = C::KR;
     constexpr bool MASS = (WHICH & 1) != 0, STIFF = (WHICH & 2) != 0;
-    __shared__ double s_phi[3][2][P1][P1];
-    __shared__ T s_pp[3][2][P2][P1];
+    __shared__ T s_pp[3][2 * P2 * P1];
     __shared__ T s_q[2][P1 * NP];                    // [v][g1][b2 a3 b3]
     __shared__ T s_r[2][P2 * P2];                    // [v][g1 g2][a3 b3]
-    const int ce = blockIdx.x / (P1 * C::NAG);
-    const int a2 = (blockIdx.x / C::NAG) % P1;
-    const int ag0 = (blockIdx.x % C::NAG) * AG;
+    const int ce = blockIdx.x;
     const int64_t eid = R.cut_elems[ce];
     int e[3];
     unlex3a(eid, R.nel, e);
     const int t = threadIdx.x;
     const bool own = t < NP;
     const int b2 = t / P2, a3 = (t / P1) % P1, b3 = t % P1;
-    // cotangents of this thread's (a1 in group, b1) x (b2, a3, b3) entries
-    T gmv[AG][P1], gkv[AG][P1];
-#pragma unroll
-    for (int i = 0; i < AG; ++i) {
-        const int a1 = ag0 + i;
-#pragma unroll
-        for (int b1 = 0; b1 < P1; ++b1) { gmv[i][b1] = 0; gkv[i][b1] = 0; }
-        if (!own || a1 >= P1) continue;
-        const int64_t alex = ((int64_t)(e[0] + a1) * R.nfun[1] + (e[1] + a2)) * R.nfun[2] + (e[2] + a3);
-        const int ra = R.lex2act[alex];
-        const int cr = act2cut[ra];
-        const int32_t* pos = R.pos_map + (int64_t)cr * M * M * M;
-        const int64_t rb = R.row_ptr[ra];
-#pragma unroll
-        for (int b1 = 0; b1 < P1; ++b1) {
-            const int o = pos[((b1 - a1 + P) * M + (b2 - a2 + P)) * M + (b3 - a3 + P)];
-            if (o < 0) continue;
-            if (MASS) gmv[i][b1] = gm[rb + o];
-            if (STIFF) gkv[i][b1] = gk[rb + o];
-        }
-    }
     const int64_t oct0 = R.n_grid + R.n_block;
     const int cb = R.cell_begin[ce], cend = R.cell_begin[ce + 1];
-    for (int cell = cb; cell < cend; ++cell) {
-        if (t < 3 * P1) {
-            const int d = t / P1, g = t % P1;
-            const int scale = 1 << R.cell_depth[cell];
-            const double size = R.h[d] / scale;
-            const double x = R.cell_lo[(int64_t)cell * 3 + d] + (1.0 + R.gxi[g]) / 2.0 * size;
-            double kn[2 * WQ_PMAX + 2];
-            for (int k = 0; k < 2 * P + 2; ++k) {
-                int kk = e[d] + k - P;
-                kk = kk < 0 ? 0 : (kk > R.nel[d] ? R.nel[d] : kk);
-                kn[k] = R.lo[d] + (double)kk * R.h[d];
+    for (int a2 = 0; a2 < P1; ++a2) {
+        for (int ag0 = 0; ag0 < P1; ag0 += AG) {
+            T gmv[AG][P1], gkv[AG][P1];
+#pragma unroll
+            for (int i = 0; i < AG; ++i) {
+                const int a1 = ag0 + i;
+#pragma unroll
+                for (int b1 = 0; b1 < P1; ++b1) { gmv[i][b1] = 0; gkv[i][b1] = 0; }
+                if (!own || a1 >= P1) continue;
+                const int64_t alex = ((int64_t)(e[0] + a1) * R.nfun[1] + (e[1] + a2)) * R.nfun[2] + (e[2] + a3);
+                const int ra = R.lex2act[alex];
+                const int cr = act2cut[ra];
+                const int32_t* pos = R.pos_map + (int64_t)cr * M * M * M;
+                const int64_t rb = R.row_ptr[ra];
+#pragma unroll
+                for (int b1 = 0; b1 < P1; ++b1) {
+                    const int o = pos[((b1 - a1 + P) * M + (b2 - a2 + P)) * M + (b3 - a3 + P)];
+                    if (o < 0) continue;
+                    if (MASS) gmv[i][b1] = gm[rb + o];
+                    if (STIFF) gkv[i][b1] = gk[rb + o];
+                }
             }
-            double N[WQ_PMAX + 1], dN[WQ_PMAX + 1];
-            basis_funs(kn, P, P, x, N, dN);
-            for (int k = 0; k <= P; ++k) { s_phi[d][0][k][g] = N[k]; s_phi[d][1][k][g] = dN[k]; }
-        }
-        __syncthreads();
-        for (int k = t; k < 3 * 2 * P2 * P1; k += C::NT) {
-            const int d = k / (2 * P2 * P1), v = (k / (P2 * P1)) % 2, ab = (k / P1) % P2, g = k % P1;
-            s_pp[d][v][ab][g] = (T)(s_phi[d][v][ab / P1][g] * s_phi[d][v][ab % P1][g]);
-        }
-        __syncthreads();
-        // C^T: Q0[g1][c2] = sum_{a1,b1} pp1[0] GM + pp1[1] GK; Q1 = sum pp1[0] GK
-        if (own) {
-#pragma unroll
-            for (int g1 = 0; g1 < P1; ++g1) {
-                T q0 = 0, q1 = 0;
-#pragma unroll
-                for (int i = 0; i < AG; ++i) {
-                    const int a1 = ag0 + i;
-                    if (a1 >= P1) break;
-#pragma unroll
-                    for (int b1 = 0; b1 < P1; ++b1) {
-                        const T w0 = s_pp[0][0][a1 * P1 + b1][g1];
-                        if (MASS) q0 += w0 * gmv[i][b1];
-                        if (STIFF) { q0 += s_pp[0][1][a1 * P1 + b1][g1] * gkv[i][b1]; q1 += w0 * gkv[i][b1]; }
+            for (int k = cb; k < cend; ++k) {
+                const int cell = R.cell_perm[k];
+                const int key = R.cell_key[cell];
+                const int kprev = k > cb ? R.cell_key[R.cell_perm[k - 1]] : -1;
+                const int xmask = (1 << 9) - 1, cmask = (1 << 15) - 1;
+                const bool new_x = kprev < 0 || (key & xmask) != (kprev & xmask);
+                const bool new_col = kprev < 0 || (key & cmask) != (kprev & cmask);
+                {
+                    constexpr int NPP = 2 * P2 * P1;
+                    const int ni = (2 << R.levels) - 1;
+                    const int dep = key & 7;
+                    for (int j = t; j < NPP; j += NT) {
+                        s_pp[2][j] = oct_tab_a<T>(R, 2)[((int64_t)e[2] * ni + (1 << dep) - 1 + ((key >> 15) & 63)) * NPP + j];
+                        if (new_col) s_pp[1][j] = oct_tab_a<T>(R, 1)[((int64_t)e[1] * ni + (1 << dep) - 1 + ((key >> 9) & 63)) * NPP + j];
+                        if (new_x) s_pp[0][j] = oct_tab_a<T>(R, 0)[((int64_t)e[0] * ni + (1 << dep) - 1 + ((key >> 3) & 63)) * NPP + j];
                     }
                 }
-                s_q[0][g1 * NP + t] = q0;
-                if (STIFF) s_q[1][g1 * NP + t] = q1;
-            }
-        }
-        __syncthreads();
-        // B^T: R0[g1 g2][a3 b3] = sum_b2 pp2[0][a2 b2][g2] Q0 + pp2[1] Q1; R1 = sum pp2[0] Q1
-        for (int k = t; k < P2 * P2; k += C::NT) {
-            const int g12 = k / P2, ab3 = k % P2;
-            const int g1 = g12 / P1, g2 = g12 % P1;
-            T r0 = 0, r1 = 0;
+                __syncthreads();
+                if (new_x) {
+                    // Q0[g1][c2] = sum_{a1,b1} pp1[0] GM + pp1[1] GK; Q1 = sum pp1[0] GK
+                    if (own) {
 #pragma unroll
-            for (int bb2 = 0; bb2 < P1; ++bb2) {
-                const T q0 = s_q[0][g1 * NP + bb2 * P2 + ab3];
-                const T w0 = s_pp[1][0][a2 * P1 + bb2][g2];
-                r0 += w0 * q0;
-                if (STIFF) {
-                    const T q1 = s_q[1][g1 * NP + bb2 * P2 + ab3];
-                    r0 += s_pp[1][1][a2 * P1 + bb2][g2] * q1;
-                    r1 += w0 * q1;
+                        for (int g1 = 0; g1 < P1; ++g1) {
+                            T q0 = 0, q1 = 0;
+#pragma unroll
+                            for (int i = 0; i < AG; ++i) {
+                                const int a1 = ag0 + i;
+                                if (a1 >= P1) break;
+#pragma unroll
+                                for (int b1 = 0; b1 < P1; ++b1) {
+                                    const T w0 = s_pp[0][(a1 * P1 + b1) * P1 + g1];
+                                    if (MASS) q0 += w0 * gmv[i][b1];
+                                    if (STIFF) { q0 += s_pp[0][P2 * P1 + (a1 * P1 + b1) * P1 + g1] * gkv[i][b1]; q1 += w0 * gkv[i][b1]; }
+                                }
+                            }
+                            s_q[0][g1 * NP + t] = q0;
+                            if (STIFF) s_q[1][g1 * NP + t] = q1;
+                        }
+                    }
+                    __syncthreads();
                 }
-            }
-            s_r[0][k] = r0;
-            if (STIFF) s_r[1][k] = r1;
-        }
-        __syncthreads();
-        // A^T: dk_g += w_g sum_{a3 b3} pp3[.][a3 b3][g3] R[.][g1 g2][a3 b3]
-        const int64_t pbase = (int64_t)cell * NP;
-        for (int k = t; k < NP; k += C::NT) {
-            const int g12 = k / P1, g3 = k % P1;
-            T v = 0;
+                if (new_col) {
+                    // R0[g1 g2][a3 b3] = sum_b2 pp2[0][a2 b2][g2] Q0 + pp2[1] Q1; R1 = sum pp2[0] Q1
 #pragma unroll
-            for (int ab3 = 0; ab3 < P2; ++ab3) {
-                v += s_pp[2][0][ab3][g3] * s_r[0][g12 * P2 + ab3];
-                if (STIFF) v += s_pp[2][1][ab3][g3] * s_r[1][g12 * P2 + ab3];
+                    for (int i = 0; i < KR; ++i) {
+                        const int it = t + i * NT;
+                        if (it < P2 * P2) {
+                            const int g12 = it / P2, ab3 = it % P2;
+                            const int g1 = g12 / P1, g2 = g12 % P1;
+                            T r0 = 0, r1 = 0;
+#pragma unroll
+                            for (int bb2 = 0; bb2 < P1; ++bb2) {
+                                const T q0 = s_q[0][g1 * NP + bb2 * P2 + ab3];
+                                const T w0 = s_pp[1][(a2 * P1 + bb2) * P1 + g2];
+                                r0 += w0 * q0;
+                                if (STIFF) {
+                                    const T q1 = s_q[1][g1 * NP + bb2 * P2 + ab3];
+                                    r0 += s_pp[1][P2 * P1 + (a2 * P1 + bb2) * P1 + g2] * q1;
+                                    r1 += w0 * q1;
+                                }
+                            }
+                            s_r[0][it] = r0;
+                            if (STIFF) s_r[1][it] = r1;
+                        }
+                    }
+                    __syncthreads();
+                }
+                // dk_g += w_g sum_{a3 b3} pp3[.][a3 b3][g3] R[.][g1 g2][a3 b3]
+                if (own) {
+                    const int g12 = t / P1, g3 = t % P1;
+                    T v = 0;
+#pragma unroll
+                    for (int ab3 = 0; ab3 < P2; ++ab3) {
+                        v += s_pp[2][ab3 * P1 + g3] * s_r[0][g12 * P2 + ab3];
+                        if (STIFF) v += s_pp[2][P2 * P1 + ab3 * P1 + g3] * s_r[1][g12 * P2 + ab3];
+                    }
+                    const int64_t pt = (int64_t)cell * NP + t;
+                    const T w = (T)R.oct_w[pt];
+                    if (w != (T)0) dk[oct0 + pt] += w * v;
+                }
+                __syncthreads();
             }
-            const T w = (T)R.oct_w[pbase + k];
-            if (w != (T)0) atomicAdd(&dk[oct0 + pbase + k], w * v);
         }
-        __syncthreads();
     }
 }
 
@@ -532,7 +545,7 @@ static void launch_adj_p(const wq_rules* H, const T* gm, const T* gk, T* dk, hip
     }
     if (R.n_cut_elems > 0) {
         using C = OctAdjCfg<P>;
-        hipLaunchKernelGGL((k_adj_octree<T, P, WHICH>), dim3((unsigned)(R.n_cut_elems * C::P1 * C::NAG)), dim3(C::NT), 0, s, R,
+        hipLaunchKernelGGL((k_adj_octree<T, P, WHICH>), dim3((unsigned)R.n_cut_elems), dim3(C::NT), 0, s, R,
                            H->act2cut, gm, gk, dk);
     }
 }

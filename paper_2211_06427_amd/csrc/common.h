@@ -60,6 +60,10 @@ struct DevRules {
     const int32_t* cell_begin;          // (n_cut_elems + 1)
     const double* cell_lo;              // [cell][3]
     const int8_t* cell_depth;
+    const int32_t* cell_key;            // depth | offx << 3 | offy << 9 | offz << 15
+    const int32_t* cell_perm;           // per cut element, leaves sorted by (depth, offx, offy, offz)
+    const double* oct_pp64[3];          // per direction: [element][interval][v][a b][g] basis products
+    const float* oct_pp32[3];
     const double* oct_w;                // [cell * (p+1)^3 + point]
     int64_t n_cut_elems, n_cells;
     // slots

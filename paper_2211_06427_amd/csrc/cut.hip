@@ -139,20 +139,32 @@ template <int P> struct OctCfg {
     static constexpr int NT = ((NP + 63) / 64) * 64;
     static constexpr int AG = P <= 4 ? P1 : (P == 5 ? 3 : 4);       // a1 per workgroup
     static constexpr int NAG = (P1 + AG - 1) / AG;
+    static constexpr int KA = (P2 * P2 + NT - 1) / NT;               // stage-A items per thread
+    static constexpr int KB = (P1 * P1 * P2 + NT - 1) / NT;          // stage-B items per thread
 };
 
+template <typename T> __device__ inline const T* oct_tab(const DevRules& R, int d);
+template <> __device__ inline const double* oct_tab<double>(const DevRules& R, int d) { return R.oct_pp64[d]; }
+template <> __device__ inline const float* oct_tab<float>(const DevRules& R, int d) { return R.oct_pp32[d]; }
+
+// Leaves are visited in the per-element sorted order: leaves with the same x-interval are
+// contiguous (one x-group), and inside an x-group leaves with the same y-interval are
+// contiguous (one column).  Stage A (direction 3) runs per leaf and accumulates over the
+// column, stage B (direction 2) runs once per column and accumulates over the x-group,
+// stage C (direction 1) runs once per x-group: each stage is applied to the sum of the
+// partial results that share its 1D basis products.
 template <typename T, int P, int WHICH>
 __global__ void __launch_bounds__(OctCfg<P>::NT)
 k_cut_octree(DevRules R, const int32_t* __restrict__ act2cut, const T* __restrict__ kappa, T* __restrict__ vm,
              T* __restrict__ vk) {
     using C = OctCfg<P>;
-    constexpr int P1 = C::P1, NP = C::NP, P2 = C::P2, AG = C::AG, M = 2 * P + 1;
+    constexpr int P1 = C::P1, NP = C::NP, P2 = C::P2, AG = C::AG, M = 2 * P + 1, NT = C::NT;
+    constexpr int KA = C::KA, KB = C::KB;
     constexpr bool MASS = (WHICH & 1) != 0, STIFF = (WHICH & 2) != 0;
     __shared__ T s_wk[NP];
-    __shared__ double s_phi[3][2][P1][P1];             // [d][a][k][g]
-    __shared__ T s_pp[3][2][P2][P1];                    // [d][v][(a b)][g]: phi_a phi_b, phi'_a phi'_b
-    __shared__ T s_p1[2][P2 * P2];                      // [v][g1 g2][a3 b3]
-    __shared__ T s_p2[2][P1 * P1 * P2];                 // [v][g1][b2][a3 b3]
+    __shared__ T s_pp[3][2 * P2 * P1];                  // x-group, column, leaf products
+    __shared__ T s_p1[2][P2 * P2];                      // column result [v][g1 g2][a3 b3]
+    __shared__ T s_p2[2][P1 * P1 * P2];                 // x-group result [v][g1][b2][a3 b3]
     const int ce = blockIdx.x / (P1 * C::NAG);
     const int a2 = (blockIdx.x / C::NAG) % P1;
     const int ag0 = (blockIdx.x % C::NAG) * AG;
@@ -162,89 +174,152 @@ k_cut_octree(DevRules R, const int32_t* __restrict__ act2cut, const T* __restric
     const int t = threadIdx.x;
     const bool own = t < NP;
     const int b2 = t / P2, a3 = (t / P1) % P1, b3 = t % P1;   // stage-C column c2 = (b2, a3, b3)
-    T accm[AG][P1], acck[AG][P1];
+    T accA[2][KA], accB[2][KB], accm[AG][P1], acck[AG][P1];
 #pragma unroll
     for (int i = 0; i < AG; ++i)
 #pragma unroll
         for (int j = 0; j < P1; ++j) { accm[i][j] = 0; acck[i][j] = 0; }
     const int64_t oct0 = R.n_grid + R.n_block;
     const int cb = R.cell_begin[ce], cend = R.cell_begin[ce + 1];
-    for (int cell = cb; cell < cend; ++cell) {
-        const int64_t pbase = (int64_t)cell * NP;
-        for (int k = t; k < NP; k += C::NT) s_wk[k] = (T)(R.oct_w[pbase + k]) * kappa[oct0 + pbase + k];
-        if (t < 3 * P1) {
-            const int d = t / P1, g = t % P1;
-            const int scale = 1 << R.cell_depth[cell];
-            const double size = R.h[d] / scale;
-            const double x = R.cell_lo[(int64_t)cell * 3 + d] + (1.0 + R.gxi[g]) / 2.0 * size;
-            double kn[2 * WQ_PMAX + 2];
-            for (int k = 0; k < 2 * P + 2; ++k) {
-                int kk = e[d] + k - P;
-                kk = kk < 0 ? 0 : (kk > R.nel[d] ? R.nel[d] : kk);
-                kn[k] = R.lo[d] + (double)kk * R.h[d];
+    // software pipeline: the next leaf's weight * kappa (one point per thread), key and its
+    // direction-3 basis products are loaded while the current leaf is contracted
+    constexpr int NPP = 2 * P2 * P1, KP = (NPP + NT - 1) / NT;
+    const int ni = (2 << R.levels) - 1;
+    const T* tab[3] = {oct_tab<T>(R, 0) + (int64_t)e[0] * ni * NPP, oct_tab<T>(R, 1) + (int64_t)e[1] * ni * NPP,
+                       oct_tab<T>(R, 2) + (int64_t)e[2] * ni * NPP};
+    auto ivl = [](int key, int d) { const int dep = key & 7; return (1 << dep) - 1 + ((key >> (3 + 6 * d)) & 63); };
+    int cell_n = cb < cend ? R.cell_perm[cb] : 0;
+    int key_n = cb < cend ? R.cell_key[cell_n] : 0;
+    T wk_n = (own && cb < cend) ? (T)R.oct_w[(int64_t)cell_n * NP + t] * kappa[oct0 + (int64_t)cell_n * NP + t] : (T)0;
+    T pz_n[KP];
+#pragma unroll
+    for (int i = 0; i < KP; ++i) {
+        const int j = t + i * NT;
+        pz_n[i] = (cb < cend && j < NPP) ? tab[2][(int64_t)ivl(key_n, 2) * NPP + j] : (T)0;
+    }
+    int kprev = -1;
+    for (int k = cb; k < cend; ++k) {
+        const int cell = cell_n, key = key_n;
+        const T wk = wk_n;
+        T pz[KP];
+#pragma unroll
+        for (int i = 0; i < KP; ++i) pz[i] = pz_n[i];
+        if (k + 1 < cend) {
+            cell_n = R.cell_perm[k + 1];
+            key_n = R.cell_key[cell_n];
+            if (own) wk_n = (T)R.oct_w[(int64_t)cell_n * NP + t] * kappa[oct0 + (int64_t)cell_n * NP + t];
+#pragma unroll
+            for (int i = 0; i < KP; ++i) {
+                const int j = t + i * NT;
+                if (j < NPP) pz_n[i] = tab[2][(int64_t)ivl(key_n, 2) * NPP + j];
             }
-            double N[WQ_PMAX + 1], dN[WQ_PMAX + 1];
-            basis_funs(kn, P, P, x, N, dN);
-            for (int k = 0; k <= P; ++k) { s_phi[d][0][k][g] = N[k]; s_phi[d][1][k][g] = dN[k]; }
+        }
+        const int knext = k + 1 < cend ? key_n : -1;
+        const int xmask = (1 << 9) - 1, cmask = (1 << 15) - 1;
+        const bool new_x = kprev < 0 || (key & xmask) != (kprev & xmask);
+        const bool new_col = kprev < 0 || (key & cmask) != (kprev & cmask);
+        const bool end_col = knext < 0 || (key & cmask) != (knext & cmask);
+        const bool end_x = knext < 0 || (key & xmask) != (knext & xmask);
+        kprev = key;
+        if (new_col) {
+#pragma unroll
+            for (int i = 0; i < KA; ++i) { accA[0][i] = 0; accA[1][i] = 0; }
+        }
+        if (new_x) {
+#pragma unroll
+            for (int i = 0; i < KB; ++i) { accB[0][i] = 0; accB[1][i] = 0; }
+        }
+        if (own) s_wk[t] = wk;
+#pragma unroll
+        for (int i = 0; i < KP; ++i) {
+            const int j = t + i * NT;
+            if (j < NPP) {
+                s_pp[2][j] = pz[i];
+                if (new_col) s_pp[1][j] = tab[1][(int64_t)ivl(key, 1) * NPP + j];
+                if (new_x) s_pp[0][j] = tab[0][(int64_t)ivl(key, 0) * NPP + j];
+            }
         }
         __syncthreads();
-        for (int k = t; k < 3 * 2 * P2 * P1; k += C::NT) {
-            const int d = k / (2 * P2 * P1), v = (k / (P2 * P1)) % 2, ab = (k / P1) % P2, g = k % P1;
-            s_pp[d][v][ab][g] = (T)(s_phi[d][v][ab / P1][g] * s_phi[d][v][ab % P1][g]);
-        }
-        __syncthreads();
-        // stage A: P1[v][g1 g2][a3 b3] = sum_g3 pp3[v][a3 b3][g3] wk[g1 g2 g3]
-        for (int k = t; k < P2 * P2; k += C::NT) {
-            const int g12 = k / P2, ab3 = k % P2;
-            T s0 = 0, s1 = 0;
+        // stage A: accA[v][g1 g2][a3 b3] += sum_g3 pp3[v][a3 b3][g3] wk[g1 g2 g3]
 #pragma unroll
-            for (int g3 = 0; g3 < P1; ++g3) {
-                const T w = s_wk[g12 * P1 + g3];
-                s0 += s_pp[2][0][ab3][g3] * w;
-                if (STIFF) s1 += s_pp[2][1][ab3][g3] * w;
+        for (int i = 0; i < KA; ++i) {
+            const int it = t + i * NT;
+            if (it < P2 * P2) {
+                const int g12 = it / P2, ab3 = it % P2;
+                T s0 = 0, s1 = 0;
+#pragma unroll
+                for (int g3 = 0; g3 < P1; ++g3) {
+                    const T w = s_wk[g12 * P1 + g3];
+                    s0 += s_pp[2][ab3 * P1 + g3] * w;
+                    if (STIFF) s1 += s_pp[2][P2 * P1 + ab3 * P1 + g3] * w;
+                }
+                accA[0][i] += s0;
+                accA[1][i] += s1;
             }
-            s_p1[0][k] = s0;
-            if (STIFF) s_p1[1][k] = s1;
         }
-        __syncthreads();
-        // stage B: P2_00[g1][b2][a3 b3] = sum_g2 pp2[0][a2 b2][g2] P1_0; P2_s = pp2[1] P1_0 + pp2[0] P1_1
-        for (int k = t; k < P1 * P1 * P2; k += C::NT) {
-            const int g1 = k / (P1 * P2), bb2 = (k / P2) % P1, ab3 = k % P2;
-            T s0 = 0, ss = 0;
+        if (end_col) {
 #pragma unroll
-            for (int g2 = 0; g2 < P1; ++g2) {
-                const T v0 = s_p1[0][(g1 * P1 + g2) * P2 + ab3];
-                const T w0 = s_pp[1][0][a2 * P1 + bb2][g2];
-                s0 += w0 * v0;
-                if (STIFF) ss += s_pp[1][1][a2 * P1 + bb2][g2] * v0 + w0 * s_p1[1][(g1 * P1 + g2) * P2 + ab3];
+            for (int i = 0; i < KA; ++i) {
+                const int it = t + i * NT;
+                if (it < P2 * P2) {
+                    s_p1[0][it] = accA[0][i];
+                    if (STIFF) s_p1[1][it] = accA[1][i];
+                }
             }
-            s_p2[0][k] = s0;
-            if (STIFF) s_p2[1][k] = ss;
-        }
-        __syncthreads();
-        // stage C: acc[a1][b1] += sum_g1 pp1[.][a1 b1][g1] P2[.][g1][c2]
-        if (own) {
-            T v0[P1], vs[P1];
+            __syncthreads();
+            // stage B: accB[g1][b2][a3 b3] += sum_g2 pp2[0][a2 b2][g2] P1_0 (+ stiffness terms)
 #pragma unroll
-            for (int g1 = 0; g1 < P1; ++g1) {
-                v0[g1] = s_p2[0][g1 * P1 * P2 + t];
-                vs[g1] = STIFF ? s_p2[1][g1 * P1 * P2 + t] : (T)0;
+            for (int i = 0; i < KB; ++i) {
+                const int it = t + i * NT;
+                if (it < P1 * P1 * P2) {
+                    const int g1 = it / (P1 * P2), bb2 = (it / P2) % P1, ab3 = it % P2;
+                    T s0 = 0, ss = 0;
+#pragma unroll
+                    for (int g2 = 0; g2 < P1; ++g2) {
+                        const T v0 = s_p1[0][(g1 * P1 + g2) * P2 + ab3];
+                        const T w0 = s_pp[1][(a2 * P1 + bb2) * P1 + g2];
+                        s0 += w0 * v0;
+                        if (STIFF) ss += s_pp[1][P2 * P1 + (a2 * P1 + bb2) * P1 + g2] * v0 + w0 * s_p1[1][(g1 * P1 + g2) * P2 + ab3];
+                    }
+                    accB[0][i] += s0;
+                    accB[1][i] += ss;
+                }
             }
+            if (end_x) {
 #pragma unroll
-            for (int i = 0; i < AG; ++i) {
-                const int a1 = ag0 + i;
-                if (a1 >= P1) break;
-#pragma unroll
-                for (int b1 = 0; b1 < P1; ++b1) {
-                    T sm = 0, sk = 0;
+                for (int i = 0; i < KB; ++i) {
+                    const int it = t + i * NT;
+                    if (it < P1 * P1 * P2) {
+                        s_p2[0][it] = accB[0][i];
+                        if (STIFF) s_p2[1][it] = accB[1][i];
+                    }
+                }
+                __syncthreads();
+                // stage C: acc[a1][b1] += sum_g1 pp1[.][a1 b1][g1] P2[.][g1][c2]
+                if (own) {
+                    T v0[P1], vs[P1];
 #pragma unroll
                     for (int g1 = 0; g1 < P1; ++g1) {
-                        const T w0 = s_pp[0][0][a1 * P1 + b1][g1];
-                        sm += w0 * v0[g1];
-                        if (STIFF) sk += s_pp[0][1][a1 * P1 + b1][g1] * v0[g1] + w0 * vs[g1];
+                        v0[g1] = s_p2[0][g1 * P1 * P2 + t];
+                        vs[g1] = STIFF ? s_p2[1][g1 * P1 * P2 + t] : (T)0;
                     }
-                    accm[i][b1] += sm;
-                    acck[i][b1] += sk;
+#pragma unroll
+                    for (int i = 0; i < AG; ++i) {
+                        const int a1 = ag0 + i;
+                        if (a1 >= P1) break;
+#pragma unroll
+                        for (int b1 = 0; b1 < P1; ++b1) {
+                            T sm = 0, sk = 0;
+#pragma unroll
+                            for (int g1 = 0; g1 < P1; ++g1) {
+                                const T w0 = s_pp[0][(a1 * P1 + b1) * P1 + g1];
+                                sm += w0 * v0[g1];
+                                if (STIFF) sk += s_pp[0][P2 * P1 + (a1 * P1 + b1) * P1 + g1] * v0[g1] + w0 * vs[g1];
+                            }
+                            accm[i][b1] += sm;
+                            acck[i][b1] += sk;
+                        }
+                    }
                 }
             }
         }

@@ -699,9 +699,10 @@ __global__ void k_flag_eq(int64_t n, const int8_t* v, int8_t want, int32_t* flag
 // octree of a cut element: depth-first, children in lexicographic order (first offset
 // bit slowest); leaves are interior cells at any depth and cut cells at depth L.
 // ----------------------------------------------------------------------------------------
+// cell key: depth | offx << 3 | offy << 9 | offz << 15 (offsets in units of h / 2^depth)
 template <bool FILL>
 __global__ void k_octree(DevRules R, int64_t nce, const int32_t* cut_elems, int32_t* cnt, const int64_t* begin,
-                         double* cell_lo, int8_t* cell_depth, int8_t* cell_cut, int32_t* cell_elem) {
+                         double* cell_lo, int8_t* cell_depth, int8_t* cell_cut, int32_t* cell_elem, int32_t* cell_key) {
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= nce) return;
     int64_t eid = cut_elems[c];
@@ -734,6 +735,7 @@ __global__ void k_octree(DevRules R, int64_t nce, const int32_t* cut_elems, int3
                 cell_depth[k] = (int8_t)dep;
                 cell_cut[k] = (int8_t)(cls != CLS_IN);
                 cell_elem[k] = (int32_t)c;
+                cell_key[k] = dep | (off[0] << 3) | (off[1] << 9) | (off[2] << 15);
                 ++k;
             }
             ++n;
@@ -748,6 +750,59 @@ __global__ void k_octree(DevRules R, int64_t nce, const int32_t* cut_elems, int3
         }
     }
     if (!FILL) cnt[c] = n;
+}
+
+// Per cut element: leaves ordered by key, so that leaves sharing an x-interval (same depth
+// and x offset) are contiguous and, inside, leaves sharing an (x, y) column are contiguous.
+__global__ void k_octree_sort(int64_t nce, const int64_t* begin, const int32_t* cell_key, int32_t* perm) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nce) return;
+    const int64_t b = begin[c], e = begin[c + 1];
+    for (int64_t k = b; k < e; ++k) {          // insertion sort by (depth, offx, offy, offz)
+        const int32_t v = (int32_t)k;
+        const int32_t key = cell_key[k];
+        const int32_t kk = (key & 7) << 18 | ((key >> 3) & 63) << 12 | ((key >> 9) & 63) << 6 | ((key >> 15) & 63);
+        int64_t j = k - 1;
+        while (j >= b) {
+            const int32_t o = cell_key[perm[j]];
+            const int32_t ok = (o & 7) << 18 | ((o >> 3) & 63) << 12 | ((o >> 9) & 63) << 6 | ((o >> 15) & 63);
+            if (ok <= kk) break;
+            perm[j + 1] = perm[j];
+            --j;
+        }
+        perm[j + 1] = v;
+    }
+}
+
+// 1D basis products of element e's functions at the Gauss points of each octree interval
+// (depth l, offset o; index 2^l - 1 + o) in direction d:
+// pp[((e * NI + iv) * 2 + v) * P1^2 + a * P1 + b][g] = phi_a phi_b (v = 0) or phi_a' phi_b' (v = 1),
+// with the leaf coordinates formed exactly as for the octree weights.
+__global__ void k_oct_basis(DevRules R, int d, const double* gxi, double* pp) {
+    const int p = R.p, p1 = p + 1, p2 = p1 * p1;
+    const int ni = (2 << R.levels) - 1;
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= (int64_t)R.nel[d] * ni * p1) return;
+    const int g = (int)(id % p1);
+    const int iv = (int)((id / p1) % ni);
+    const int e = (int)(id / ((int64_t)p1 * ni));
+    int dep = 0;
+    while ((2 << dep) - 1 <= iv) ++dep;
+    const int off = iv - ((1 << dep) - 1);
+    const int scale = 1 << dep;
+    const double size = R.h[d] / scale;
+    const double lo = R.lo[d] + ((double)e * scale + off) * (R.h[d] / scale);
+    const double x = lo + (1.0 + gxi[g]) / 2.0 * size;
+    double kn[2 * WQ_PMAX + 2];
+    for (int j = 0; j < 2 * p + 2; ++j) kn[j] = knot_at(e + j, p, R.nel[d], R.lo[d], R.h[d]);
+    double N[WQ_PMAX + 1], dN[WQ_PMAX + 1];
+    basis_funs(kn, p, p, x, N, dN);
+    double* out = pp + ((int64_t)e * ni + iv) * 2 * p2 * p1;
+    for (int a = 0; a < p1; ++a)
+        for (int b = 0; b < p1; ++b) {
+            out[(a * p1 + b) * p1 + g] = N[a] * N[b];
+            out[p2 * p1 + (a * p1 + b) * p1 + g] = dN[a] * dN[b];
+        }
 }
 
 __global__ void k_octree_weights(DevRules R, const double* gxi, const double* gw, const double* cell_lo,
@@ -1016,7 +1071,7 @@ int build_rules(const wq_mesh* mesh, const wq_levelset* ls, const wq_options* op
         if (!ccnt || !cbeg || !cbeg32) return B.fail();
         if (nce > 0)
             hipLaunchKernelGGL(k_octree<false>, grid_for(nce, 64), dim3(64), 0, stream, R, nce, cut_elems, ccnt, nullptr,
-                               nullptr, nullptr, nullptr, nullptr);
+                               nullptr, nullptr, nullptr, nullptr, nullptr);
         int64_t ncell = 0;
         if (scan_exclusive(B, ccnt, cbeg, nce, &ncell)) return B.fail();
         if (ncell >= (int64_t)1 << 31) return B.fail_msg(WQ_EUNSUPPORTED, "octree has too many cells (%lld)", (long long)ncell);
@@ -1027,10 +1082,25 @@ int build_rules(const wq_mesh* mesh, const wq_levelset* ls, const wq_options* op
         int8_t* cdep = B.keep<int8_t>(nc);
         int8_t* ccut = B.keep<int8_t>(nc);
         int32_t* celem = B.keep<int32_t>(nc);
-        if (!clo || !cdep || !ccut || !celem) return B.fail();
-        if (nce > 0)
+        int32_t* ckey = B.keep<int32_t>(nc);
+        int32_t* cperm = B.keep<int32_t>(nc);
+        if (!clo || !cdep || !ccut || !celem || !ckey || !cperm) return B.fail();
+        if (nce > 0) {
             hipLaunchKernelGGL(k_octree<true>, grid_for(nce, 64), dim3(64), 0, stream, R, nce, cut_elems, nullptr, cbeg,
-                               clo, cdep, ccut, celem);
+                               clo, cdep, ccut, celem, ckey);
+            hipLaunchKernelGGL(k_octree_sort, grid_for(nce, 64), dim3(64), 0, stream, nce, cbeg, ckey, cperm);
+        }
+        R.cell_key = ckey; R.cell_perm = cperm;
+        const int ni = (2 << R.levels) - 1;
+        for (int d = 0; d < 3; ++d) {
+            const int64_t n = (int64_t)R.nel[d] * ni * 2 * p1 * p1 * p1;
+            double* pp = B.keep<double>(n);
+            float* pp32 = B.keep<float>(n);
+            if (!pp || !pp32) return B.fail();
+            hipLaunchKernelGGL(k_oct_basis, grid_for((int64_t)R.nel[d] * ni * p1), dim3(256), 0, stream, R, d, gxi, pp);
+            hipLaunchKernelGGL(k_convert<float>, grid_for(n), dim3(256), 0, stream, pp, pp32, n);
+            R.oct_pp64[d] = pp; R.oct_pp32[d] = pp32;
+        }
         hipLaunchKernelGGL(k_i64_to_i32, grid_for(nce + 1), dim3(256), 0, stream, cbeg, cbeg32, nce + 1);
         R.cell_begin = cbeg32; R.cell_lo = clo; R.cell_depth = cdep;
         H->cell_cut = ccut; H->cell_elem = celem;
