@@ -292,6 +292,7 @@ k_adj_remainder(DevRules R, const int32_t* __restrict__ box, const T* __restrict
     __shared__ T s_w[NWAVE][3][2][P1 * P1];
     __shared__ T s_c[NWAVE][2][NP];
     __shared__ T s_b[NWAVE][2][NP];
+    __shared__ int s_rem[NP], s_nrem;
     const int64_t cr = blockIdx.x;
     const int ra = R.cut_rows[cr];
     int I[3];
@@ -315,13 +316,22 @@ k_adj_remainder(DevRules R, const int32_t* __restrict__ box, const T* __restrict
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     const int n2 = hi[1] - lo[1] + 1, n3 = hi[2] - lo[2] + 1;
     const int ne = (hi[0] - lo[0] + 1) * n2 * n3;
-    for (int k = wave; k < ne; k += NWAVE) {
+    // compact list of this row's remainder elements (interior, outside the DWQ box)
+    if (threadIdx.x == 0) s_nrem = 0;
+    __syncthreads();
+    for (int k = threadIdx.x; k < ne; k += 256) {
+        const int e0 = lo[0] + k / (n2 * n3), e1 = lo[1] + (k / n3) % n2, e2 = lo[2] + k % n3;
+        const int64_t eid = ((int64_t)e0 * R.nel[1] + e1) * R.nel[2] + e2;
+        const bool inbox = has_box && e0 >= blo[0] && e0 <= bhi[0] && e1 >= blo[1] && e1 <= bhi[1] && e2 >= blo[2] &&
+                           e2 <= bhi[2];
+        if (R.ecls[eid] == CLS_IN && !inbox) s_rem[atomicAdd(&s_nrem, 1)] = k;
+    }
+    __syncthreads();
+    const int nrem = s_nrem;
+    for (int r = wave; r < nrem; r += NWAVE) {
+        const int k = s_rem[r];
         const int e[3] = {lo[0] + k / (n2 * n3), lo[1] + (k / n3) % n2, lo[2] + k % n3};
         const int64_t eid = ((int64_t)e[0] * R.nel[1] + e[1]) * R.nel[2] + e[2];
-        if (R.ecls[eid] != CLS_IN) continue;
-        if (has_box && e[0] >= blo[0] && e[0] <= bhi[0] && e[1] >= blo[1] && e[1] <= bhi[1] && e[2] >= blo[2] &&
-            e[2] <= bhi[2])
-            continue;
         for (int t = lane; t < 3 * 2 * P1 * P1; t += 64) {
             const int d = t / (2 * P1 * P1), a = (t / (P1 * P1)) % 2, kk = (t / P1) % P1, g = t % P1;
             const int64_t y = (int64_t)e[d] * P1 + g;
@@ -371,8 +381,7 @@ k_adj_remainder(DevRules R, const int32_t* __restrict__ box, const T* __restrict
                 v += s_w[wave][2][0][k3 * P1 + g3] * s_b[wave][0][g12 * P1 + k3];
                 if (STIFF) v += s_w[wave][2][1][k3 * P1 + g3] * s_b[wave][1][g12 * P1 + k3];
             }
-            const int g1 = g12 / P1, g2 = g12 % P1;
-            atomicAdd(&dk[slot_of(R, e[0] * P1 + g1, e[1] * P1 + g2, e[2] * P1 + g3)], v);
+            atomicAdd(&dk[R.blk_slot[(int64_t)R.elem_block[eid] * NP + t]], v);
         }
         wave_sync_a();
     }
@@ -386,7 +395,6 @@ template <int P> struct OctAdjCfg {
     static constexpr int NT = ((NP + 63) / 64) * 64;
     static constexpr int AG = P <= 4 ? P1 : (P == 5 ? 3 : 4);
     static constexpr int NAG = (P1 + AG - 1) / AG;
-    static constexpr int KR = (P2 * P2 + NT - 1) / NT;
 };
 
 template <typename T> __device__ inline const T* oct_tab_a(const DevRules& R, int d);
@@ -394,129 +402,167 @@ template <> __device__ inline const double* oct_tab_a<double>(const DevRules& R,
 template <> __device__ inline const float* oct_tab_a<float>(const DevRules& R, int d) { return R.oct_pp32[d]; }
 
 // One workgroup per cut element (it owns the element's octree slots, so dkappa is updated
-// without atomics).  For each a2 (and group of a1) the cotangent block is contracted with
-// direction 1 once per x-group, with direction 2 once per column, and with direction 3 per
-// leaf, following the same leaf order as the forward kernel.
+// without atomics).  For each a3 (and group of a1) the cotangent block G[a1 b1][a2 b2 b3] is
+// contracted with direction 1 once per x-group, with direction 2 once per column, and with
+// direction 3 per leaf, in the same leaf order as the forward kernel.
 template <typename T, int P, int WHICH>
 __global__ void __launch_bounds__(OctAdjCfg<P>::NT)
 k_adj_octree(DevRules R, const int32_t* __restrict__ act2cut, const T* __restrict__ gm, const T* __restrict__ gk,
              T* __restrict__ dk) {
     using C = OctAdjCfg<P>;
-    constexpr int P1 = C::P1, NP = C::NP, P2 = C::P2, AG = C::AG, M = 2 * P + 1, NT = C::NT, KR = C::KR;
+    constexpr int P1 = C::P1, NP = C::NP, P2 = C::P2, AG = C::AG, M = 2 * P + 1, NT = C::NT;
+    constexpr int NPP = 2 * P2 * P1, KP = (NPP + NT - 1) / NT, MAXC = 512;
     constexpr bool MASS = (WHICH & 1) != 0, STIFF = (WHICH & 2) != 0;
-    __shared__ T s_pp[3][2 * P2 * P1];
-    __shared__ T s_q[2][P1 * NP];                    // [v][g1][b2 a3 b3]
-    __shared__ T s_r[2][P2 * P2];                    // [v][g1 g2][a3 b3]
+    __shared__ int s_cell[MAXC], s_key[MAXC];
+    __shared__ T s_pz[2][NPP], s_py[NPP], s_px[NPP];
+    __shared__ T s_q[2][P1 * NP];                    // [v][g1][a2 b2 b3]
+    __shared__ T s_r[2][P2 * P1];                    // [v][g1 g2][b3]
     const int ce = blockIdx.x;
     const int64_t eid = R.cut_elems[ce];
     int e[3];
     unlex3a(eid, R.nel, e);
     const int t = threadIdx.x;
     const bool own = t < NP;
-    const int b2 = t / P2, a3 = (t / P1) % P1, b3 = t % P1;
+    const int a2 = t / P2, b2 = (t / P1) % P1, b3 = t % P1;     // c2 = (a2, b2, b3) = t
+    const int g12R = t / P1;                                     // R item (g1 g2, b3) = t
     const int64_t oct0 = R.n_grid + R.n_block;
     const int cb = R.cell_begin[ce], cend = R.cell_begin[ce + 1];
-    for (int a2 = 0; a2 < P1; ++a2) {
-        for (int ag0 = 0; ag0 < P1; ag0 += AG) {
-            T gmv[AG][P1], gkv[AG][P1];
+    const int ni = (2 << R.levels) - 1;
+    const T* tx = oct_tab_a<T>(R, 0) + (int64_t)e[0] * ni * NPP;
+    const T* ty = oct_tab_a<T>(R, 1) + (int64_t)e[1] * ni * NPP;
+    const T* tz = oct_tab_a<T>(R, 2) + (int64_t)e[2] * ni * NPP;
+    auto ivl = [](int key, int d) { return (1 << (key & 7)) - 1 + ((key >> (3 + 6 * d)) & 63); };
+    const int xmask = (1 << 9) - 1, cmask = (1 << 15) - 1;
+    for (int c0 = cb; c0 < cend; c0 += MAXC) {
+        const int nc = cend - c0 < MAXC ? cend - c0 : MAXC;
+        __syncthreads();
+        for (int j = t; j < nc; j += NT) {
+            const int cell = R.cell_perm[c0 + j];
+            s_cell[j] = cell;
+            s_key[j] = R.cell_key[cell];
+        }
+        __syncthreads();
+        for (int a3 = 0; a3 < P1; ++a3) {
+            for (int ag0 = 0; ag0 < P1; ag0 += AG) {
+                T gmv[AG][P1], gkv[AG][P1];
 #pragma unroll
-            for (int i = 0; i < AG; ++i) {
-                const int a1 = ag0 + i;
+                for (int i = 0; i < AG; ++i) {
+                    const int a1 = ag0 + i;
 #pragma unroll
-                for (int b1 = 0; b1 < P1; ++b1) { gmv[i][b1] = 0; gkv[i][b1] = 0; }
-                if (!own || a1 >= P1) continue;
-                const int64_t alex = ((int64_t)(e[0] + a1) * R.nfun[1] + (e[1] + a2)) * R.nfun[2] + (e[2] + a3);
-                const int ra = R.lex2act[alex];
-                const int cr = act2cut[ra];
-                const int32_t* pos = R.pos_map + (int64_t)cr * M * M * M;
-                const int64_t rb = R.row_ptr[ra];
+                    for (int b1 = 0; b1 < P1; ++b1) { gmv[i][b1] = 0; gkv[i][b1] = 0; }
+                    if (!own || a1 >= P1) continue;
+                    const int64_t alex = ((int64_t)(e[0] + a1) * R.nfun[1] + (e[1] + a2)) * R.nfun[2] + (e[2] + a3);
+                    const int ra = R.lex2act[alex];
+                    const int cr = act2cut[ra];
+                    const int32_t* pos = R.pos_map + (int64_t)cr * M * M * M;
+                    const int64_t rb = R.row_ptr[ra];
 #pragma unroll
-                for (int b1 = 0; b1 < P1; ++b1) {
-                    const int o = pos[((b1 - a1 + P) * M + (b2 - a2 + P)) * M + (b3 - a3 + P)];
-                    if (o < 0) continue;
-                    if (MASS) gmv[i][b1] = gm[rb + o];
-                    if (STIFF) gkv[i][b1] = gk[rb + o];
-                }
-            }
-            for (int k = cb; k < cend; ++k) {
-                const int cell = R.cell_perm[k];
-                const int key = R.cell_key[cell];
-                const int kprev = k > cb ? R.cell_key[R.cell_perm[k - 1]] : -1;
-                const int xmask = (1 << 9) - 1, cmask = (1 << 15) - 1;
-                const bool new_x = kprev < 0 || (key & xmask) != (kprev & xmask);
-                const bool new_col = kprev < 0 || (key & cmask) != (kprev & cmask);
-                {
-                    constexpr int NPP = 2 * P2 * P1;
-                    const int ni = (2 << R.levels) - 1;
-                    const int dep = key & 7;
-                    for (int j = t; j < NPP; j += NT) {
-                        s_pp[2][j] = oct_tab_a<T>(R, 2)[((int64_t)e[2] * ni + (1 << dep) - 1 + ((key >> 15) & 63)) * NPP + j];
-                        if (new_col) s_pp[1][j] = oct_tab_a<T>(R, 1)[((int64_t)e[1] * ni + (1 << dep) - 1 + ((key >> 9) & 63)) * NPP + j];
-                        if (new_x) s_pp[0][j] = oct_tab_a<T>(R, 0)[((int64_t)e[0] * ni + (1 << dep) - 1 + ((key >> 3) & 63)) * NPP + j];
+                    for (int b1 = 0; b1 < P1; ++b1) {
+                        const int o = pos[((b1 - a1 + P) * M + (b2 - a2 + P)) * M + (b3 - a3 + P)];
+                        if (o < 0) continue;
+                        if (MASS) gmv[i][b1] = gm[rb + o];
+                        if (STIFF) gkv[i][b1] = gk[rb + o];
                     }
                 }
-                __syncthreads();
-                if (new_x) {
-                    // Q0[g1][c2] = sum_{a1,b1} pp1[0] GM + pp1[1] GK; Q1 = sum pp1[0] GK
-                    if (own) {
+                T w_n = 0, pz_n[KP], py_n[KP], px_n[KP];
+                {
+                    const int cell = s_cell[0], key = s_key[0];
+                    if (own) w_n = (T)R.oct_w[(int64_t)cell * NP + t];
 #pragma unroll
-                        for (int g1 = 0; g1 < P1; ++g1) {
-                            T q0 = 0, q1 = 0;
+                    for (int i = 0; i < KP; ++i) {
+                        const int q = t + i * NT;
+                        pz_n[i] = q < NPP ? tz[(int64_t)ivl(key, 2) * NPP + q] : (T)0;
+                        py_n[i] = q < NPP ? ty[(int64_t)ivl(key, 1) * NPP + q] : (T)0;
+                        px_n[i] = q < NPP ? tx[(int64_t)ivl(key, 0) * NPP + q] : (T)0;
+                    }
+                }
+                int kprev = -1, buf = 0;
+                for (int j = 0; j < nc; ++j) {
+                    const int cell = s_cell[j], key = s_key[j];
+                    const bool new_x = kprev < 0 || (key & xmask) != (kprev & xmask);
+                    const bool new_col = kprev < 0 || (key & cmask) != (kprev & cmask);
+                    kprev = key;
+                    const T w = w_n;
 #pragma unroll
-                            for (int i = 0; i < AG; ++i) {
-                                const int a1 = ag0 + i;
-                                if (a1 >= P1) break;
+                    for (int i = 0; i < KP; ++i) {
+                        const int q = t + i * NT;
+                        if (q < NPP) {
+                            s_pz[buf][q] = pz_n[i];
+                            if (new_col) s_py[q] = py_n[i];
+                            if (new_x) s_px[q] = px_n[i];
+                        }
+                    }
+                    if (j + 1 < nc) {
+                        const int cn = s_cell[j + 1], kn = s_key[j + 1];
+                        if (own) w_n = (T)R.oct_w[(int64_t)cn * NP + t];
+                        const bool nc_next = (kn & cmask) != (key & cmask), nx_next = (kn & xmask) != (key & xmask);
 #pragma unroll
-                                for (int b1 = 0; b1 < P1; ++b1) {
-                                    const T w0 = s_pp[0][(a1 * P1 + b1) * P1 + g1];
-                                    if (MASS) q0 += w0 * gmv[i][b1];
-                                    if (STIFF) { q0 += s_pp[0][P2 * P1 + (a1 * P1 + b1) * P1 + g1] * gkv[i][b1]; q1 += w0 * gkv[i][b1]; }
-                                }
+                        for (int i = 0; i < KP; ++i) {
+                            const int q = t + i * NT;
+                            if (q < NPP) {
+                                pz_n[i] = tz[(int64_t)ivl(kn, 2) * NPP + q];
+                                if (nc_next) py_n[i] = ty[(int64_t)ivl(kn, 1) * NPP + q];
+                                if (nx_next) px_n[i] = tx[(int64_t)ivl(kn, 0) * NPP + q];
                             }
-                            s_q[0][g1 * NP + t] = q0;
-                            if (STIFF) s_q[1][g1 * NP + t] = q1;
                         }
                     }
                     __syncthreads();
-                }
-                if (new_col) {
-                    // R0[g1 g2][a3 b3] = sum_b2 pp2[0][a2 b2][g2] Q0 + pp2[1] Q1; R1 = sum pp2[0] Q1
+                    if (new_x) {
+                        // Q0[g1][c2] = sum_{a1,b1} px[0] GM + px[1] GK; Q1 = sum px[0] GK
+                        if (own) {
 #pragma unroll
-                    for (int i = 0; i < KR; ++i) {
-                        const int it = t + i * NT;
-                        if (it < P2 * P2) {
-                            const int g12 = it / P2, ab3 = it % P2;
-                            const int g1 = g12 / P1, g2 = g12 % P1;
+                            for (int g1 = 0; g1 < P1; ++g1) {
+                                T q0 = 0, q1 = 0;
+#pragma unroll
+                                for (int i = 0; i < AG; ++i) {
+                                    const int a1 = ag0 + i;
+                                    if (a1 >= P1) break;
+#pragma unroll
+                                    for (int b1 = 0; b1 < P1; ++b1) {
+                                        const T w0 = s_px[(a1 * P1 + b1) * P1 + g1];
+                                        if (MASS) q0 += w0 * gmv[i][b1];
+                                        if (STIFF) { q0 += s_px[P2 * P1 + (a1 * P1 + b1) * P1 + g1] * gkv[i][b1]; q1 += w0 * gkv[i][b1]; }
+                                    }
+                                }
+                                s_q[0][g1 * NP + t] = q0;
+                                if (STIFF) s_q[1][g1 * NP + t] = q1;
+                            }
+                        }
+                        __syncthreads();
+                    }
+                    if (new_col) {
+                        // R0[g1 g2][b3] = sum_{a2 b2} py[0][a2 b2][g2] Q0[g1][a2 b2 b3] + py[1] Q1; R1 = sum py[0] Q1
+                        if (t < P2 * P1) {
+                            const int g1 = g12R / P1, g2 = g12R % P1;
                             T r0 = 0, r1 = 0;
 #pragma unroll
-                            for (int bb2 = 0; bb2 < P1; ++bb2) {
-                                const T q0 = s_q[0][g1 * NP + bb2 * P2 + ab3];
-                                const T w0 = s_pp[1][(a2 * P1 + bb2) * P1 + g2];
+                            for (int ab2 = 0; ab2 < P2; ++ab2) {
+                                const T q0 = s_q[0][g1 * NP + ab2 * P1 + b3];
+                                const T w0 = s_py[ab2 * P1 + g2];
                                 r0 += w0 * q0;
                                 if (STIFF) {
-                                    const T q1 = s_q[1][g1 * NP + bb2 * P2 + ab3];
-                                    r0 += s_pp[1][P2 * P1 + (a2 * P1 + bb2) * P1 + g2] * q1;
+                                    const T q1 = s_q[1][g1 * NP + ab2 * P1 + b3];
+                                    r0 += s_py[P2 * P1 + ab2 * P1 + g2] * q1;
                                     r1 += w0 * q1;
                                 }
                             }
-                            s_r[0][it] = r0;
-                            if (STIFF) s_r[1][it] = r1;
+                            s_r[0][t] = r0;
+                            if (STIFF) s_r[1][t] = r1;
                         }
+                        __syncthreads();
                     }
-                    __syncthreads();
-                }
-                // dk_g += w_g sum_{a3 b3} pp3[.][a3 b3][g3] R[.][g1 g2][a3 b3]
-                if (own) {
-                    const int g12 = t / P1, g3 = t % P1;
-                    T v = 0;
+                    // dk_g += w_g sum_b3 pz[.][a3 b3][g3] R[.][g1 g2][b3]
+                    if (own && w != (T)0) {
+                        const int g12 = t / P1, g3 = t % P1;
+                        T v = 0;
 #pragma unroll
-                    for (int ab3 = 0; ab3 < P2; ++ab3) {
-                        v += s_pp[2][ab3 * P1 + g3] * s_r[0][g12 * P2 + ab3];
-                        if (STIFF) v += s_pp[2][P2 * P1 + ab3 * P1 + g3] * s_r[1][g12 * P2 + ab3];
+                        for (int bb3 = 0; bb3 < P1; ++bb3) {
+                            v += s_pz[buf][(a3 * P1 + bb3) * P1 + g3] * s_r[0][g12 * P1 + bb3];
+                            if (STIFF) v += s_pz[buf][P2 * P1 + (a3 * P1 + bb3) * P1 + g3] * s_r[1][g12 * P1 + bb3];
+                        }
+                        dk[oct0 + (int64_t)cell * NP + t] += w * v;
                     }
-                    const int64_t pt = (int64_t)cell * NP + t;
-                    const T w = (T)R.oct_w[pt];
-                    if (w != (T)0) dk[oct0 + pt] += w * v;
+                    buf ^= 1;
                 }
                 __syncthreads();
             }

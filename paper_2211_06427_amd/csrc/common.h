@@ -55,6 +55,7 @@ struct DevRules {
     const float* dwq_Wt32;
     // element Gauss blocks
     const int32_t* elem_block;          // element -> block or -1
+    const int32_t* blk_slot;            // [block][(p+1)^3] canonical kappa slot of each Gauss point
     // octree
     const int32_t* cut_elems;           // lexicographic element index of each cut element
     const int32_t* cell_begin;          // (n_cut_elems + 1)

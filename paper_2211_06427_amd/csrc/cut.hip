@@ -39,6 +39,7 @@ k_cut_remainder(DevRules R, const int32_t* __restrict__ box, const T* __restrict
     __shared__ T s_w[NWAVE][3][2][P1 * P1];          // [dir][a][k][g]
     __shared__ T s_t1[NWAVE][2][NP];
     __shared__ T s_t2[NWAVE][2][NP];
+    __shared__ int s_rem[NP], s_nrem;
     const int64_t cr = blockIdx.x;
     const int ra = R.cut_rows[cr];
     int I[3];
@@ -59,13 +60,22 @@ k_cut_remainder(DevRules R, const int32_t* __restrict__ box, const T* __restrict
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     const int n2 = hi[1] - lo[1] + 1, n3 = hi[2] - lo[2] + 1;
     const int ne = (hi[0] - lo[0] + 1) * n2 * n3;
-    for (int k = wave; k < ne; k += NWAVE) {
+    // compact list of this row's remainder elements (interior, outside the DWQ box)
+    if (threadIdx.x == 0) s_nrem = 0;
+    __syncthreads();
+    for (int k = threadIdx.x; k < ne; k += 256) {
+        const int e0 = lo[0] + k / (n2 * n3), e1 = lo[1] + (k / n3) % n2, e2 = lo[2] + k % n3;
+        const int64_t eid = ((int64_t)e0 * R.nel[1] + e1) * R.nel[2] + e2;
+        const bool inbox = has_box && e0 >= blo[0] && e0 <= bhi[0] && e1 >= blo[1] && e1 <= bhi[1] && e2 >= blo[2] &&
+                           e2 <= bhi[2];
+        if (R.ecls[eid] == CLS_IN && !inbox) s_rem[atomicAdd(&s_nrem, 1)] = k;
+    }
+    __syncthreads();
+    const int nrem = s_nrem;
+    for (int r = wave; r < nrem; r += NWAVE) {
+        const int k = s_rem[r];
         const int e[3] = {lo[0] + k / (n2 * n3), lo[1] + (k / n3) % n2, lo[2] + k % n3};
         const int64_t eid = ((int64_t)e[0] * R.nel[1] + e[1]) * R.nel[2] + e[2];
-        if (R.ecls[eid] != CLS_IN) continue;
-        if (has_box && e[0] >= blo[0] && e[0] <= bhi[0] && e[1] >= blo[1] && e[1] <= bhi[1] && e[2] >= blo[2] &&
-            e[2] <= bhi[2])
-            continue;
         // W_d[a][k][g] = omega_g (h/2) B_{I_d}^(a)(y_g) B_{e_d+k}^(a)(y_g)
         for (int t = lane; t < 3 * 2 * P1 * P1; t += 64) {
             const int d = t / (2 * P1 * P1), a = (t / (P1 * P1)) % 2, kk = (t / P1) % P1, g = t % P1;
@@ -74,10 +84,8 @@ k_cut_remainder(DevRules R, const int32_t* __restrict__ box, const T* __restrict
             const double om = R.gw[g] * R.h[d] * 0.5;
             s_w[wave][d][a][kk * P1 + g] = (T)(om * tab[y * P1 + (I[d] - e[d])] * tab[y * P1 + kk]);
         }
-        for (int t = lane; t < NP; t += 64) {
-            const int g1 = t / (P1 * P1), g2 = (t / P1) % P1, g3 = t % P1;
-            s_kap[wave][t] = kappa[slot_of(R, e[0] * P1 + g1, e[1] * P1 + g2, e[2] * P1 + g3)];
-        }
+        const int32_t* bs = R.blk_slot + (int64_t)R.elem_block[eid] * NP;
+        for (int t = lane; t < NP; t += 64) s_kap[wave][t] = kappa[bs[t]];
         wave_sync();
         for (int t = lane; t < NP; t += 64) {          // T1[v][g1][g2][k3]
             const int g12 = t / P1, k3 = t % P1;
@@ -139,191 +147,197 @@ template <int P> struct OctCfg {
     static constexpr int NT = ((NP + 63) / 64) * 64;
     static constexpr int AG = P <= 4 ? P1 : (P == 5 ? 3 : 4);       // a1 per workgroup
     static constexpr int NAG = (P1 + AG - 1) / AG;
-    static constexpr int KA = (P2 * P2 + NT - 1) / NT;               // stage-A items per thread
-    static constexpr int KB = (P1 * P1 * P2 + NT - 1) / NT;          // stage-B items per thread
 };
 
 template <typename T> __device__ inline const T* oct_tab(const DevRules& R, int d);
 template <> __device__ inline const double* oct_tab<double>(const DevRules& R, int d) { return R.oct_pp64[d]; }
 template <> __device__ inline const float* oct_tab<float>(const DevRules& R, int d) { return R.oct_pp32[d]; }
 
-// Leaves are visited in the per-element sorted order: leaves with the same x-interval are
-// contiguous (one x-group), and inside an x-group leaves with the same y-interval are
-// contiguous (one column).  Stage A (direction 3) runs per leaf and accumulates over the
-// column, stage B (direction 2) runs once per column and accumulates over the x-group,
-// stage C (direction 1) runs once per x-group: each stage is applied to the sum of the
-// partial results that share its 1D basis products.
+// One workgroup per (cut element, a3, group of a1), (a1, a2, a3) the local index of the test
+// function on the element.  With a3 fixed, the direction-3 stage per leaf is
+// P1[g1 g2][b3] = sum_g3 pz[a3 b3][g3] wk[g1 g2 g3].  Leaves are visited in the per-element
+// sorted order: leaves with the same x-interval are contiguous (x-group), and inside an
+// x-group leaves with the same y-interval are contiguous (column).  The direction-3 stage
+// accumulates over a column, the direction-2 stage runs once per column and accumulates
+// over the x-group, the direction-1 stage runs once per x-group.
 template <typename T, int P, int WHICH>
 __global__ void __launch_bounds__(OctCfg<P>::NT)
 k_cut_octree(DevRules R, const int32_t* __restrict__ act2cut, const T* __restrict__ kappa, T* __restrict__ vm,
              T* __restrict__ vk) {
     using C = OctCfg<P>;
     constexpr int P1 = C::P1, NP = C::NP, P2 = C::P2, AG = C::AG, M = 2 * P + 1, NT = C::NT;
-    constexpr int KA = C::KA, KB = C::KB;
+    constexpr int NPP = 2 * P2 * P1, KP = (NPP + NT - 1) / NT, MAXC = 512;
     constexpr bool MASS = (WHICH & 1) != 0, STIFF = (WHICH & 2) != 0;
-    __shared__ T s_wk[NP];
-    __shared__ T s_pp[3][2 * P2 * P1];                  // x-group, column, leaf products
-    __shared__ T s_p1[2][P2 * P2];                      // column result [v][g1 g2][a3 b3]
-    __shared__ T s_p2[2][P1 * P1 * P2];                 // x-group result [v][g1][b2][a3 b3]
+    __shared__ int s_cell[MAXC], s_key[MAXC];          // this chunk of the sorted leaves
+    __shared__ T s_wk[2][NP];                           // weight * kappa, double buffered
+    __shared__ T s_pz[2][NPP];                          // direction-3 products, double buffered
+    __shared__ T s_py[NPP], s_px[NPP];                  // column / x-group products
+    __shared__ T s_p1[2][P2 * P1];                      // column result [v][g1 g2][b3]
+    __shared__ T s_p2[2][P1 * NP];                      // x-group result [v][g1][a2 b2 b3]
     const int ce = blockIdx.x / (P1 * C::NAG);
-    const int a2 = (blockIdx.x / C::NAG) % P1;
+    const int a3 = (blockIdx.x / C::NAG) % P1;
     const int ag0 = (blockIdx.x % C::NAG) * AG;
     const int64_t eid = R.cut_elems[ce];
     int e[3];
     unlex3i(eid, R.nel, e);
     const int t = threadIdx.x;
     const bool own = t < NP;
-    const int b2 = t / P2, a3 = (t / P1) % P1, b3 = t % P1;   // stage-C column c2 = (b2, a3, b3)
-    T accA[2][KA], accB[2][KB], accm[AG][P1], acck[AG][P1];
+    // stage C column c2 = t = (a2, b2, b3); stage A item (g1 g2, b3) = t; stage B item (g1, a2, b3)
+    const int a2 = t / P2, b2 = (t / P1) % P1, b3 = t % P1;
+    const int g12A = t / P1;
+    const int g1B = t / P2, a2B = (t / P1) % P1;
+    T accA0 = 0, accA1 = 0, accB[2][P1], accm[AG][P1], acck[AG][P1];
 #pragma unroll
     for (int i = 0; i < AG; ++i)
 #pragma unroll
         for (int j = 0; j < P1; ++j) { accm[i][j] = 0; acck[i][j] = 0; }
     const int64_t oct0 = R.n_grid + R.n_block;
     const int cb = R.cell_begin[ce], cend = R.cell_begin[ce + 1];
-    // software pipeline: the next leaf's weight * kappa (one point per thread), key and its
-    // direction-3 basis products are loaded while the current leaf is contracted
-    constexpr int NPP = 2 * P2 * P1, KP = (NPP + NT - 1) / NT;
     const int ni = (2 << R.levels) - 1;
-    const T* tab[3] = {oct_tab<T>(R, 0) + (int64_t)e[0] * ni * NPP, oct_tab<T>(R, 1) + (int64_t)e[1] * ni * NPP,
-                       oct_tab<T>(R, 2) + (int64_t)e[2] * ni * NPP};
-    auto ivl = [](int key, int d) { const int dep = key & 7; return (1 << dep) - 1 + ((key >> (3 + 6 * d)) & 63); };
-    int cell_n = cb < cend ? R.cell_perm[cb] : 0;
-    int key_n = cb < cend ? R.cell_key[cell_n] : 0;
-    T wk_n = (own && cb < cend) ? (T)R.oct_w[(int64_t)cell_n * NP + t] * kappa[oct0 + (int64_t)cell_n * NP + t] : (T)0;
-    T pz_n[KP];
-#pragma unroll
-    for (int i = 0; i < KP; ++i) {
-        const int j = t + i * NT;
-        pz_n[i] = (cb < cend && j < NPP) ? tab[2][(int64_t)ivl(key_n, 2) * NPP + j] : (T)0;
-    }
-    int kprev = -1;
-    for (int k = cb; k < cend; ++k) {
-        const int cell = cell_n, key = key_n;
-        const T wk = wk_n;
-        T pz[KP];
-#pragma unroll
-        for (int i = 0; i < KP; ++i) pz[i] = pz_n[i];
-        if (k + 1 < cend) {
-            cell_n = R.cell_perm[k + 1];
-            key_n = R.cell_key[cell_n];
-            if (own) wk_n = (T)R.oct_w[(int64_t)cell_n * NP + t] * kappa[oct0 + (int64_t)cell_n * NP + t];
+    const T* tx = oct_tab<T>(R, 0) + (int64_t)e[0] * ni * NPP;
+    const T* ty = oct_tab<T>(R, 1) + (int64_t)e[1] * ni * NPP;
+    const T* tz = oct_tab<T>(R, 2) + (int64_t)e[2] * ni * NPP;
+    auto ivl = [](int key, int d) { return (1 << (key & 7)) - 1 + ((key >> (3 + 6 * d)) & 63); };
+    const int xmask = (1 << 9) - 1, cmask = (1 << 15) - 1;
+    int kprev = -1, buf = 0;
+    for (int c0 = cb; c0 < cend; c0 += MAXC) {
+        const int nc = cend - c0 < MAXC ? cend - c0 : MAXC;
+        __syncthreads();
+        for (int j = t; j < nc; j += NT) {
+            const int cell = R.cell_perm[c0 + j];
+            s_cell[j] = cell;
+            s_key[j] = R.cell_key[cell];
+        }
+        const int key_after = c0 + nc < cend ? R.cell_key[R.cell_perm[c0 + nc]] : -1;
+        __syncthreads();
+        // software pipeline: the next leaf's data is loaded while the current one is contracted
+        T wk_n = 0, pz_n[KP], py_n[KP], px_n[KP];
+        {
+            const int cell = s_cell[0], key = s_key[0];
+            if (own) wk_n = (T)R.oct_w[(int64_t)cell * NP + t] * kappa[oct0 + (int64_t)cell * NP + t];
 #pragma unroll
             for (int i = 0; i < KP; ++i) {
-                const int j = t + i * NT;
-                if (j < NPP) pz_n[i] = tab[2][(int64_t)ivl(key_n, 2) * NPP + j];
+                const int q = t + i * NT;
+                pz_n[i] = q < NPP ? tz[(int64_t)ivl(key, 2) * NPP + q] : (T)0;
+                py_n[i] = q < NPP ? ty[(int64_t)ivl(key, 1) * NPP + q] : (T)0;
+                px_n[i] = q < NPP ? tx[(int64_t)ivl(key, 0) * NPP + q] : (T)0;
             }
         }
-        const int knext = k + 1 < cend ? key_n : -1;
-        const int xmask = (1 << 9) - 1, cmask = (1 << 15) - 1;
-        const bool new_x = kprev < 0 || (key & xmask) != (kprev & xmask);
-        const bool new_col = kprev < 0 || (key & cmask) != (kprev & cmask);
-        const bool end_col = knext < 0 || (key & cmask) != (knext & cmask);
-        const bool end_x = knext < 0 || (key & xmask) != (knext & xmask);
-        kprev = key;
-        if (new_col) {
+        for (int j = 0; j < nc; ++j) {
+            const int key = s_key[j];
+            const int knext = j + 1 < nc ? s_key[j + 1] : key_after;
+            const bool new_x = kprev < 0 || (key & xmask) != (kprev & xmask);
+            const bool new_col = kprev < 0 || (key & cmask) != (kprev & cmask);
+            const bool end_col = knext < 0 || (key & cmask) != (knext & cmask);
+            const bool end_x = knext < 0 || (key & xmask) != (knext & xmask);
+            kprev = key;
+            if (new_col) { accA0 = 0; accA1 = 0; }
+            if (new_x) {
 #pragma unroll
-            for (int i = 0; i < KA; ++i) { accA[0][i] = 0; accA[1][i] = 0; }
-        }
-        if (new_x) {
-#pragma unroll
-            for (int i = 0; i < KB; ++i) { accB[0][i] = 0; accB[1][i] = 0; }
-        }
-        if (own) s_wk[t] = wk;
-#pragma unroll
-        for (int i = 0; i < KP; ++i) {
-            const int j = t + i * NT;
-            if (j < NPP) {
-                s_pp[2][j] = pz[i];
-                if (new_col) s_pp[1][j] = tab[1][(int64_t)ivl(key, 1) * NPP + j];
-                if (new_x) s_pp[0][j] = tab[0][(int64_t)ivl(key, 0) * NPP + j];
+                for (int b = 0; b < P1; ++b) { accB[0][b] = 0; accB[1][b] = 0; }
             }
-        }
-        __syncthreads();
-        // stage A: accA[v][g1 g2][a3 b3] += sum_g3 pp3[v][a3 b3][g3] wk[g1 g2 g3]
+            if (own) s_wk[buf][t] = wk_n;
 #pragma unroll
-        for (int i = 0; i < KA; ++i) {
-            const int it = t + i * NT;
-            if (it < P2 * P2) {
-                const int g12 = it / P2, ab3 = it % P2;
-                T s0 = 0, s1 = 0;
-#pragma unroll
-                for (int g3 = 0; g3 < P1; ++g3) {
-                    const T w = s_wk[g12 * P1 + g3];
-                    s0 += s_pp[2][ab3 * P1 + g3] * w;
-                    if (STIFF) s1 += s_pp[2][P2 * P1 + ab3 * P1 + g3] * w;
+            for (int i = 0; i < KP; ++i) {
+                const int q = t + i * NT;
+                if (q < NPP) {
+                    s_pz[buf][q] = pz_n[i];
+                    if (new_col) s_py[q] = py_n[i];
+                    if (new_x) s_px[q] = px_n[i];
                 }
-                accA[0][i] += s0;
-                accA[1][i] += s1;
             }
-        }
-        if (end_col) {
+            if (j + 1 < nc) {
+                const int cell = s_cell[j + 1];
+                if (own) wk_n = (T)R.oct_w[(int64_t)cell * NP + t] * kappa[oct0 + (int64_t)cell * NP + t];
+                const bool nc_next = (knext & cmask) != (key & cmask), nx_next = (knext & xmask) != (key & xmask);
 #pragma unroll
-            for (int i = 0; i < KA; ++i) {
-                const int it = t + i * NT;
-                if (it < P2 * P2) {
-                    s_p1[0][it] = accA[0][i];
-                    if (STIFF) s_p1[1][it] = accA[1][i];
+                for (int i = 0; i < KP; ++i) {
+                    const int q = t + i * NT;
+                    if (q < NPP) {
+                        pz_n[i] = tz[(int64_t)ivl(knext, 2) * NPP + q];
+                        if (nc_next) py_n[i] = ty[(int64_t)ivl(knext, 1) * NPP + q];
+                        if (nx_next) px_n[i] = tx[(int64_t)ivl(knext, 0) * NPP + q];
+                    }
                 }
             }
             __syncthreads();
-            // stage B: accB[g1][b2][a3 b3] += sum_g2 pp2[0][a2 b2][g2] P1_0 (+ stiffness terms)
+            // stage A: P1[v][g1 g2][b3] += sum_g3 pz[v][a3 b3][g3] wk[g1 g2 g3]
+            if (t < P2 * P1) {
 #pragma unroll
-            for (int i = 0; i < KB; ++i) {
-                const int it = t + i * NT;
-                if (it < P1 * P1 * P2) {
-                    const int g1 = it / (P1 * P2), bb2 = (it / P2) % P1, ab3 = it % P2;
-                    T s0 = 0, ss = 0;
-#pragma unroll
-                    for (int g2 = 0; g2 < P1; ++g2) {
-                        const T v0 = s_p1[0][(g1 * P1 + g2) * P2 + ab3];
-                        const T w0 = s_pp[1][(a2 * P1 + bb2) * P1 + g2];
-                        s0 += w0 * v0;
-                        if (STIFF) ss += s_pp[1][P2 * P1 + (a2 * P1 + bb2) * P1 + g2] * v0 + w0 * s_p1[1][(g1 * P1 + g2) * P2 + ab3];
-                    }
-                    accB[0][i] += s0;
-                    accB[1][i] += ss;
+                for (int g3 = 0; g3 < P1; ++g3) {
+                    const T w = s_wk[buf][g12A * P1 + g3];
+                    accA0 += s_pz[buf][(a3 * P1 + b3) * P1 + g3] * w;
+                    if (STIFF) accA1 += s_pz[buf][P2 * P1 + (a3 * P1 + b3) * P1 + g3] * w;
                 }
             }
-            if (end_x) {
-#pragma unroll
-                for (int i = 0; i < KB; ++i) {
-                    const int it = t + i * NT;
-                    if (it < P1 * P1 * P2) {
-                        s_p2[0][it] = accB[0][i];
-                        if (STIFF) s_p2[1][it] = accB[1][i];
-                    }
+            buf ^= 1;
+            if (end_col) {
+                if (t < P2 * P1) {
+                    s_p1[0][t] = accA0;
+                    if (STIFF) s_p1[1][t] = accA1;
                 }
                 __syncthreads();
-                // stage C: acc[a1][b1] += sum_g1 pp1[.][a1 b1][g1] P2[.][g1][c2]
+                // stage B: P2[g1][a2 b2][b3] += sum_g2 py[0][a2 b2][g2] P1_0[g1 g2][b3] (+ stiffness)
                 if (own) {
-                    T v0[P1], vs[P1];
+                    T u0[P1], u1[P1];
 #pragma unroll
-                    for (int g1 = 0; g1 < P1; ++g1) {
-                        v0[g1] = s_p2[0][g1 * P1 * P2 + t];
-                        vs[g1] = STIFF ? s_p2[1][g1 * P1 * P2 + t] : (T)0;
+                    for (int g2 = 0; g2 < P1; ++g2) {
+                        u0[g2] = s_p1[0][(g1B * P1 + g2) * P1 + b3];
+                        u1[g2] = STIFF ? s_p1[1][(g1B * P1 + g2) * P1 + b3] : (T)0;
                     }
 #pragma unroll
-                    for (int i = 0; i < AG; ++i) {
-                        const int a1 = ag0 + i;
-                        if (a1 >= P1) break;
+                    for (int bb2 = 0; bb2 < P1; ++bb2) {
+                        T s0 = 0, ss = 0;
 #pragma unroll
-                        for (int b1 = 0; b1 < P1; ++b1) {
-                            T sm = 0, sk = 0;
+                        for (int g2 = 0; g2 < P1; ++g2) {
+                            const T w0 = s_py[(a2B * P1 + bb2) * P1 + g2];
+                            s0 += w0 * u0[g2];
+                            if (STIFF) ss += s_py[P2 * P1 + (a2B * P1 + bb2) * P1 + g2] * u0[g2] + w0 * u1[g2];
+                        }
+                        accB[0][bb2] += s0;
+                        accB[1][bb2] += ss;
+                    }
+                }
+                if (end_x) {
+                    if (own) {
 #pragma unroll
-                            for (int g1 = 0; g1 < P1; ++g1) {
-                                const T w0 = s_pp[0][(a1 * P1 + b1) * P1 + g1];
-                                sm += w0 * v0[g1];
-                                if (STIFF) sk += s_pp[0][P2 * P1 + (a1 * P1 + b1) * P1 + g1] * v0[g1] + w0 * vs[g1];
+                        for (int bb2 = 0; bb2 < P1; ++bb2) {
+                            const int c = (a2B * P1 + bb2) * P1 + b3;
+                            s_p2[0][g1B * NP + c] = accB[0][bb2];
+                            if (STIFF) s_p2[1][g1B * NP + c] = accB[1][bb2];
+                        }
+                    }
+                    __syncthreads();
+                    // stage C: acc[a1][b1] += sum_g1 px[.][a1 b1][g1] P2[.][g1][c2]
+                    if (own) {
+                        T v0[P1], vs[P1];
+#pragma unroll
+                        for (int g1 = 0; g1 < P1; ++g1) {
+                            v0[g1] = s_p2[0][g1 * NP + t];
+                            vs[g1] = STIFF ? s_p2[1][g1 * NP + t] : (T)0;
+                        }
+#pragma unroll
+                        for (int i = 0; i < AG; ++i) {
+                            const int a1 = ag0 + i;
+                            if (a1 >= P1) break;
+#pragma unroll
+                            for (int b1 = 0; b1 < P1; ++b1) {
+                                T sm = 0, sk = 0;
+#pragma unroll
+                                for (int g1 = 0; g1 < P1; ++g1) {
+                                    const T w0 = s_px[(a1 * P1 + b1) * P1 + g1];
+                                    sm += w0 * v0[g1];
+                                    if (STIFF) sk += s_px[P2 * P1 + (a1 * P1 + b1) * P1 + g1] * v0[g1] + w0 * vs[g1];
+                                }
+                                accm[i][b1] += sm;
+                                acck[i][b1] += sk;
                             }
-                            accm[i][b1] += sm;
-                            acck[i][b1] += sk;
                         }
                     }
                 }
+                __syncthreads();       // s_py / s_px / s_p1 / s_p2 are rewritten by the next column
             }
         }
-        __syncthreads();
     }
     if (!own) return;
     // scatter: row a = e + (a1, a2, a3), column b = e + (b1, b2, b3)

@@ -826,6 +826,19 @@ __global__ void k_octree_weights(DevRules R, const double* gxi, const double* gw
     xyz[s * 3 + 0] = x[0]; xyz[s * 3 + 1] = x[1]; xyz[s * 3 + 2] = x[2];
 }
 
+// canonical slot of every Gauss point of every block element (grid slot when the point is a
+// WQ grid point, else the block entry)
+__global__ void k_blk_slot(DevRules R, const int32_t* block_elems, int64_t nb, int32_t* out) {
+    const int p1 = R.p + 1, npe = p1 * p1 * p1;
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= nb * npe) return;
+    const int64_t eid = block_elems[id / npe];
+    const int pt = (int)(id % npe);
+    const int e3 = (int)(eid % R.nel[2]), e2 = (int)((eid / R.nel[2]) % R.nel[1]);
+    const int e1 = (int)(eid / ((int64_t)R.nel[1] * R.nel[2]));
+    out[id] = (int32_t)slot_of(R, e1 * p1 + pt / (p1 * p1), e2 * p1 + (pt / p1) % p1, e3 * p1 + pt % p1);
+}
+
 // grid and block slot coordinates
 __global__ void k_slot_xyz(DevRules R, const int32_t* block_elems, double* xyz) {
     int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1119,6 +1132,12 @@ int build_rules(const wq_mesh* mesh, const wq_levelset* ls, const wq_options* op
         R.oct_w = ow;
         H->kappa_xyz = xyz;
         hipLaunchKernelGGL(k_slot_xyz, grid_for(R.n_grid + R.n_block), dim3(256), 0, stream, R, H->block_elems, xyz);
+        if (R.n_kappa >= ((int64_t)1 << 31)) return B.fail_msg(WQ_EUNSUPPORTED, "too many kappa slots (%lld)", (long long)R.n_kappa);
+        int32_t* bslot = B.keep<int32_t>(R.n_block > 0 ? R.n_block : 1);
+        if (!bslot) return B.fail();
+        if (R.n_block > 0)
+            hipLaunchKernelGGL(k_blk_slot, grid_for(R.n_block), dim3(256), 0, stream, R, H->block_elems, H->n_block_elems, bslot);
+        R.blk_slot = bslot;
         if (H->n_oct > 0)
             hipLaunchKernelGGL(k_octree_weights, grid_for(H->n_oct), dim3(256), 0, stream, R, gxi, gw, R.cell_lo, R.cell_depth,
                                H->cell_cut, ow, xyz);
