@@ -48,6 +48,11 @@ typedef enum { WQ_F64 = 0, WQ_F32 = 1 } wq_dtype;
 
 enum { WQ_MASS = 1u, WQ_STIFF = 2u };   /* 'which' bit mask */
 
+/* Optional part bits of cut_assemble's 'which': run only the element Gauss remainder
+ * and/or only the octree part (neither bit set: both).  Each part accumulates on its
+ * own, so the two calls in sequence equal one call with both parts. */
+enum { WQ_CUT_REMAINDER = 4u, WQ_CUT_OCTREE = 8u };
+
 /* Background mesh: nel[d] uniform elements on [lo[d], hi[d]], degree 1 <= p <= 6, open
  * knot vectors with maximal smoothness C^{p-1} (Section 1, Section 2). */
 typedef struct {
@@ -88,6 +93,9 @@ typedef struct {
     int64_t n_cut_elems;     /* cut elements */
     int64_t n_cells;         /* octree leaves */
     int64_t n_line_blocks;   /* interior row blocks of the fast kernel */
+    int64_t n_oct_xgroups;   /* octree leaves grouped by (cut element, depth, x offset) */
+    int64_t n_oct_columns;   /* octree leaves grouped by (cut element, depth, x and y offsets) */
+    int64_t n_rem_pairs;     /* (cut row, element Gauss remainder element) pairs */
     int32_t grid_dims[3];    /* |X_d| */
     int32_t nfun[3];         /* functions per direction, nel[d] + p */
     const int64_t* row_ptr;        /* (n_active+1) CSR row pointer */
@@ -125,7 +133,8 @@ int wq_assemble_rows(const wq_rules* rules, int dtype, uint32_t which, const voi
 
 /* Cut part of Eq. (1): element Gauss on the interior elements of each cut row's support
  * outside its DWQ box, and octree Gauss on every cut element.  ACCUMULATES into the
- * values (call after wq_assemble_rows on the same stream). */
+ * values (call after wq_assemble_rows on the same stream).  'which' may add the part bits
+ * WQ_CUT_REMAINDER / WQ_CUT_OCTREE to run one part only. */
 int cut_assemble(const wq_rules* rules, int dtype, uint32_t which, const void* kappa,
                  void* vals_mass, void* vals_stiff, void* stream);
 

@@ -9,6 +9,7 @@ LIB_PATH = os.path.join(HERE, "libwqfd.so")
 
 WQ_F64, WQ_F32 = 0, 1
 WQ_MASS, WQ_STIFF = 1, 2
+WQ_CUT_REMAINDER, WQ_CUT_OCTREE = 4, 8
 STATUS = {0: "WQ_OK", -1: "WQ_EINVAL", -2: "WQ_ENOMEM", -3: "WQ_EHIP", -4: "WQ_ESINGULAR", -5: "WQ_EUNSUPPORTED"}
 
 EXPORTS = ["wq_build_rules", "wq_rules_info_get", "wq_assemble_rows", "cut_assemble", "wq_assemble_adjoint",
@@ -31,7 +32,8 @@ class WqOptions(C.Structure):
 class WqRulesInfo(C.Structure):
     _fields_ = [(k, C.c_int64) for k in ("n_active", "nnz", "n_rows_interior", "n_rows_cut", "n_rows_split",
                                          "n_dwq_rules", "n_kappa", "n_grid", "n_block", "n_octree",
-                                         "n_block_elems", "n_cut_elems", "n_cells", "n_line_blocks")] + [
+                                         "n_block_elems", "n_cut_elems", "n_cells", "n_line_blocks",
+                                         "n_oct_xgroups", "n_oct_columns", "n_rem_pairs")] + [
         ("grid_dims", C.c_int32 * 3), ("nfun", C.c_int32 * 3),
         ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p), ("active_to_lex", C.c_void_p),
         ("kappa_xyz", C.c_void_p), ("octree_w", C.c_void_p), ("block_elems", C.c_void_p),

@@ -59,7 +59,8 @@ class Rules:
         L.check(lib.wq_rules_info_get(h, C.byref(info)))
         self._info = info
         for k in ("n_active", "nnz", "n_rows_interior", "n_rows_cut", "n_rows_split", "n_dwq_rules", "n_kappa",
-                  "n_grid", "n_block", "n_octree", "n_block_elems", "n_cut_elems", "n_cells", "n_line_blocks"):
+                  "n_grid", "n_block", "n_octree", "n_block_elems", "n_cut_elems", "n_cells", "n_line_blocks",
+                  "n_oct_xgroups", "n_oct_columns", "n_rem_pairs"):
             setattr(self, k, int(getattr(info, k)))
         self.grid_dims = tuple(info.grid_dims)
         self.nfun = tuple(info.nfun)
@@ -135,10 +136,11 @@ class Rules:
             (L.WQ_STIFF if vals_stiff is not None else 0)
         self._call(L.load().wq_assemble_rows, kappa, vals_mass, vals_stiff, which)
 
-    def cut_assemble(self, kappa, vals_mass=None, vals_stiff=None, which=None):
+    def cut_assemble(self, kappa, vals_mass=None, vals_stiff=None, which=None, parts=0):
+        """Accumulates the cut part; parts = WQ_CUT_REMAINDER and/or WQ_CUT_OCTREE (0: both)."""
         which = which if which is not None else (L.WQ_MASS if vals_mass is not None else 0) | \
             (L.WQ_STIFF if vals_stiff is not None else 0)
-        self._call(L.load().cut_assemble, kappa, vals_mass, vals_stiff, which)
+        self._call(L.load().cut_assemble, kappa, vals_mass, vals_stiff, which | parts)
 
     def assemble(self, kappa, which=L.WQ_MASS | L.WQ_STIFF):
         """Whole matrices: rows, then the cut part. Returns (M values or None, K values or None)."""

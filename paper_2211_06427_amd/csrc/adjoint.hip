@@ -282,108 +282,108 @@ k_adj_cut(DevRules R, const T* __restrict__ gm, const T* __restrict__ gk, T* __r
 // ----------------------------------------------------------------------------------------
 // remainder elements (element Gauss) of cut rows
 // ----------------------------------------------------------------------------------------
+template <typename T> __device__ inline const T* rem_tab_a(const DevRules& R, int d);
+template <> __device__ inline const double* rem_tab_a<double>(const DevRules& R, int d) { return R.rem_w64[d]; }
+template <> __device__ inline const float* rem_tab_a<float>(const DevRules& R, int d) { return R.rem_w32[d]; }
+
+template <int P> struct RemAdjCfg {
+    static constexpr int P1 = P + 1, NP = P1 * P1 * P1, P2 = P1 * P1;
+    static constexpr int SLOT = ((NP + 63) / 64) * 64;         // threads per element in flight
+    static constexpr int NT = SLOT >= 256 ? SLOT : 256;
+    static constexpr int NSLOT = NT / SLOT;
+};
+
+// One workgroup per cut row; NSLOT remainder elements in flight, one thread per Gauss point
+// (or per intermediate entry) of each, transposed contractions in the order 1, 2, 3.  The
+// row's 1D weights and cotangent block sit in LDS; slot indices are loaded one pass ahead.
 template <typename T, int P, int WHICH>
-__global__ void __launch_bounds__(256)
-k_adj_remainder(DevRules R, const int32_t* __restrict__ box, const T* __restrict__ gm, const T* __restrict__ gk,
-                T* __restrict__ dk) {
-    constexpr int P1 = P + 1, NP = P1 * P1 * P1, M = 2 * P + 1, M3 = M * M * M, NWAVE = 4;
+__global__ void __launch_bounds__(RemAdjCfg<P>::NT)
+k_adj_remainder(DevRules R, const T* __restrict__ gm, const T* __restrict__ gk, T* __restrict__ dk) {
+    using C = RemAdjCfg<P>;
+    constexpr int P1 = C::P1, NP = C::NP, P2 = C::P2, M = 2 * P + 1, M3 = M * M * M, NT = C::NT, SLOT = C::SLOT;
+    constexpr int NSLOT = C::NSLOT;
     constexpr bool MASS = (WHICH & 1) != 0, STIFF = (WHICH & 2) != 0;
     __shared__ T s_g[2][M3];
-    __shared__ T s_w[NWAVE][3][2][P1 * P1];
-    __shared__ T s_c[NWAVE][2][NP];
-    __shared__ T s_b[NWAVE][2][NP];
-    __shared__ int s_rem[NP], s_nrem;
+    __shared__ T s_wt[3][P1][2 * P2];                 // [d][I_d - e_d][a][k][g]
+    __shared__ T s_c[NSLOT][2][NP];
+    __shared__ T s_b[NSLOT][2][NP];
+    __shared__ int2 s_list[NP];
     const int64_t cr = blockIdx.x;
     const int ra = R.cut_rows[cr];
     int I[3];
     unlex3a(R.act2lex[ra], R.nfun, I);
     const int32_t* pos = R.pos_map + cr * (int64_t)M3;
     const int64_t rb = R.row_ptr[ra];
-    for (int k = threadIdx.x; k < M3; k += 256) {
+    const int t = threadIdx.x;
+    const int l0 = R.rem_ptr[cr], nrem = R.rem_ptr[cr + 1] - l0;
+    if (nrem == 0) return;
+    for (int k = t; k < M3; k += NT) {
         const int o = pos[k];
         s_g[0][k] = (o >= 0 && MASS) ? gm[rb + o] : (T)0;
         s_g[1][k] = (o >= 0 && STIFF) ? gk[rb + o] : (T)0;
     }
-    int lo[3], hi[3], blo[3], bhi[3];
-    const bool has_box = R.split[cr].x >= 0;
-    for (int d = 0; d < 3; ++d) {
-        lo[d] = I[d] - P < 0 ? 0 : I[d] - P;
-        hi[d] = I[d] < R.nel[d] - 1 ? I[d] : R.nel[d] - 1;
-        blo[d] = box[cr * 6 + 2 * d];
-        bhi[d] = box[cr * 6 + 2 * d + 1];
+    for (int q = t; q < 3 * P1 * 2 * P2; q += NT) {
+        const int d = q / (P1 * 2 * P2), kI = (q / (2 * P2)) % P1, rest = q % (2 * P2);
+        const int e = I[d] - kI;
+        s_wt[d][kI][rest] = (e >= 0 && e < R.nel[d]) ? rem_tab_a<T>(R, d)[((int64_t)e * P1 + kI) * 2 * P2 + rest] : (T)0;
     }
+    for (int k = t; k < nrem; k += NT) s_list[k] = R.rem_list[l0 + k];
     __syncthreads();
-    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-    const int n2 = hi[1] - lo[1] + 1, n3 = hi[2] - lo[2] + 1;
-    const int ne = (hi[0] - lo[0] + 1) * n2 * n3;
-    // compact list of this row's remainder elements (interior, outside the DWQ box)
-    if (threadIdx.x == 0) s_nrem = 0;
-    __syncthreads();
-    for (int k = threadIdx.x; k < ne; k += 256) {
-        const int e0 = lo[0] + k / (n2 * n3), e1 = lo[1] + (k / n3) % n2, e2 = lo[2] + k % n3;
-        const int64_t eid = ((int64_t)e0 * R.nel[1] + e1) * R.nel[2] + e2;
-        const bool inbox = has_box && e0 >= blo[0] && e0 <= bhi[0] && e1 >= blo[1] && e1 <= bhi[1] && e2 >= blo[2] &&
-                           e2 <= bhi[2];
-        if (R.ecls[eid] == CLS_IN && !inbox) s_rem[atomicAdd(&s_nrem, 1)] = k;
-    }
-    __syncthreads();
-    const int nrem = s_nrem;
-    for (int r = wave; r < nrem; r += NWAVE) {
-        const int k = s_rem[r];
-        const int e[3] = {lo[0] + k / (n2 * n3), lo[1] + (k / n3) % n2, lo[2] + k % n3};
-        const int64_t eid = ((int64_t)e[0] * R.nel[1] + e[1]) * R.nel[2] + e[2];
-        for (int t = lane; t < 3 * 2 * P1 * P1; t += 64) {
-            const int d = t / (2 * P1 * P1), a = (t / (P1 * P1)) % 2, kk = (t / P1) % P1, g = t % P1;
-            const int64_t y = (int64_t)e[d] * P1 + g;
-            const double* tab = a ? R.dBval[d] : R.Bval[d];
-            const double om = R.gw[g] * R.h[d] * 0.5;
-            s_w[wave][d][a][kk * P1 + g] = (T)(om * tab[y * P1 + (I[d] - e[d])] * tab[y * P1 + kk]);
-        }
-        wave_sync_a();
-        // 1^T: C[v][g1][k2][k3] = sum_k1 W1[k1][g1] G[k1][k2][k3]
-        for (int t = lane; t < NP; t += 64) {
-            const int g1 = t / (P1 * P1), k23 = t % (P1 * P1);
-            const int k2 = k23 / P1, k3 = k23 % P1;
+    const int sl = t / SLOT, u = t % SLOT;
+    const bool act_u = u < NP;
+    const int d1 = u / P2, d2 = (u / P1) % P1, d3 = u % P1;       // u = (d1, d2, d3)
+    int bs_c = (act_u && sl < nrem) ? R.blk_slot[(int64_t)s_list[sl].y * NP + u] : 0;
+    for (int r0 = 0; r0 < nrem; r0 += NSLOT) {
+        const int r = r0 + sl;
+        const bool active = r < nrem;
+        const int bs = bs_c;
+        bs_c = (act_u && r + NSLOT < nrem) ? R.blk_slot[(int64_t)s_list[r + NSLOT].y * NP + u] : 0;
+        const int pk = active ? s_list[r].x : 0;
+        const int kI0 = pk & 15, kI1 = (pk >> 4) & 15, kI2 = (pk >> 8) & 15;
+        const T* W1 = s_wt[0][kI0];
+        const T* W2 = s_wt[1][kI1];
+        const T* W3 = s_wt[2][kI2];
+        if (active && act_u) {      // 1^T: C[v][g1][k2][k3] = sum_k1 W1[k1][g1] G[k1][k2][k3], u = (g1, k2, k3)
             T c0 = 0, c1 = 0;
+            const int j23 = (d2 - kI1 + P) * M + (d3 - kI2 + P);
+#pragma unroll
             for (int k1 = 0; k1 < P1; ++k1) {
-                const int jj = ((e[0] + k1 - I[0] + P) * M + (e[1] + k2 - I[1] + P)) * M + (e[2] + k3 - I[2] + P);
-                const T w0 = s_w[wave][0][0][k1 * P1 + g1];
+                const int jj = (k1 - kI0 + P) * M * M + j23;
+                const T w0 = W1[k1 * P1 + d1];
                 if (MASS) c0 += w0 * s_g[0][jj];
-                if (STIFF) { c0 += s_w[wave][0][1][k1 * P1 + g1] * s_g[1][jj]; c1 += w0 * s_g[1][jj]; }
+                if (STIFF) { c0 += W1[P2 + k1 * P1 + d1] * s_g[1][jj]; c1 += w0 * s_g[1][jj]; }
             }
-            s_c[wave][0][t] = c0;
-            if (STIFF) s_c[wave][1][t] = c1;
+            s_c[sl][0][u] = c0;
+            if (STIFF) s_c[sl][1][u] = c1;
         }
-        wave_sync_a();
-        // 2^T: B[v][g1][g2][k3]
-        for (int t = lane; t < NP; t += 64) {
-            const int g1 = t / (P1 * P1), g2 = (t / P1) % P1, k3 = t % P1;
+        __syncthreads();
+        if (active && act_u) {      // 2^T: B[v][g1][g2][k3], u = (g1, g2, k3)
             T b0 = 0, b1 = 0;
+#pragma unroll
             for (int k2 = 0; k2 < P1; ++k2) {
-                const T c0 = s_c[wave][0][(g1 * P1 + k2) * P1 + k3];
-                const T w0 = s_w[wave][1][0][k2 * P1 + g2];
+                const T c0 = s_c[sl][0][(d1 * P1 + k2) * P1 + d3];
+                const T w0 = W2[k2 * P1 + d2];
                 b0 += w0 * c0;
                 if (STIFF) {
-                    const T c1 = s_c[wave][1][(g1 * P1 + k2) * P1 + k3];
-                    b0 += s_w[wave][1][1][k2 * P1 + g2] * c1;
+                    const T c1 = s_c[sl][1][(d1 * P1 + k2) * P1 + d3];
+                    b0 += W2[P2 + k2 * P1 + d2] * c1;
                     b1 += w0 * c1;
                 }
             }
-            s_b[wave][0][t] = b0;
-            if (STIFF) s_b[wave][1][t] = b1;
+            s_b[sl][0][u] = b0;
+            if (STIFF) s_b[sl][1][u] = b1;
         }
-        wave_sync_a();
-        // 3^T: dk(g1, g2, g3)
-        for (int t = lane; t < NP; t += 64) {
-            const int g12 = t / P1, g3 = t % P1;
+        __syncthreads();
+        if (active && act_u) {      // 3^T: dk(g1, g2, g3), u = (g1, g2, g3)
             T v = 0;
+#pragma unroll
             for (int k3 = 0; k3 < P1; ++k3) {
-                v += s_w[wave][2][0][k3 * P1 + g3] * s_b[wave][0][g12 * P1 + k3];
-                if (STIFF) v += s_w[wave][2][1][k3 * P1 + g3] * s_b[wave][1][g12 * P1 + k3];
+                v += W3[k3 * P1 + d3] * s_b[sl][0][(d1 * P1 + d2) * P1 + k3];
+                if (STIFF) v += W3[P2 + k3 * P1 + d3] * s_b[sl][1][(d1 * P1 + d2) * P1 + k3];
             }
-            atomicAdd(&dk[R.blk_slot[(int64_t)R.elem_block[eid] * NP + t]], v);
+            atomicAdd(&dk[bs], v);
         }
-        wave_sync_a();
+        __syncthreads();
     }
 }
 
@@ -587,7 +587,8 @@ static void launch_adj_p(const wq_rules* H, const T* gm, const T* gk, T* dk, hip
     }
     if (R.n_cut > 0) {
         hipLaunchKernelGGL((k_adj_cut<T, P, WHICH>), dim3((unsigned)R.n_cut), dim3(256), 0, s, R, gm, gk, dk);
-        hipLaunchKernelGGL((k_adj_remainder<T, P, WHICH>), dim3((unsigned)R.n_cut), dim3(256), 0, s, R, H->box, gm, gk, dk);
+        hipLaunchKernelGGL((k_adj_remainder<T, P, WHICH>), dim3((unsigned)R.n_cut), dim3(RemAdjCfg<P>::NT), 0, s, R, gm, gk,
+                           dk);
     }
     if (R.n_cut_elems > 0) {
         using C = OctAdjCfg<P>;

@@ -23,10 +23,12 @@ static int check_launch(const char* what) {
 }
 
 static int check_values(const wq_rules* r, int dtype, uint32_t which, const void* kappa, const void* a,
-                        const void* b, const char* what) {
+                        const void* b, const char* what, uint32_t extra_bits = 0) {
     if (!r) return wq_set_error(WQ_EINVAL, "%s: rules handle is NULL", what);
     if (dtype != WQ_F64 && dtype != WQ_F32) return wq_set_error(WQ_EINVAL, "%s: unknown dtype %d", what, dtype);
-    if (which == 0 || (which & ~3u)) return wq_set_error(WQ_EINVAL, "%s: which must be a non-empty subset of MASS|STIFF", what);
+    if ((which & 3u) == 0 || (which & ~(3u | extra_bits)))
+        return wq_set_error(WQ_EINVAL, "%s: which must hold a non-empty subset of MASS|STIFF%s", what,
+                            extra_bits ? " (plus optional part bits)" : "");
     if (!kappa) return wq_set_error(WQ_EINVAL, "%s: kappa is NULL", what);
     if ((which & WQ_MASS) && !a) return wq_set_error(WQ_EINVAL, "%s: mass output requested but pointer is NULL", what);
     if ((which & WQ_STIFF) && !b) return wq_set_error(WQ_EINVAL, "%s: stiffness output requested but pointer is NULL", what);
@@ -84,6 +86,9 @@ int wq_rules_info_get(const wq_rules* r, wq_rules_info* out) {
     out->n_cut_elems = R.n_cut_elems;
     out->n_cells = R.n_cells;
     out->n_line_blocks = R.n_lblocks;
+    out->n_oct_xgroups = r->n_oct_xgroups;
+    out->n_oct_columns = r->n_oct_columns;
+    out->n_rem_pairs = r->n_rem_pairs;
     for (int d = 0; d < 3; ++d) { out->grid_dims[d] = R.nx[d]; out->nfun[d] = R.nfun[d]; }
     out->row_ptr = R.row_ptr;
     out->col_idx = R.col_idx;
@@ -110,13 +115,15 @@ int wq_assemble_rows(const wq_rules* r, int dtype, uint32_t which, const void* k
 }
 
 int cut_assemble(const wq_rules* r, int dtype, uint32_t which, const void* kappa, void* vm, void* vk, void* stream) {
-    int st = check_values(r, dtype, which, kappa, vm, vk, "cut_assemble");
+    int st = check_values(r, dtype, which, kappa, vm, vk, "cut_assemble", WQ_CUT_REMAINDER | WQ_CUT_OCTREE);
     if (st) return st;
     if (r->nnz == 0) return WQ_OK;
+    uint32_t parts = which & (WQ_CUT_REMAINDER | WQ_CUT_OCTREE);
+    if (parts == 0) parts = WQ_CUT_REMAINDER | WQ_CUT_OCTREE;
     if (dtype == WQ_F64)
-        launch_cut<double>(r, which, (const double*)kappa, (double*)vm, (double*)vk, (hipStream_t)stream);
+        launch_cut<double>(r, which & 3u, parts, (const double*)kappa, (double*)vm, (double*)vk, (hipStream_t)stream);
     else
-        launch_cut<float>(r, which, (const float*)kappa, (float*)vm, (float*)vk, (hipStream_t)stream);
+        launch_cut<float>(r, which & 3u, parts, (const float*)kappa, (float*)vm, (float*)vk, (hipStream_t)stream);
     return check_launch("cut_assemble");
 }
 

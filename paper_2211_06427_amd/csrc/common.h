@@ -56,6 +56,10 @@ struct DevRules {
     // element Gauss blocks
     const int32_t* elem_block;          // element -> block or -1
     const int32_t* blk_slot;            // [block][(p+1)^3] canonical kappa slot of each Gauss point
+    const int32_t* rem_ptr;             // [cut row + 1] offsets into rem_list
+    const int2* rem_list;               // remainder elements: (I_d - e_d packed 4 bits/direction, block)
+    const double* rem_w64[3];           // per direction: [e][kI][a][k][g] element-Gauss test x trial weights
+    const float* rem_w32[3];
     // octree
     const int32_t* cut_elems;           // lexicographic element index of each cut element
     const int32_t* cell_begin;          // (n_cut_elems + 1)

@@ -28,114 +28,127 @@ __device__ inline void wave_sync() {
 // ----------------------------------------------------------------------------------------
 // (i) remainder element Gauss, one workgroup per cut row
 // ----------------------------------------------------------------------------------------
+template <int P> struct RemCfg {
+    static constexpr int P1 = P + 1, NP = P1 * P1 * P1, P2 = P1 * P1;
+    static constexpr int SLOT = ((NP + 63) / 64) * 64;         // threads per element in flight
+    static constexpr int NT = SLOT >= 256 ? SLOT : 256;
+    static constexpr int NSLOT = NT / SLOT;                    // elements in flight per workgroup
+};
+
+template <typename T> __device__ inline const T* rem_tab(const DevRules& R, int d);
+template <> __device__ inline const double* rem_tab<double>(const DevRules& R, int d) { return R.rem_w64[d]; }
+template <> __device__ inline const float* rem_tab<float>(const DevRules& R, int d) { return R.rem_w32[d]; }
+
+// One workgroup per cut row, NSLOT remainder elements in flight, one thread per Gauss point
+// (stage 1) or per partial / output entry (stages 2, 3).  The row's 1D weights sit in LDS;
+// kappa of the next element is loaded while the current one is contracted.
 template <typename T, int P, int WHICH>
-__global__ void __launch_bounds__(256)
-k_cut_remainder(DevRules R, const int32_t* __restrict__ box, const T* __restrict__ kappa, T* __restrict__ vm,
-                T* __restrict__ vk) {
-    constexpr int P1 = P + 1, NP = P1 * P1 * P1, M = 2 * P + 1, M3 = M * M * M, NWAVE = 4;
+__global__ void __launch_bounds__(RemCfg<P>::NT)
+k_cut_remainder(DevRules R, const T* __restrict__ kappa, T* __restrict__ vm, T* __restrict__ vk) {
+    using C = RemCfg<P>;
+    constexpr int P1 = C::P1, NP = C::NP, P2 = C::P2, M = 2 * P + 1, M3 = M * M * M, NT = C::NT, SLOT = C::SLOT;
+    constexpr int NSLOT = C::NSLOT;
     constexpr bool MASS = (WHICH & 1) != 0, STIFF = (WHICH & 2) != 0;
-    __shared__ T s_accm[MASS ? M3 : 1], s_acck[STIFF ? M3 : 1];
-    __shared__ T s_kap[NWAVE][NP];
-    __shared__ T s_w[NWAVE][3][2][P1 * P1];          // [dir][a][k][g]
-    __shared__ T s_t1[NWAVE][2][NP];
-    __shared__ T s_t2[NWAVE][2][NP];
-    __shared__ int s_rem[NP], s_nrem;
+    // per-slot accumulators: inside one pass every output of a slot has one writer, so
+    // they are updated without atomics and summed over the slots at the end
+    __shared__ T s_accm[NSLOT][MASS ? M3 : 1], s_acck[NSLOT][STIFF ? M3 : 1];
+    __shared__ T s_wt[3][P1][2 * P2];                 // [d][I_d - e_d][a][k][g]
+    __shared__ T s_kap[NSLOT][NP];
+    __shared__ T s_t1[NSLOT][2][NP];
+    __shared__ T s_t2[NSLOT][2][NP];
+    __shared__ int2 s_list[NP];
     const int64_t cr = blockIdx.x;
     const int ra = R.cut_rows[cr];
     int I[3];
     unlex3i(R.act2lex[ra], R.nfun, I);
-    for (int k = threadIdx.x; k < M3; k += 256) {
-        if (MASS) s_accm[k] = 0;
-        if (STIFF) s_acck[k] = 0;
+    const int t = threadIdx.x;
+    const int l0 = R.rem_ptr[cr], nrem = R.rem_ptr[cr + 1] - l0;
+    if (nrem == 0) return;
+    for (int k = t; k < NSLOT * M3; k += NT) {
+        if (MASS) s_accm[k / M3][k % M3] = 0;
+        if (STIFF) s_acck[k / M3][k % M3] = 0;
     }
-    int lo[3], hi[3], blo[3], bhi[3];
-    const bool has_box = R.split[cr].x >= 0;
-    for (int d = 0; d < 3; ++d) {
-        lo[d] = I[d] - P < 0 ? 0 : I[d] - P;
-        hi[d] = I[d] < R.nel[d] - 1 ? I[d] : R.nel[d] - 1;
-        blo[d] = box[cr * 6 + 2 * d];
-        bhi[d] = box[cr * 6 + 2 * d + 1];
+    for (int q = t; q < 3 * P1 * 2 * P2; q += NT) {
+        const int d = q / (P1 * 2 * P2), kI = (q / (2 * P2)) % P1, rest = q % (2 * P2);
+        const int e = I[d] - kI;
+        s_wt[d][kI][rest] = (e >= 0 && e < R.nel[d]) ? rem_tab<T>(R, d)[((int64_t)e * P1 + kI) * 2 * P2 + rest] : (T)0;
     }
+    for (int k = t; k < nrem; k += NT) s_list[k] = R.rem_list[l0 + k];
     __syncthreads();
-    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-    const int n2 = hi[1] - lo[1] + 1, n3 = hi[2] - lo[2] + 1;
-    const int ne = (hi[0] - lo[0] + 1) * n2 * n3;
-    // compact list of this row's remainder elements (interior, outside the DWQ box)
-    if (threadIdx.x == 0) s_nrem = 0;
-    __syncthreads();
-    for (int k = threadIdx.x; k < ne; k += 256) {
-        const int e0 = lo[0] + k / (n2 * n3), e1 = lo[1] + (k / n3) % n2, e2 = lo[2] + k % n3;
-        const int64_t eid = ((int64_t)e0 * R.nel[1] + e1) * R.nel[2] + e2;
-        const bool inbox = has_box && e0 >= blo[0] && e0 <= bhi[0] && e1 >= blo[1] && e1 <= bhi[1] && e2 >= blo[2] &&
-                           e2 <= bhi[2];
-        if (R.ecls[eid] == CLS_IN && !inbox) s_rem[atomicAdd(&s_nrem, 1)] = k;
-    }
-    __syncthreads();
-    const int nrem = s_nrem;
-    for (int r = wave; r < nrem; r += NWAVE) {
-        const int k = s_rem[r];
-        const int e[3] = {lo[0] + k / (n2 * n3), lo[1] + (k / n3) % n2, lo[2] + k % n3};
-        const int64_t eid = ((int64_t)e[0] * R.nel[1] + e[1]) * R.nel[2] + e[2];
-        // W_d[a][k][g] = omega_g (h/2) B_{I_d}^(a)(y_g) B_{e_d+k}^(a)(y_g)
-        for (int t = lane; t < 3 * 2 * P1 * P1; t += 64) {
-            const int d = t / (2 * P1 * P1), a = (t / (P1 * P1)) % 2, kk = (t / P1) % P1, g = t % P1;
-            const int64_t y = (int64_t)e[d] * P1 + g;
-            const double* tab = a ? R.dBval[d] : R.Bval[d];
-            const double om = R.gw[g] * R.h[d] * 0.5;
-            s_w[wave][d][a][kk * P1 + g] = (T)(om * tab[y * P1 + (I[d] - e[d])] * tab[y * P1 + kk]);
-        }
-        const int32_t* bs = R.blk_slot + (int64_t)R.elem_block[eid] * NP;
-        for (int t = lane; t < NP; t += 64) s_kap[wave][t] = kappa[bs[t]];
-        wave_sync();
-        for (int t = lane; t < NP; t += 64) {          // T1[v][g1][g2][k3]
-            const int g12 = t / P1, k3 = t % P1;
+    const int sl = t / SLOT, u = t % SLOT;
+    const bool act_u = u < NP;
+    const int d1 = u / P2, d2 = (u / P1) % P1, d3 = u % P1;       // u = (d1, d2, d3)
+    // pipeline: kappa one pass ahead, its slot index two passes ahead
+    T kap_c = 0;
+    int bs_n = 0;
+    if (act_u && sl < nrem) kap_c = kappa[R.blk_slot[(int64_t)s_list[sl].y * NP + u]];
+    if (act_u && sl + NSLOT < nrem) bs_n = R.blk_slot[(int64_t)s_list[sl + NSLOT].y * NP + u];
+    for (int r0 = 0; r0 < nrem; r0 += NSLOT) {
+        const int r = r0 + sl;
+        const bool active = r < nrem;
+        if (active && act_u) s_kap[sl][u] = kap_c;
+        kap_c = (act_u && r + NSLOT < nrem) ? kappa[bs_n] : (T)0;
+        bs_n = (act_u && r + 2 * NSLOT < nrem) ? R.blk_slot[(int64_t)s_list[r + 2 * NSLOT].y * NP + u] : 0;
+        const int pk = active ? s_list[r].x : 0;
+        const int kI0 = pk & 15, kI1 = (pk >> 4) & 15, kI2 = (pk >> 8) & 15;
+        const T* W1 = s_wt[0][kI0];
+        const T* W2 = s_wt[1][kI1];
+        const T* W3 = s_wt[2][kI2];
+        __syncthreads();
+        if (active && act_u) {                      // stage 1: T1[v][g1 g2][k3], u = (g1, g2, k3)
             T a0 = 0, a1 = 0;
+#pragma unroll
             for (int g3 = 0; g3 < P1; ++g3) {
-                const T kv = s_kap[wave][g12 * P1 + g3];
-                a0 += s_w[wave][2][0][k3 * P1 + g3] * kv;
-                if (STIFF) a1 += s_w[wave][2][1][k3 * P1 + g3] * kv;
+                const T kv = s_kap[sl][(d1 * P1 + d2) * P1 + g3];
+                a0 += W3[d3 * P1 + g3] * kv;
+                if (STIFF) a1 += W3[P2 + d3 * P1 + g3] * kv;
             }
-            s_t1[wave][0][t] = a0;
-            if (STIFF) s_t1[wave][1][t] = a1;
+            s_t1[sl][0][u] = a0;
+            if (STIFF) s_t1[sl][1][u] = a1;
         }
-        wave_sync();
-        for (int t = lane; t < NP; t += 64) {          // T2[v][g1][k2][k3]
-            const int g1 = t / (P1 * P1), k2 = (t / P1) % P1, k3 = t % P1;
+        __syncthreads();
+        if (active && act_u) {                      // stage 2: T2[v][g1][k2][k3], u = (g1, k2, k3)
             T m0 = 0, ms = 0;
+#pragma unroll
             for (int g2 = 0; g2 < P1; ++g2) {
-                const T t0 = s_t1[wave][0][(g1 * P1 + g2) * P1 + k3];
-                const T w0 = s_w[wave][1][0][k2 * P1 + g2];
+                const T t0 = s_t1[sl][0][(d1 * P1 + g2) * P1 + d3];
+                const T w0 = W2[d2 * P1 + g2];
                 m0 += w0 * t0;
-                if (STIFF) ms += s_w[wave][1][1][k2 * P1 + g2] * t0 + w0 * s_t1[wave][1][(g1 * P1 + g2) * P1 + k3];
+                if (STIFF) ms += W2[P2 + d2 * P1 + g2] * t0 + w0 * s_t1[sl][1][(d1 * P1 + g2) * P1 + d3];
             }
-            s_t2[wave][0][t] = m0;
-            if (STIFF) s_t2[wave][1][t] = ms;
+            s_t2[sl][0][u] = m0;
+            if (STIFF) s_t2[sl][1][u] = ms;
         }
-        wave_sync();
-        for (int t = lane; t < NP; t += 64) {          // out[k1][k2][k3] into the row window
-            const int k1 = t / (P1 * P1), k23 = t % (P1 * P1);
-            const int k2 = k23 / P1, k3 = k23 % P1;
+        __syncthreads();
+        if (active && act_u) {                      // stage 3: out[k1][k2][k3], u = (k1, k2, k3)
             T am = 0, ak = 0;
+#pragma unroll
             for (int g1 = 0; g1 < P1; ++g1) {
-                const T t0 = s_t2[wave][0][g1 * P1 * P1 + k23];
-                const T w0 = s_w[wave][0][0][k1 * P1 + g1];
+                const T t0 = s_t2[sl][0][g1 * P2 + d2 * P1 + d3];
+                const T w0 = W1[d1 * P1 + g1];
                 am += w0 * t0;
-                if (STIFF) ak += s_w[wave][0][1][k1 * P1 + g1] * t0 + w0 * s_t2[wave][1][g1 * P1 * P1 + k23];
+                if (STIFF) ak += W1[P2 + d1 * P1 + g1] * t0 + w0 * s_t2[sl][1][g1 * P2 + d2 * P1 + d3];
             }
-            const int jj = ((e[0] + k1 - I[0] + P) * M + (e[1] + k2 - I[1] + P)) * M + (e[2] + k3 - I[2] + P);
-            if (MASS) atomicAdd(&s_accm[jj], am);
-            if (STIFF) atomicAdd(&s_acck[jj], ak);
+            // trial J = e + (d1, d2, d3) = I + (d - kI): local index d - kI + P
+            const int jj = ((d1 - kI0 + P) * M + (d2 - kI1 + P)) * M + (d3 - kI2 + P);
+            if (MASS) s_accm[sl][jj] += am;
+            if (STIFF) s_acck[sl][jj] += ak;
         }
-        wave_sync();
+        __syncthreads();
     }
-    __syncthreads();
     const int32_t* pos = R.pos_map + cr * (int64_t)M3;
     const int64_t rb = R.row_ptr[ra];
-    for (int k = threadIdx.x; k < M3; k += 256) {
+    for (int k = t; k < M3; k += NT) {
         const int o = pos[k];
         if (o < 0) continue;
-        if (MASS) vm[rb + o] += s_accm[k];
-        if (STIFF) vk[rb + o] += s_acck[k];
+        T am = 0, ak = 0;
+#pragma unroll
+        for (int i = 0; i < NSLOT; ++i) {
+            if (MASS) am += s_accm[i][k];
+            if (STIFF) ak += s_acck[i][k];
+        }
+        if (MASS) vm[rb + o] += am;
+        if (STIFF) vk[rb + o] += ak;
     }
 }
 
@@ -365,11 +378,12 @@ k_cut_octree(DevRules R, const int32_t* __restrict__ act2cut, const T* __restric
 // host launchers
 // ----------------------------------------------------------------------------------------
 template <typename T, int P, int WHICH>
-static void launch_cut_p(const wq_rules* H, const T* kappa, T* vm, T* vk, hipStream_t s) {
+static void launch_cut_p(const wq_rules* H, uint32_t parts, const T* kappa, T* vm, T* vk, hipStream_t s) {
     const DevRules& R = H->R;
-    if (R.n_cut > 0)
-        hipLaunchKernelGGL((k_cut_remainder<T, P, WHICH>), dim3((unsigned)R.n_cut), dim3(256), 0, s, R, H->box, kappa, vm, vk);
-    if (R.n_cut_elems > 0) {
+    if ((parts & WQ_CUT_REMAINDER) && R.n_cut > 0)
+        hipLaunchKernelGGL((k_cut_remainder<T, P, WHICH>), dim3((unsigned)R.n_cut), dim3(RemCfg<P>::NT), 0, s, R, kappa, vm,
+                           vk);
+    if ((parts & WQ_CUT_OCTREE) && R.n_cut_elems > 0) {
         using C = OctCfg<P>;
         hipLaunchKernelGGL((k_cut_octree<T, P, WHICH>), dim3((unsigned)(R.n_cut_elems * C::P1 * C::NAG)), dim3(C::NT), 0, s, R,
                            H->act2cut, kappa, vm, vk);
@@ -377,27 +391,27 @@ static void launch_cut_p(const wq_rules* H, const T* kappa, T* vm, T* vk, hipStr
 }
 
 template <typename T, int P>
-static void launch_cut_w(const wq_rules* H, uint32_t which, const T* kappa, T* vm, T* vk, hipStream_t s) {
-    if (which == 1) launch_cut_p<T, P, 1>(H, kappa, vm, vk, s);
-    else if (which == 2) launch_cut_p<T, P, 2>(H, kappa, vm, vk, s);
-    else launch_cut_p<T, P, 3>(H, kappa, vm, vk, s);
+static void launch_cut_w(const wq_rules* H, uint32_t which, uint32_t parts, const T* kappa, T* vm, T* vk, hipStream_t s) {
+    if (which == 1) launch_cut_p<T, P, 1>(H, parts, kappa, vm, vk, s);
+    else if (which == 2) launch_cut_p<T, P, 2>(H, parts, kappa, vm, vk, s);
+    else launch_cut_p<T, P, 3>(H, parts, kappa, vm, vk, s);
 }
 
 template <typename T>
-void launch_cut(const wq_rules* H, uint32_t which, const T* kappa, T* vm, T* vk, hipStream_t s) {
+void launch_cut(const wq_rules* H, uint32_t which, uint32_t parts, const T* kappa, T* vm, T* vk, hipStream_t s) {
     switch (H->R.p) {
-        case 1: launch_cut_w<T, 1>(H, which, kappa, vm, vk, s); break;
-        case 2: launch_cut_w<T, 2>(H, which, kappa, vm, vk, s); break;
-        case 3: launch_cut_w<T, 3>(H, which, kappa, vm, vk, s); break;
-        case 4: launch_cut_w<T, 4>(H, which, kappa, vm, vk, s); break;
-        case 5: launch_cut_w<T, 5>(H, which, kappa, vm, vk, s); break;
-        case 6: launch_cut_w<T, 6>(H, which, kappa, vm, vk, s); break;
+        case 1: launch_cut_w<T, 1>(H, which, parts, kappa, vm, vk, s); break;
+        case 2: launch_cut_w<T, 2>(H, which, parts, kappa, vm, vk, s); break;
+        case 3: launch_cut_w<T, 3>(H, which, parts, kappa, vm, vk, s); break;
+        case 4: launch_cut_w<T, 4>(H, which, parts, kappa, vm, vk, s); break;
+        case 5: launch_cut_w<T, 5>(H, which, parts, kappa, vm, vk, s); break;
+        case 6: launch_cut_w<T, 6>(H, which, parts, kappa, vm, vk, s); break;
     }
 }
 
 #ifndef WQ_ONLY_F32
-template void launch_cut<double>(const wq_rules*, uint32_t, const double*, double*, double*, hipStream_t);
+template void launch_cut<double>(const wq_rules*, uint32_t, uint32_t, const double*, double*, double*, hipStream_t);
 #endif
 #ifndef WQ_ONLY_F64
-template void launch_cut<float>(const wq_rules*, uint32_t, const float*, float*, float*, hipStream_t);
+template void launch_cut<float>(const wq_rules*, uint32_t, uint32_t, const float*, float*, float*, hipStream_t);
 #endif

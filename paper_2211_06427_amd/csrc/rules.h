@@ -17,6 +17,8 @@ struct wq_rules {
     double* gw = nullptr;
     int64_t n_active = 0, nnz = 0, n_interior_rows = 0, n_cut = 0, n_dwq = 0;
     int64_t n_block_elems = 0, n_cells = 0, n_oct = 0;
+    int64_t n_oct_xgroups = 0, n_oct_columns = 0;    // octree leaf groups of the cut kernels
+    int64_t n_rem_pairs = 0;                         // (cut row, remainder element) pairs
     int row_block = 16;
     int32_t* act2cut = nullptr;         // active row -> cut row or -1
     int32_t* box = nullptr;             // [cut row][6] DWQ box (inclusive element ranges)

@@ -683,6 +683,33 @@ __global__ void k_mark_blocks(DevRules R, int64_t ncut, const int32_t* cut_rows,
             }
 }
 
+// Remainder elements of each cut row: interior elements of its support outside its DWQ box,
+// lexicographic.  Entry = (offsets I_d - e_d packed 4 bits each, element's block index).
+template <bool FILL>
+__global__ void k_rem_list(DevRules R, int64_t ncut, const int32_t* cut_rows, const int32_t* act2lex, const int8_t* ecls,
+                           const int32_t* box, const int32_t* eblock, int32_t* cnt, const int64_t* off, int2* list) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncut) return;
+    int I[3], lo[3], hi[3];
+    unlex3(act2lex[cut_rows[c]], R.nfun, I);
+    fun_support(R, I, lo, hi);
+    const int* bx = box + c * 6;
+    const bool has_box = R.split[c].x >= 0;
+    int32_t n = 0;
+    int64_t o = FILL ? off[c] : 0;
+    for (int a = lo[0]; a <= hi[0]; ++a)
+        for (int b = lo[1]; b <= hi[1]; ++b)
+            for (int k = lo[2]; k <= hi[2]; ++k) {
+                const int64_t e = ((int64_t)a * R.nel[1] + b) * R.nel[2] + k;
+                const bool inbox = has_box && a >= bx[0] && a <= bx[1] && b >= bx[2] && b <= bx[3] && k >= bx[4] &&
+                                   k <= bx[5];
+                if (ecls[e] != CLS_IN || inbox) continue;
+                if (FILL) list[o + n] = make_int2((I[0] - a) | (I[1] - b) << 4 | (I[2] - k) << 8, eblock[e]);
+                ++n;
+            }
+    if (!FILL) cnt[c] = n;
+}
+
 __global__ void k_flag_index(int64_t n, const int32_t* flag, const int64_t* off, int32_t* idx, int32_t* list) {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n) return;
@@ -774,6 +801,24 @@ __global__ void k_octree_sort(int64_t nce, const int64_t* begin, const int32_t* 
     }
 }
 
+// Counts of x-groups (leaves sharing depth and x offset) and columns (sharing depth, x and y
+// offsets) over all cut elements, from the sorted leaf order.
+__global__ void k_octree_groups(int64_t nce, const int64_t* begin, const int32_t* cell_key, const int32_t* perm,
+                                unsigned long long* counts) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nce) return;
+    unsigned long long nx = 0, ncol = 0;
+    int32_t prev = -1;
+    for (int64_t k = begin[c]; k < begin[c + 1]; ++k) {
+        const int32_t key = cell_key[perm[k]];
+        if (prev < 0 || (key & 511) != (prev & 511)) ++nx;
+        if (prev < 0 || (key & 32767) != (prev & 32767)) ++ncol;
+        prev = key;
+    }
+    atomicAdd(&counts[0], nx);
+    atomicAdd(&counts[1], ncol);
+}
+
 // 1D basis products of element e's functions at the Gauss points of each octree interval
 // (depth l, offset o; index 2^l - 1 + o) in direction d:
 // pp[((e * NI + iv) * 2 + v) * P1^2 + a * P1 + b][g] = phi_a phi_b (v = 0) or phi_a' phi_b' (v = 1),
@@ -837,6 +882,21 @@ __global__ void k_blk_slot(DevRules R, const int32_t* block_elems, int64_t nb, i
     const int e3 = (int)(eid % R.nel[2]), e2 = (int)((eid / R.nel[2]) % R.nel[1]);
     const int e1 = (int)(eid / ((int64_t)R.nel[1] * R.nel[2]));
     out[id] = (int32_t)slot_of(R, e1 * p1 + pt / (p1 * p1), e2 * p1 + (pt / p1) % p1, e3 * p1 + pt % p1);
+}
+
+// Element-Gauss test x trial weights of one direction:
+// W[((e * P1 + kI) * 2 + a) * P1^2 + k * P1 + g] = omega_g (h/2) B^(a)_{e+kI}(y) B^(a)_{e+k}(y), y the g-th
+// Gauss point of element e (kI: the test function's offset on the element).
+__global__ void k_rem_w(DevRules R, int d, const double* gw, double* W) {
+    const int p1 = R.p + 1;
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= (int64_t)R.nel[d] * p1 * 2 * p1 * p1) return;
+    const int g = (int)(id % p1), k = (int)((id / p1) % p1), a = (int)((id / (p1 * p1)) % 2);
+    const int kI = (int)((id / (2 * p1 * p1)) % p1);
+    const int64_t e = id / (2 * p1 * p1 * p1);
+    const int64_t y = e * p1 + g;
+    const double* tab = a ? R.dBval[d] : R.Bval[d];
+    W[id] = gw[g] * R.h[d] * 0.5 * tab[y * p1 + kI] * tab[y * p1 + k];
 }
 
 // grid and block slot coordinates
@@ -1063,6 +1123,25 @@ int build_rules(const wq_mesh* mesh, const wq_levelset* ls, const wq_options* op
         R.elem_block = eblock;
         H->block_elems = blist;
         H->n_block_elems = nbe;
+        // per cut row remainder element lists
+        int32_t* rcnt2 = B.tmp<int32_t>(ncut + 1);
+        int64_t* roff = B.tmp<int64_t>(ncut + 1);
+        int32_t* rptr = B.keep<int32_t>(ncut + 1);
+        if (!rcnt2 || !roff || !rptr) return B.fail();
+        if (ncut > 0)
+            hipLaunchKernelGGL(k_rem_list<false>, grid_for(ncut), dim3(256), 0, stream, R, ncut, cut_rows, act2lex, ecls, box,
+                               eblock, rcnt2, nullptr, nullptr);
+        int64_t npairs = 0;
+        if (scan_exclusive(B, rcnt2, roff, ncut, &npairs)) return B.fail();
+        if (npairs >= ((int64_t)1 << 31)) return B.fail_msg(WQ_EUNSUPPORTED, "too many remainder pairs (%lld)", (long long)npairs);
+        int2* rlist = B.keep<int2>(npairs > 0 ? npairs : 1);
+        if (!rlist) return B.fail();
+        if (ncut > 0)
+            hipLaunchKernelGGL(k_rem_list<true>, grid_for(ncut), dim3(256), 0, stream, R, ncut, cut_rows, act2lex, ecls, box,
+                               eblock, nullptr, roff, rlist);
+        hipLaunchKernelGGL(k_i64_to_i32, grid_for(ncut + 1), dim3(256), 0, stream, roff, rptr, ncut + 1);
+        R.rem_ptr = rptr; R.rem_list = rlist;
+        H->n_rem_pairs = npairs;
     }
 
     // octree
@@ -1103,6 +1182,16 @@ int build_rules(const wq_mesh* mesh, const wq_levelset* ls, const wq_options* op
                                clo, cdep, ccut, celem, ckey);
             hipLaunchKernelGGL(k_octree_sort, grid_for(nce, 64), dim3(64), 0, stream, nce, cbeg, ckey, cperm);
         }
+        unsigned long long* grp = B.tmp<unsigned long long>(2);
+        if (!grp) return B.fail();
+        if (B.check(hipMemsetAsync(grp, 0, 2 * sizeof(unsigned long long), stream))) return B.fail();
+        if (nce > 0)
+            hipLaunchKernelGGL(k_octree_groups, grid_for(nce, 64), dim3(64), 0, stream, nce, cbeg, ckey, cperm, grp);
+        unsigned long long hg[2] = {0, 0};
+        if (B.check(hipMemcpyAsync(hg, grp, sizeof(hg), hipMemcpyDeviceToHost, stream))) return B.fail();
+        if (B.check(hipStreamSynchronize(stream))) return B.fail();
+        H->n_oct_xgroups = (int64_t)hg[0];
+        H->n_oct_columns = (int64_t)hg[1];
         R.cell_key = ckey; R.cell_perm = cperm;
         const int ni = (2 << R.levels) - 1;
         for (int d = 0; d < 3; ++d) {
@@ -1138,6 +1227,15 @@ int build_rules(const wq_mesh* mesh, const wq_levelset* ls, const wq_options* op
         if (R.n_block > 0)
             hipLaunchKernelGGL(k_blk_slot, grid_for(R.n_block), dim3(256), 0, stream, R, H->block_elems, H->n_block_elems, bslot);
         R.blk_slot = bslot;
+        for (int d = 0; d < 3; ++d) {
+            const int64_t n = (int64_t)R.nel[d] * p1 * 2 * p1 * p1;
+            double* w = B.keep<double>(n);
+            float* w32 = B.keep<float>(n);
+            if (!w || !w32) return B.fail();
+            hipLaunchKernelGGL(k_rem_w, grid_for(n), dim3(256), 0, stream, R, d, gw, w);
+            hipLaunchKernelGGL(k_convert<float>, grid_for(n), dim3(256), 0, stream, w, w32, n);
+            R.rem_w64[d] = w; R.rem_w32[d] = w32;
+        }
         if (H->n_oct > 0)
             hipLaunchKernelGGL(k_octree_weights, grid_for(H->n_oct), dim3(256), 0, stream, R, gxi, gw, R.cell_lo, R.cell_depth,
                                H->cell_cut, ow, xyz);

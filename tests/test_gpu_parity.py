@@ -94,6 +94,7 @@ def test_structure_matches_oracle(name):
             n_split += 1
             assert (sp[c, 0], sp[c, 1], sp[c, 2]) == (ref[0], ref[1], int(ref[2]))
     assert R.n_rows_split == n_split
+    assert R.n_rem_pairs == sum(len(P.remainder_elements(dom.unlex(dom.active_lex[r]))) for r in cut)
     sl = P.slots()
     assert R.n_grid == sl.n_grid
     assert np.array_equal(R.block_elems().cpu().numpy(),
@@ -142,6 +143,15 @@ def test_which_subsets_and_determinism(name):
     assert torch.equal(rm[0], rm[1]) and torch.equal(rk[0], rk[1])
     assert float((vm - vm1).abs().max()) <= 1e-14 * float(vm.abs().max())
     assert float((vk - vk2).abs().max()) <= 1e-14 * float(vk.abs().max())
+    # the cut part split into its remainder and octree calls equals the combined call
+    from paper_2211_06427_amd._lib import WQ_CUT_OCTREE, WQ_CUT_REMAINDER
+    pm, pk = torch.empty_like(vm), torch.empty_like(vk)
+    R.assemble_rows(kap, pm, pk)
+    R.cut_assemble(kap, pm, pk, parts=WQ_CUT_REMAINDER)
+    R.cut_assemble(kap, pm, pk, parts=WQ_CUT_OCTREE)
+    torch.cuda.synchronize()
+    assert float((vm - pm).abs().max()) <= 1e-14 * float(vm.abs().max())
+    assert float((vk - pk).abs().max()) <= 1e-14 * float(vk.abs().max())
 
 
 def test_plane48_sampled_rows():
@@ -204,7 +214,8 @@ def test_adjoint_matches_oracle(name):
 
 
 def test_adjoint_torus32_fd():
-    """Torus 32^3 p=3, L = u^T A(kappa) v: finite differences at 50 seeded slots (step 1e-6)."""
+    """Torus 32^3 p=3, L = u^T A(kappa) v: finite differences at 50 seeded slots (steps 1e-6 and
+    1e-2) and the exact directional derivative along each slot's unit vector."""
     wl = W.workload("torus32_p3")
     print("case torus32 fd", flush=True)
     R = rules_for(wl)
@@ -236,16 +247,30 @@ def test_adjoint_torus32_fd():
     for _ in range(3):
         m1, k1 = mats(kap)
         noise = max(noise, abs(float(((m1 - m0) * G).sum() + ((k1 - k0) * G).sum())))
+    u_fp64 = np.finfo(np.float64).eps / 2
     for step, rel in ((1e-6, 1e-4), (1e-2, 1e-9)):
         for s in picks:
             kp = kap.clone(); kp[s] += step
             km = kap.clone(); km[s] -= step
             mp, kp_ = mats(kp)
             mm, km_ = mats(km)
-            # L is linear in kappa: difference the matrices first, then contract with G
+            # L is linear in kappa: difference the matrices first, then contract with G.  With
+            # no truncation error, the FD error is the rounding of the entries that the
+            # perturbation changes (a few u of their magnitude each) over 2*step.
             fd = float(((mp - mm) * G).sum() + ((kp_ - km_) * G).sum()) / (2 * step)
-            tol = rel * abs(dkh[s]) + 10 * noise / (2 * step) + 1e-15 * np.abs(dkh).max()
-            assert abs(fd - dkh[s]) <= tol, (step, s, fd, dkh[s], noise)
+            chg = (mp != mm) | (kp_ != km_)
+            mag = float((G.abs() * (mp.abs() + mm.abs() + kp_.abs() + km_.abs()))[chg].sum())
+            tol = rel * abs(dkh[s]) + (4 * u_fp64 * mag + 10 * noise) / (2 * step) + 1e-15 * np.abs(dkh).max()
+            assert abs(fd - dkh[s]) <= tol, (step, s, fd, dkh[s], noise, mag)
+    # exact directional derivative: A is linear in kappa, so A(e_s) (kappa = 1 at slot s,
+    # 0 elsewhere) is dA/dkappa_s and <G, A(e_s)> must equal the adjoint at s
+    for s in picks:
+        ks = torch.zeros_like(kap)
+        ks[s] = 1.0
+        ms, kss = mats(ks)
+        val = float((ms * G).sum() + (kss * G).sum())
+        scale = float((ms.abs() * G.abs()).sum() + (kss.abs() * G.abs()).sum())
+        assert abs(val - dkh[s]) <= 1e-12 * scale + 1e-300, (s, val, dkh[s], scale)
 
 
 def test_errors_are_reported():
