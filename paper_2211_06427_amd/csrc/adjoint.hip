@@ -397,6 +397,9 @@ template <int P> struct OctAdjCfg {
     static constexpr int NAG = (P1 + AG - 1) / AG;
 };
 
+template <typename T> __device__ inline const T* oct_wt_a(const DevRules& R);
+template <> __device__ inline const double* oct_wt_a<double>(const DevRules& R) { return R.oct_w; }
+template <> __device__ inline const float* oct_wt_a<float>(const DevRules& R) { return R.oct_w32; }
 template <typename T> __device__ inline const T* oct_tab_a(const DevRules& R, int d);
 template <> __device__ inline const double* oct_tab_a<double>(const DevRules& R, int d) { return R.oct_pp64[d]; }
 template <> __device__ inline const float* oct_tab_a<float>(const DevRules& R, int d) { return R.oct_pp32[d]; }
@@ -467,7 +470,7 @@ k_adj_octree(DevRules R, const int32_t* __restrict__ act2cut, const T* __restric
                 T w_n = 0, pz_n[KP], py_n[KP], px_n[KP];
                 {
                     const int cell = s_cell[0], key = s_key[0];
-                    if (own) w_n = (T)R.oct_w[(int64_t)cell * NP + t];
+                    if (own) w_n = oct_wt_a<T>(R)[(int64_t)cell * NP + t];
 #pragma unroll
                     for (int i = 0; i < KP; ++i) {
                         const int q = t + i * NT;
@@ -494,7 +497,7 @@ k_adj_octree(DevRules R, const int32_t* __restrict__ act2cut, const T* __restric
                     }
                     if (j + 1 < nc) {
                         const int cn = s_cell[j + 1], kn = s_key[j + 1];
-                        if (own) w_n = (T)R.oct_w[(int64_t)cn * NP + t];
+                        if (own) w_n = oct_wt_a<T>(R)[(int64_t)cn * NP + t];
                         const bool nc_next = (kn & cmask) != (key & cmask), nx_next = (kn & xmask) != (key & xmask);
 #pragma unroll
                         for (int i = 0; i < KP; ++i) {

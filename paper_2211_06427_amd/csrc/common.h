@@ -70,6 +70,7 @@ struct DevRules {
     const double* oct_pp64[3];          // per direction: [element][interval][v][a b][g] basis products
     const float* oct_pp32[3];
     const double* oct_w;                // [cell * (p+1)^3 + point]
+    const float* oct_w32;               // the same rounded once to FP32
     int64_t n_cut_elems, n_cells;
     // slots
     int64_t n_grid, n_block, n_kappa;
@@ -79,6 +80,15 @@ struct DevRules {
 // B-spline evaluation (local triangular scheme of the Cox-de Boor recursion)
 // ----------------------------------------------------------------------------------------
 // Knot span s with t[s] <= x < t[s+1] (non-empty), searched in [p, nt-p-2].
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup b runs on XCD b mod 8).
+// Returns a logical index such that consecutive logical indices run on the same XCD, so
+// workgroups that share data also share that XCD's L2.  A bijection of [0, n).
+__device__ __host__ inline int xcd_logical(int b, int n) {
+    constexpr int NX = 8;
+    const int x = b % NX, q = n / NX, r = n % NX;
+    return x * q + (x < r ? x : r) + b / NX;
+}
+
 __device__ __host__ inline int find_span(const double* t, int nt, int p, double x) {
     int lo = p, hi = nt - p - 2;
     if (x >= t[hi + 1]) {

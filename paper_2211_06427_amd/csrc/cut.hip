@@ -162,6 +162,9 @@ template <int P> struct OctCfg {
     static constexpr int NAG = (P1 + AG - 1) / AG;
 };
 
+template <typename T> __device__ inline const T* oct_wt(const DevRules& R);
+template <> __device__ inline const double* oct_wt<double>(const DevRules& R) { return R.oct_w; }
+template <> __device__ inline const float* oct_wt<float>(const DevRules& R) { return R.oct_w32; }
 template <typename T> __device__ inline const T* oct_tab(const DevRules& R, int d);
 template <> __device__ inline const double* oct_tab<double>(const DevRules& R, int d) { return R.oct_pp64[d]; }
 template <> __device__ inline const float* oct_tab<float>(const DevRules& R, int d) { return R.oct_pp32[d]; }
@@ -187,9 +190,12 @@ k_cut_octree(DevRules R, const int32_t* __restrict__ act2cut, const T* __restric
     __shared__ T s_py[NPP], s_px[NPP];                  // column / x-group products
     __shared__ T s_p1[2][P2 * P1];                      // column result [v][g1 g2][b3]
     __shared__ T s_p2[2][P1 * NP];                      // x-group result [v][g1][a2 b2 b3]
-    const int ce = blockIdx.x / (P1 * C::NAG);
-    const int a3 = (blockIdx.x / C::NAG) % P1;
-    const int ag0 = (blockIdx.x % C::NAG) * AG;
+    // the P1 * NAG workgroups of one cut element read the same leaves: keep them on one XCD
+    const int bid = xcd_logical(blockIdx.x, gridDim.x);
+    const int ce = bid / (P1 * C::NAG);
+    const int a3 = (bid / C::NAG) % P1;
+    const int ag0 = (bid % C::NAG) * AG;
+    const T* __restrict__ ow = oct_wt<T>(R);
     const int64_t eid = R.cut_elems[ce];
     int e[3];
     unlex3i(eid, R.nel, e);
@@ -227,7 +233,7 @@ k_cut_octree(DevRules R, const int32_t* __restrict__ act2cut, const T* __restric
         T wk_n = 0, pz_n[KP], py_n[KP], px_n[KP];
         {
             const int cell = s_cell[0], key = s_key[0];
-            if (own) wk_n = (T)R.oct_w[(int64_t)cell * NP + t] * kappa[oct0 + (int64_t)cell * NP + t];
+            if (own) wk_n = ow[(int64_t)cell * NP + t] * kappa[oct0 + (int64_t)cell * NP + t];
 #pragma unroll
             for (int i = 0; i < KP; ++i) {
                 const int q = t + i * NT;
@@ -261,7 +267,7 @@ k_cut_octree(DevRules R, const int32_t* __restrict__ act2cut, const T* __restric
             }
             if (j + 1 < nc) {
                 const int cell = s_cell[j + 1];
-                if (own) wk_n = (T)R.oct_w[(int64_t)cell * NP + t] * kappa[oct0 + (int64_t)cell * NP + t];
+                if (own) wk_n = ow[(int64_t)cell * NP + t] * kappa[oct0 + (int64_t)cell * NP + t];
                 const bool nc_next = (knext & cmask) != (key & cmask), nx_next = (knext & xmask) != (key & xmask);
 #pragma unroll
                 for (int i = 0; i < KP; ++i) {

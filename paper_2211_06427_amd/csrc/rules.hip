@@ -1236,9 +1236,14 @@ int build_rules(const wq_mesh* mesh, const wq_levelset* ls, const wq_options* op
             hipLaunchKernelGGL(k_convert<float>, grid_for(n), dim3(256), 0, stream, w, w32, n);
             R.rem_w64[d] = w; R.rem_w32[d] = w32;
         }
-        if (H->n_oct > 0)
+        float* ow32 = B.keep<float>(H->n_oct > 0 ? H->n_oct : 1);
+        if (!ow32) return B.fail();
+        R.oct_w32 = ow32;
+        if (H->n_oct > 0) {
             hipLaunchKernelGGL(k_octree_weights, grid_for(H->n_oct), dim3(256), 0, stream, R, gxi, gw, R.cell_lo, R.cell_depth,
                                H->cell_cut, ow, xyz);
+            hipLaunchKernelGGL(k_convert<float>, grid_for(H->n_oct), dim3(256), 0, stream, ow, ow32, H->n_oct);
+        }
     }
     if (B.check(hipGetLastError())) return B.fail();
     int herr = 0;
