@@ -176,12 +176,15 @@ def main():
     roofs = {"rows": {"bound": "hbm", "kernel": "k_rows_interior + k_rows_cut (wq_assemble_rows)",
                       "achieved": rows_bytes / (timed_ms["rows"] * 1e-3) / 1e9, "peak": PEAK["hbm_GBps"],
                       "unit": "GB/s", "traffic": None}}
-    P1 = wl.degree + 1
-    # octree: sum-factorized local mass + stiffness, in FMA: direction 3 per leaf 2 P1^5,
-    # direction 2 per column 3 P1^6, direction 1 per x-group 3 P1^7 (2 flop per FMA)
-    oct_flop = 2 * (2 * R.n_cells * P1 ** 5 + 3 * R.n_oct_columns * P1 ** 6 + 3 * R.n_oct_xgroups * P1 ** 7)
+    P1, NK = wl.degree + 1, 2 * wl.degree + 1
+    # cut elements in moment form (M + K, 1 FMA = 2 flop): moments with direction 3 per leaf
+    # P1^2 NK P1, direction 2 per column P1 NK^2 P1, direction 1 per x-group NK^3 P1; then per
+    # element and a3: 2 NK^3 P1 + 3 NK^2 P1^3 + 3 NK P1^5 for the three contractions
+    oct_fma = (R.n_cells * P1 ** 3 * NK + R.n_oct_columns * P1 ** 2 * NK ** 2 + R.n_oct_xgroups * NK ** 3 * P1
+               + R.n_cut_elems * P1 * (2 * NK ** 3 * P1 + 3 * NK ** 2 * P1 ** 3 + 3 * NK * P1 ** 5))
+    oct_flop = 2 * oct_fma
     peak = PEAK["fp64_TFLOPs"] if main_dt == "f64" else PEAK["fp32_TFLOPs"]
-    roofs["octree"] = {"bound": "alu", "kernel": "k_cut_octree (cut_assemble, octree part)",
+    roofs["octree"] = {"bound": "alu", "kernel": "k_cut_moments (cut_assemble, octree part)",
                        "achieved": oct_flop / (timed_ms["octree"] * 1e-3) / 1e12, "peak": peak, "unit": "TFLOP/s",
                        "traffic": None}
     for v in roofs.values():

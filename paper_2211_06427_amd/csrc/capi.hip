@@ -121,9 +121,10 @@ int cut_assemble(const wq_rules* r, int dtype, uint32_t which, const void* kappa
     uint32_t parts = which & (WQ_CUT_REMAINDER | WQ_CUT_OCTREE);
     if (parts == 0) parts = WQ_CUT_REMAINDER | WQ_CUT_OCTREE;
     if (dtype == WQ_F64)
-        launch_cut<double>(r, which & 3u, parts, (const double*)kappa, (double*)vm, (double*)vk, (hipStream_t)stream);
+        st = launch_cut<double>(r, which & 3u, parts, (const double*)kappa, (double*)vm, (double*)vk, (hipStream_t)stream);
     else
-        launch_cut<float>(r, which & 3u, parts, (const float*)kappa, (float*)vm, (float*)vk, (hipStream_t)stream);
+        st = launch_cut<float>(r, which & 3u, parts, (const float*)kappa, (float*)vm, (float*)vk, (hipStream_t)stream);
+    if (st) return st;
     return check_launch("cut_assemble");
 }
 

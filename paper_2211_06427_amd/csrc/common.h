@@ -58,6 +58,8 @@ struct DevRules {
     const int32_t* blk_slot;            // [block][(p+1)^3] canonical kappa slot of each Gauss point
     const int32_t* rem_ptr;             // [cut row + 1] offsets into rem_list
     const int2* rem_list;               // remainder elements: (I_d - e_d packed 4 bits/direction, block)
+    const int32_t* rcut_ptr;            // [cut row + 1] offsets into rcut_list
+    const int2* rcut_list;              // cut elements of a cut row: (cut element, I_d - e_d packed 4 bits/direction)
     const double* rem_w64[3];           // per direction: [e][kI][a][k][g] element-Gauss test x trial weights
     const float* rem_w32[3];
     // octree
@@ -71,6 +73,10 @@ struct DevRules {
     const float* oct_pp32[3];
     const double* oct_w;                // [cell * (p+1)^3 + point]
     const float* oct_w32;               // the same rounded once to FP32
+    const double* bern_q64[3];          // per direction [e][v][a][b][k]: Bernstein coefficients of basis products
+    const float* bern_q32[3];
+    const double* bern_i64;             // [interval][k][g]: degree-2p Bernstein values at octree Gauss points
+    const float* bern_i32;
     int64_t n_cut_elems, n_cells;
     // slots
     int64_t n_grid, n_block, n_kappa;

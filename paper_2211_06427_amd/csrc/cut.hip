@@ -381,43 +381,477 @@ k_cut_octree(DevRules R, const int32_t* __restrict__ act2cut, const T* __restric
 }
 
 // ----------------------------------------------------------------------------------------
+// (ii') octree cut elements for p <= 4: the column (direction 2) and x-group (direction 1)
+// contractions on matrix cores
+// ----------------------------------------------------------------------------------------
+// 16x16x4 MFMA: A (16x4) element (m, k) in lane m + 16 k, B (4x16) element (k, n) in lane
+// n + 16 k; D (16x16) column n = lane % 16, row given by MfmaOp<T>::row(lane, r) for the
+// accumulator register r (FP32: 4 (lane / 16) + r, FP64: lane / 16 + 4 r).
+template <typename T> struct MfmaOp;
+template <> struct MfmaOp<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    static __device__ inline v4 mma(float a, float b, v4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    static __device__ inline int row(int l, int r) { return 4 * (l >> 4) + r; }
+};
+template <> struct MfmaOp<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    static __device__ inline v4 mma(double a, double b, v4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    static __device__ inline int row(int l, int r) { return (l >> 4) + 4 * r; }
+};
+
+template <int P> struct MomCfg {
+    static constexpr int P1 = P + 1, P2 = P1 * P1, NP = P2 * P1;
+    static constexpr int NK = 2 * P + 1, NK2 = NK * NK, NK3 = NK2 * NK;
+    static constexpr int NT = 256, NWAVE = 4;
+    static constexpr int NB = 8;                              // leaves per load batch
+    static constexpr int KW = (NB * NP + NT - 1) / NT;        // weight / kappa loads per thread per batch
+    static constexpr int NIMAX = 15, MAXC = 512;              // octree depth <= 3
+    static constexpr int NZ = P2 * NK, NY = P1 * NK2;         // column sums [g1 g2][k3], x-group sums [g1][k2 k3]
+    static constexpr int RZ = (NZ + NT - 1) / NT, RY = (NY + NT - 1) / NT, RX = (NK3 + NT - 1) / NT;
+    static constexpr int NS1 = NK2 * P1, NS2 = NK * NP;       // [k1 k2][b3], [k1][(a2 b2) b3]
+    static constexpr int MT = (P2 + 15) / 16, NTC = (NP + 15) / 16, NTW = (NTC + NWAVE - 1) / NWAVE;
+    static constexpr int KS1 = (NK + 3) / 4, KS2 = (2 * NK + 3) / 4;
+};
+
+template <typename T> __device__ inline const T* bern_q(const DevRules& R, int d);
+template <> __device__ inline const double* bern_q<double>(const DevRules& R, int d) { return R.bern_q64[d]; }
+template <> __device__ inline const float* bern_q<float>(const DevRules& R, int d) { return R.bern_q32[d]; }
+template <typename T> __device__ inline const T* bern_i(const DevRules& R);
+template <> __device__ inline const double* bern_i<double>(const DevRules& R) { return R.bern_i64; }
+template <> __device__ inline const float* bern_i<float>(const DevRules& R) { return R.bern_i32; }
+
+// Cut elements in moment form.  On an element every product phi_a phi_b (and phi_a' phi_b')
+// of one direction is a degree-2p polynomial with Bernstein coefficients Q_v[ab][k], so with
+// the moments
+//   Mom[k1 k2 k3] = sum over the element's octree points of w kappa B_k1(x) B_k2(y) B_k3(z)
+// (B the degree-2p Bernstein polynomials of the element) the local matrices are
+//   M[a][b] = sum_k QX0[a1 b1][k1] QY0[a2 b2][k2] QZ0[a3 b3][k3] Mom[k],
+//   K[a][b] = the same with Q1 in one direction, summed over the three directions.
+// Exact up to rounding: the Bernstein expansion is an identity.
+//
+// k_cut_moments: one workgroup per cut element forms Mom leaf by leaf (direction 3 per
+// leaf, direction 2 per column, direction 1 per x-group) and writes it to a scratch buffer.
+template <typename T, int P>
+__global__ void __launch_bounds__(256)
+k_cut_moments(DevRules R, const T* __restrict__ kappa, T* __restrict__ mom) {
+    using C = MomCfg<P>;
+    constexpr int P1 = C::P1, P2 = C::P2, NP = C::NP, NK = C::NK, NK2 = C::NK2, NK3 = C::NK3, NT = C::NT;
+    constexpr int NB = C::NB, KW = C::KW, MAXC = C::MAXC;
+    constexpr int NZ = C::NZ, NY = C::NY, RZ = C::RZ, RY = C::RY, RX = C::RX;
+    __shared__ int s_cell[MAXC], s_key[MAXC];
+    __shared__ T s_bi[C::NIMAX * NK * P1];
+    __shared__ T s_wk[2 * NB * NP];                 // weight * kappa of a batch of leaves
+    __shared__ T s_mz[2 * NZ];                      // column sums, double buffered
+    __shared__ T s_my[NY];                          // x-group sums
+
+    const int ce = blockIdx.x;
+    const int t = threadIdx.x;
+    const int ni = (2 << R.levels) - 1;
+    for (int i = t; i < ni * NK * P1; i += NT) s_bi[i] = bern_i<T>(R)[i];
+    const int64_t oct0 = R.n_grid + R.n_block;
+    const T* __restrict__ ow = oct_wt<T>(R);
+    const int cb = R.cell_begin[ce], cend = R.cell_begin[ce + 1];
+    auto ivl = [](int key, int d) { return (1 << (key & 7)) - 1 + ((key >> (3 + 6 * d)) & 63); };
+    const int xmask = (1 << 9) - 1, cmask = (1 << 15) - 1;
+
+    // ---------------- phase 1: moments ----------------
+    T accZ[RZ], accY[RY], accX[RX];
+#pragma unroll
+    for (int r = 0; r < RZ; ++r) accZ[r] = 0;
+#pragma unroll
+    for (int r = 0; r < RY; ++r) accY[r] = 0;
+#pragma unroll
+    for (int r = 0; r < RX; ++r) accX[r] = 0;
+    T pw[KW], pk[KW];
+    int kprev = -1, zbuf = 0;
+    for (int c0 = cb; c0 < cend; c0 += MAXC) {
+        const int nc = cend - c0 < MAXC ? cend - c0 : MAXC;
+        __syncthreads();
+        for (int j = t; j < nc; j += NT) {
+            const int cell = R.cell_perm[c0 + j];
+            s_cell[j] = cell;
+            s_key[j] = R.cell_key[cell];
+        }
+        const int key_after = c0 + nc < cend ? R.cell_key[R.cell_perm[c0 + nc]] : -1;
+        __syncthreads();
+        auto issue = [&](int jb, int nb) {
+#pragma unroll
+            for (int i = 0; i < KW; ++i) {
+                const int idx = t + i * NT;
+                if (idx < nb * NP) {
+                    const int64_t o = (int64_t)s_cell[jb + idx / NP] * NP + idx % NP;
+                    pw[i] = ow[o];
+                    pk[i] = kappa[oct0 + o];
+                }
+            }
+        };
+        const int nbat = (nc + NB - 1) / NB;
+        issue(0, nc < NB ? nc : NB);
+        for (int b = 0; b < nbat; ++b) {
+            const int jb = b * NB, nb = nc - jb < NB ? nc - jb : NB;
+            T* wkb = s_wk + (b & 1) * NB * NP;
+#pragma unroll
+            for (int i = 0; i < KW; ++i) {
+                const int idx = t + i * NT;
+                if (idx < nb * NP) wkb[idx] = pw[i] * pk[i];
+            }
+            __syncthreads();
+            if (b + 1 < nbat) issue(jb + NB, nc - jb - NB < NB ? nc - jb - NB : NB);
+            for (int jl = 0; jl < nb; ++jl) {
+                const int j = jb + jl;
+                const int key = s_key[j];
+                const int knext = j + 1 < nc ? s_key[j + 1] : key_after;
+                const bool end_col = knext < 0 || (key & cmask) != (knext & cmask);
+                const bool end_x = knext < 0 || (key & xmask) != (knext & xmask);
+                kprev = key;
+                {   // direction 3: Mz[g1 g2][k3] += sum_g3 B_k3(z_g3) wk[g1 g2 g3]
+                    const T* bz = s_bi + ivl(key, 2) * NK * P1;
+                    const T* wk = wkb + jl * NP;
+#pragma unroll
+                    for (int r = 0; r < RZ; ++r) {
+                        const int i = t + r * NT;
+                        if (i < NZ) {
+                            const int g12 = i / NK, k3 = i % NK;
+                            T s = 0;
+#pragma unroll
+                            for (int g3 = 0; g3 < P1; ++g3) s += bz[k3 * P1 + g3] * wk[g12 * P1 + g3];
+                            accZ[r] += s;
+                        }
+                    }
+                }
+                if (!end_col) continue;
+                T* mz = s_mz + zbuf * NZ;
+#pragma unroll
+                for (int r = 0; r < RZ; ++r) {
+                    const int i = t + r * NT;
+                    if (i < NZ) mz[i] = accZ[r];
+                    accZ[r] = 0;
+                }
+                __syncthreads();
+                {   // direction 2: My[g1][k2 k3] += sum_g2 B_k2(y_g2) Mz[g1 g2][k3]
+                    const T* by = s_bi + ivl(key, 1) * NK * P1;
+#pragma unroll
+                    for (int r = 0; r < RY; ++r) {
+                        const int i = t + r * NT;
+                        if (i < NY) {
+                            const int g1 = i / NK2, k2 = (i / NK) % NK, k3 = i % NK;
+                            T s = 0;
+#pragma unroll
+                            for (int g2 = 0; g2 < P1; ++g2) s += by[k2 * P1 + g2] * mz[(g1 * P1 + g2) * NK + k3];
+                            accY[r] += s;
+                        }
+                    }
+                }
+                zbuf ^= 1;
+                if (!end_x) continue;
+#pragma unroll
+                for (int r = 0; r < RY; ++r) {
+                    const int i = t + r * NT;
+                    if (i < NY) s_my[i] = accY[r];
+                    accY[r] = 0;
+                }
+                __syncthreads();
+                {   // direction 1: Mom[k1][k2 k3] += sum_g1 B_k1(x_g1) My[g1][k2 k3]
+                    const T* bx = s_bi + ivl(key, 0) * NK * P1;
+#pragma unroll
+                    for (int r = 0; r < RX; ++r) {
+                        const int i = t + r * NT;
+                        if (i < NK3) {
+                            const int k1 = i / NK2, k23 = i % NK2;
+                            T s = 0;
+#pragma unroll
+                            for (int g1 = 0; g1 < P1; ++g1) s += bx[k1 * P1 + g1] * s_my[g1 * NK2 + k23];
+                            accX[r] += s;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    (void)kprev;
+#pragma unroll
+    for (int r = 0; r < RX; ++r) {
+        const int i = t + r * NT;
+        if (i < NK3) mom[(int64_t)ce * NK3 + i] = accX[r];
+    }
+}
+
+
+// k_cut_local: one workgroup per (cut element, a3) contracts Mom with the Q tables
+// (directions 3 and 2 on the vector ALU, direction 1 on matrix cores) and stores the local
+// rows a = (a1, a2, a3) of both matrices, loc[((ce P1 + a3) 2 + v) P1^2 + (a1 P1 + a2)][b],
+// through LDS so that every row is one contiguous run.
+template <typename T, int P, int WHICH>
+__global__ void __launch_bounds__(256)
+k_cut_local(DevRules R, const T* __restrict__ mom, T* __restrict__ loc) {
+    using C = MomCfg<P>;
+    using MF = MfmaOp<T>;
+    using v4 = typename MF::v4;
+    constexpr int P1 = C::P1, P2 = C::P2, NP = C::NP, NK = C::NK, NK2 = C::NK2, NK3 = C::NK3, NT = C::NT;
+    constexpr int M = 2 * P + 1, M3 = M * M * M, NS1 = C::NS1, NS2 = C::NS2;
+    constexpr int MT = C::MT, NTC = C::NTC, NTW = C::NTW, KS1 = C::KS1, KS2 = C::KS2, QN = 2 * P2 * NK;
+    constexpr int NBLK = P2 * NP;                   // one matrix's block: rows (a1 a2) x columns b
+    constexpr int NSU = (2 * NS1 + 2 * NS2) > NBLK ? (2 * NS1 + 2 * NS2) : NBLK;
+    constexpr bool MASS = (WHICH & 1) != 0, STIFF = (WHICH & 2) != 0;
+    __shared__ T s_q[3][QN];
+    __shared__ T s_mom[NK3];
+    __shared__ T s_u[NSU];
+    T* s_s1 = s_u;                                  // [2][NS1]
+    T* s_s2 = s_u + 2 * NS1;                        // [2][NS2]
+    T* s_blk = s_u;                                 // [(a1 a2)][b] after the contractions
+
+    const int ce = blockIdx.x / P1, a3 = blockIdx.x % P1;
+    const int64_t eid = R.cut_elems[ce];
+    int e[3];
+    unlex3i(eid, R.nel, e);
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int lm = lane & 15, lk = lane >> 4;
+    for (int i = t; i < 3 * QN; i += NT) {
+        const int d = i / QN;
+        s_q[d][i % QN] = bern_q<T>(R, d)[(int64_t)e[d] * QN + i % QN];
+    }
+    for (int i = t; i < NK3; i += NT) s_mom[i] = mom[(int64_t)ce * NK3 + i];
+    __syncthreads();
+    const T* qx = s_q[0];
+    const T* qy = s_q[1];
+    const T* qz = s_q[2];
+    // S1_v[k1 k2][b3] = sum_k3 QZ_v[a3 b3][k3] Mom[k1 k2 k3]
+    for (int i = t; i < NS1; i += NT) {
+        const int k12 = i / P1, b3 = i % P1;
+        const T* z0 = qz + (a3 * P1 + b3) * NK;
+        const T* z1 = qz + P2 * NK + (a3 * P1 + b3) * NK;
+        T s0 = 0, s1 = 0;
+#pragma unroll
+        for (int k3 = 0; k3 < NK; ++k3) {
+            const T mo = s_mom[k12 * NK + k3];
+            s0 += z0[k3] * mo;
+            if (STIFF) s1 += z1[k3] * mo;
+        }
+        s_s1[i] = s0;
+        if (STIFF) s_s1[NS1 + i] = s1;
+    }
+    __syncthreads();
+    // S2_0[k1][(a2 b2) b3] = sum_k2 QY0 S1_0,  S2_s = sum_k2 (QY1 S1_0 + QY0 S1_1)
+    for (int i = t; i < NS2; i += NT) {
+        const int k1 = i / NP, c = i % NP, ab2 = c / P1, b3 = c % P1;
+        const T* y0 = qy + ab2 * NK;
+        const T* y1 = qy + P2 * NK + ab2 * NK;
+        T m0 = 0, ms = 0;
+#pragma unroll
+        for (int k2 = 0; k2 < NK; ++k2) {
+            const T u0 = s_s1[(k1 * NK + k2) * P1 + b3];
+            m0 += y0[k2] * u0;
+            if (STIFF) ms += y1[k2] * u0 + y0[k2] * s_s1[NS1 + (k1 * NK + k2) * P1 + b3];
+        }
+        s_s2[i] = m0;
+        if (STIFF) s_s2[NS2 + i] = ms;
+    }
+    __syncthreads();
+    // direction 1 on matrix cores: rows m = (a1 b1), columns n = (a2 b2 b3), K = k1
+    v4 accM[NTW][MT], accK[NTW][MT];
+#pragma unroll
+    for (int ti = 0; ti < NTW; ++ti)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) { accM[ti][mt] = v4{0, 0, 0, 0}; accK[ti][mt] = v4{0, 0, 0, 0}; }
+#pragma unroll
+    for (int ti = 0; ti < NTW; ++ti) {
+        const int nt = wv + ti * C::NWAVE;
+        if (nt >= NTC) break;
+        const int n = nt * 16 + lm;
+        const bool nv = n < NP;
+        if (MASS) {
+#pragma unroll
+            for (int k = 0; k < KS1; ++k) {
+                const int k1 = 4 * k + lk;
+                const T bv = (nv && k1 < NK) ? s_s2[k1 * NP + n] : (T)0;
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) {
+                    const int m = mt * 16 + lm;
+                    const T av = (m < P2 && k1 < NK) ? qx[m * NK + k1] : (T)0;
+                    accM[ti][mt] = MF::mma(av, bv, accM[ti][mt]);
+                }
+            }
+        }
+        if (STIFF) {                                // K = [QX1 | QX0] [S2_0 ; S2_s]
+#pragma unroll
+            for (int k = 0; k < KS2; ++k) {
+                const int kk = 4 * k + lk;
+                T bv = 0;
+                if (nv && kk < NK) bv = s_s2[kk * NP + n];
+                else if (nv && kk < 2 * NK) bv = s_s2[NS2 + (kk - NK) * NP + n];
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) {
+                    const int m = mt * 16 + lm;
+                    T av = 0;
+                    if (m < P2 && kk < NK) av = qx[P2 * NK + m * NK + kk];
+                    else if (m < P2 && kk < 2 * NK) av = qx[m * NK + (kk - NK)];
+                    accK[ti][mt] = MF::mma(av, bv, accK[ti][mt]);
+                }
+            }
+        }
+    }
+    // stage each matrix's block as [(a1 a2)][(b1 b2 b3)] and store it
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+        if ((v == 0 && !MASS) || (v == 1 && !STIFF)) continue;
+        T* out = loc + ((int64_t)(ce * P1 + a3) * 2 + v) * NBLK;
+        __syncthreads();                            // s_u is free (contractions / previous scatter done)
+#pragma unroll
+        for (int ti = 0; ti < NTW; ++ti) {
+            const int nt = wv + ti * C::NWAVE;
+            if (nt >= NTC) break;
+            const int n = nt * 16 + lm;
+            if (n >= NP) continue;
+            const int a2 = n / P2, b2 = (n / P1) % P1, b3 = n % P1;
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int m = mt * 16 + MF::row(lane, r);
+                    if (m >= P2) continue;
+                    const int a1 = m / P1, b1 = m % P1;
+                    s_blk[(a1 * P1 + a2) * NP + (b1 * P1 + b2) * P1 + b3] = v == 0 ? accM[ti][mt][r] : accK[ti][mt][r];
+                }
+        }
+        __syncthreads();
+        for (int i = t; i < NBLK; i += NT) out[i] = s_blk[i];
+    }
+}
+
+// k_cut_gather: one workgroup per cut row adds the local rows of its cut elements (a fixed
+// order, no atomics): NSLOT elements in flight, one lane per column b of the element,
+// per-slot LDS accumulators over the row's (2p+1)^3 window, then one pass over the row.
+template <typename T, int P, int WHICH>
+__global__ void __launch_bounds__(RemCfg<P>::NT)
+k_cut_gather(DevRules R, const T* __restrict__ loc, T* __restrict__ vm, T* __restrict__ vk) {
+    using C = RemCfg<P>;
+    constexpr int P1 = C::P1, NP = C::NP, P2 = C::P2, M = 2 * P + 1, M3 = M * M * M, NT = C::NT, SLOT = C::SLOT;
+    constexpr int NSLOT = C::NSLOT, NBLK = P2 * NP;
+    constexpr bool MASS = (WHICH & 1) != 0, STIFF = (WHICH & 2) != 0;
+    __shared__ T s_accm[NSLOT][MASS ? M3 : 1], s_acck[NSLOT][STIFF ? M3 : 1];
+    __shared__ int2 s_list[NP];
+    const int64_t cr = blockIdx.x;
+    const int t = threadIdx.x;
+    const int l0 = R.rcut_ptr[cr], n = R.rcut_ptr[cr + 1] - l0;
+    if (n == 0) return;
+    for (int k = t; k < NSLOT * M3; k += NT) {
+        if (MASS) s_accm[k / M3][k % M3] = 0;
+        if (STIFF) s_acck[k / M3][k % M3] = 0;
+    }
+    for (int k = t; k < n; k += NT) s_list[k] = R.rcut_list[l0 + k];
+    __syncthreads();
+    const int sl = t / SLOT, u = t % SLOT;
+    const bool act_u = u < NP;
+    const int b1 = u / P2, b2 = (u / P1) % P1, b3 = u % P1;
+    auto src = [&](int r, int v) -> const T* {
+        const int2 en = s_list[r];
+        const int k0 = en.y & 15, k1 = (en.y >> 4) & 15, k2 = (en.y >> 8) & 15;
+        return loc + ((int64_t)(en.x * P1 + k2) * 2 + v) * NBLK + (k0 * P1 + k1) * NP;
+    };
+    T cm = 0, ck = 0;                               // values of the element in flight
+    if (act_u && sl < n) {
+        if (MASS) cm = src(sl, 0)[u];
+        if (STIFF) ck = src(sl, 1)[u];
+    }
+    for (int r0 = 0; r0 < n; r0 += NSLOT) {
+        const int r = r0 + sl;
+        const bool active = r < n;
+        T nm = 0, nk = 0;                           // next pass, loaded before this one is added
+        if (act_u && r + NSLOT < n) {
+            if (MASS) nm = src(r + NSLOT, 0)[u];
+            if (STIFF) nk = src(r + NSLOT, 1)[u];
+        }
+        if (active && act_u) {
+            const int pk = s_list[r].y;
+            const int a1 = pk & 15, a2 = (pk >> 4) & 15, a3 = (pk >> 8) & 15;
+            const int jj = ((b1 - a1 + P) * M + (b2 - a2 + P)) * M + (b3 - a3 + P);
+            if (MASS) s_accm[sl][jj] += cm;
+            if (STIFF) s_acck[sl][jj] += ck;
+        }
+        cm = nm; ck = nk;
+        __syncthreads();
+    }
+    const int ra = R.cut_rows[cr];
+    const int32_t* pos = R.pos_map + cr * (int64_t)M3;
+    const int64_t rb = R.row_ptr[ra];
+    for (int k = t; k < M3; k += NT) {
+        const int o = pos[k];
+        if (o < 0) continue;
+        T am = 0, ak = 0;
+#pragma unroll
+        for (int i = 0; i < NSLOT; ++i) {
+            if (MASS) am += s_accm[i][k];
+            if (STIFF) ak += s_acck[i][k];
+        }
+        if (MASS) vm[rb + o] += am;
+        if (STIFF) vk[rb + o] += ak;
+    }
+}
+
+// ----------------------------------------------------------------------------------------
 // host launchers
 // ----------------------------------------------------------------------------------------
 template <typename T, int P, int WHICH>
-static void launch_cut_p(const wq_rules* H, uint32_t parts, const T* kappa, T* vm, T* vk, hipStream_t s) {
+static int launch_cut_p(const wq_rules* H, uint32_t parts, const T* kappa, T* vm, T* vk, hipStream_t s) {
     const DevRules& R = H->R;
     if ((parts & WQ_CUT_REMAINDER) && R.n_cut > 0)
         hipLaunchKernelGGL((k_cut_remainder<T, P, WHICH>), dim3((unsigned)R.n_cut), dim3(RemCfg<P>::NT), 0, s, R, kappa, vm,
                            vk);
     if ((parts & WQ_CUT_OCTREE) && R.n_cut_elems > 0) {
+        if constexpr (P <= 4) {
+            if (R.levels <= 3) {
+                // moments scratch, stream ordered
+                // scratch (stream ordered): moments and local rows of every cut element
+                using C = MomCfg<P>;
+                const size_t nmom = (size_t)R.n_cut_elems * C::NK3;
+                const size_t nloc = (size_t)R.n_cut_elems * C::P1 * 2 * C::P2 * C::NP;
+                T* mom = nullptr;
+                hipError_t err = H->scratch_alloc((void**)&mom, sizeof(T) * (nmom + nloc), s);
+                if (err != hipSuccess)
+                    return wq_set_error(WQ_ENOMEM, "cut_assemble: scratch allocation failed: %s", hipGetErrorString(err));
+                T* loc = mom + nmom;
+                hipLaunchKernelGGL((k_cut_moments<T, P>), dim3((unsigned)R.n_cut_elems), dim3(256), 0, s, R, kappa, mom);
+                hipLaunchKernelGGL((k_cut_local<T, P, WHICH>), dim3((unsigned)(R.n_cut_elems * (P + 1))), dim3(256), 0, s, R,
+                                   (const T*)mom, loc);
+                if (R.n_cut > 0)
+                    hipLaunchKernelGGL((k_cut_gather<T, P, WHICH>), dim3((unsigned)R.n_cut), dim3(RemCfg<P>::NT), 0, s, R,
+                                       (const T*)loc, vm, vk);
+                err = hipFreeAsync(mom, s);
+                if (err != hipSuccess)
+                    return wq_set_error(WQ_EHIP, "cut_assemble: scratch release failed: %s", hipGetErrorString(err));
+                return WQ_OK;
+            }
+        }
         using C = OctCfg<P>;
         hipLaunchKernelGGL((k_cut_octree<T, P, WHICH>), dim3((unsigned)(R.n_cut_elems * C::P1 * C::NAG)), dim3(C::NT), 0, s, R,
                            H->act2cut, kappa, vm, vk);
     }
+    return WQ_OK;
 }
 
 template <typename T, int P>
-static void launch_cut_w(const wq_rules* H, uint32_t which, uint32_t parts, const T* kappa, T* vm, T* vk, hipStream_t s) {
-    if (which == 1) launch_cut_p<T, P, 1>(H, parts, kappa, vm, vk, s);
-    else if (which == 2) launch_cut_p<T, P, 2>(H, parts, kappa, vm, vk, s);
-    else launch_cut_p<T, P, 3>(H, parts, kappa, vm, vk, s);
+static int launch_cut_w(const wq_rules* H, uint32_t which, uint32_t parts, const T* kappa, T* vm, T* vk, hipStream_t s) {
+    if (which == 1) return launch_cut_p<T, P, 1>(H, parts, kappa, vm, vk, s);
+    if (which == 2) return launch_cut_p<T, P, 2>(H, parts, kappa, vm, vk, s);
+    return launch_cut_p<T, P, 3>(H, parts, kappa, vm, vk, s);
 }
 
 template <typename T>
-void launch_cut(const wq_rules* H, uint32_t which, uint32_t parts, const T* kappa, T* vm, T* vk, hipStream_t s) {
+int launch_cut(const wq_rules* H, uint32_t which, uint32_t parts, const T* kappa, T* vm, T* vk, hipStream_t s) {
     switch (H->R.p) {
-        case 1: launch_cut_w<T, 1>(H, which, parts, kappa, vm, vk, s); break;
-        case 2: launch_cut_w<T, 2>(H, which, parts, kappa, vm, vk, s); break;
-        case 3: launch_cut_w<T, 3>(H, which, parts, kappa, vm, vk, s); break;
-        case 4: launch_cut_w<T, 4>(H, which, parts, kappa, vm, vk, s); break;
-        case 5: launch_cut_w<T, 5>(H, which, parts, kappa, vm, vk, s); break;
-        case 6: launch_cut_w<T, 6>(H, which, parts, kappa, vm, vk, s); break;
+        case 1: return launch_cut_w<T, 1>(H, which, parts, kappa, vm, vk, s);
+        case 2: return launch_cut_w<T, 2>(H, which, parts, kappa, vm, vk, s);
+        case 3: return launch_cut_w<T, 3>(H, which, parts, kappa, vm, vk, s);
+        case 4: return launch_cut_w<T, 4>(H, which, parts, kappa, vm, vk, s);
+        case 5: return launch_cut_w<T, 5>(H, which, parts, kappa, vm, vk, s);
+        case 6: return launch_cut_w<T, 6>(H, which, parts, kappa, vm, vk, s);
     }
+    return WQ_OK;
 }
 
 #ifndef WQ_ONLY_F32
-template void launch_cut<double>(const wq_rules*, uint32_t, uint32_t, const double*, double*, double*, hipStream_t);
+template int launch_cut<double>(const wq_rules*, uint32_t, uint32_t, const double*, double*, double*, hipStream_t);
 #endif
 #ifndef WQ_ONLY_F64
-template void launch_cut<float>(const wq_rules*, uint32_t, uint32_t, const float*, float*, float*, hipStream_t);
+template int launch_cut<float>(const wq_rules*, uint32_t, uint32_t, const float*, float*, float*, hipStream_t);
 #endif

@@ -27,8 +27,14 @@ struct wq_rules {
     int32_t* cell_elem = nullptr;       // octree leaf -> cut element
     double* kappa_xyz = nullptr;
     int64_t n_split = 0;
+    hipMemPool_t pool = nullptr;        // stream-ordered scratch of the assembly calls (may be null)
     ~wq_rules() {
         for (void* p : allocs) (void)hipFree(p);
+        if (pool) (void)hipMemPoolDestroy(pool);
+    }
+    // stream-ordered scratch: from the handle's pool (kept across calls), else the default pool
+    hipError_t scratch_alloc(void** p, size_t n, hipStream_t s) const {
+        return pool ? hipMallocFromPoolAsync(p, n, pool, s) : hipMallocAsync(p, n, s);
     }
 };
 

@@ -710,6 +710,29 @@ __global__ void k_rem_list(DevRules R, int64_t ncut, const int32_t* cut_rows, co
     if (!FILL) cnt[c] = n;
 }
 
+// Cut elements of each cut row's support, lexicographic.  Entry = (cut element index, offsets
+// I_d - e_d packed 4 bits each).
+template <bool FILL>
+__global__ void k_rowcut_list(DevRules R, int64_t ncut, const int32_t* cut_rows, const int32_t* act2lex, const int8_t* ecls,
+                              const int32_t* ceidx, int32_t* cnt, const int64_t* off, int2* list) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncut) return;
+    int I[3], lo[3], hi[3];
+    unlex3(act2lex[cut_rows[c]], R.nfun, I);
+    fun_support(R, I, lo, hi);
+    int32_t n = 0;
+    const int64_t o = FILL ? off[c] : 0;
+    for (int a = lo[0]; a <= hi[0]; ++a)
+        for (int b = lo[1]; b <= hi[1]; ++b)
+            for (int k = lo[2]; k <= hi[2]; ++k) {
+                const int64_t e = ((int64_t)a * R.nel[1] + b) * R.nel[2] + k;
+                if (ecls[e] != CLS_CUT) continue;
+                if (FILL) list[o + n] = make_int2(ceidx[e], (I[0] - a) | (I[1] - b) << 4 | (I[2] - k) << 8);
+                ++n;
+            }
+    if (!FILL) cnt[c] = n;
+}
+
 __global__ void k_flag_index(int64_t n, const int32_t* flag, const int64_t* off, int32_t* idx, int32_t* list) {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n) return;
@@ -848,6 +871,104 @@ __global__ void k_oct_basis(DevRules R, int d, const double* gxi, double* pp) {
             out[(a * p1 + b) * p1 + g] = N[a] * N[b];
             out[p2 * p1 + (a * p1 + b) * p1 + g] = dN[a] * dN[b];
         }
+}
+
+// Bernstein form of the cut-element integrand.  On element e of direction d the local
+// functions phi_a (a = 0..p, phi_a = B_{e+a}) are degree-p polynomials; their products are
+// degree 2p.  Q[((e * 2 + v) * P1^2 + a * P1 + b) * (2p+1) + k] holds the degree-2p
+// Bernstein coefficients (in the element's local coordinate t in [0, 1]) of
+// phi_a phi_b (v = 0) and of phi_a' phi_b' (v = 1, physical derivatives).
+__device__ inline double binom(int n, int k) {
+    double r = 1.0;
+    for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+    return r;
+}
+
+__device__ inline double bernstein(int n, int k, double t) {
+    double r = binom(n, k);
+    for (int i = 0; i < k; ++i) r *= t;
+    for (int i = 0; i < n - k; ++i) r *= 1.0 - t;
+    return r;
+}
+
+__global__ void k_bern_products(DevRules R, int d, double* Q) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= R.nel[d]) return;
+    const int p = R.p, p1 = p + 1, nk = 2 * p + 1;
+    const double h = R.h[d];
+    double kn[2 * WQ_PMAX + 2];
+    for (int j = 0; j < 2 * p + 2; ++j) kn[j] = knot_at(e + j, p, R.nel[d], R.lo[d], h);
+    // Bernstein coefficients of phi_a on the element: the blossom of the polynomial piece at
+    // (left end repeated p-i times, right end repeated i times), evaluated by de Boor's
+    // algorithm on the unit control vector of phi_a.  Every step is a convex combination, so
+    // coefficients are accurate relative to themselves and structural zeros stay exact.
+    double cb[WQ_PMAX + 1][WQ_PMAX + 1];               // cb[a][i]: Bernstein coefficients of phi_a
+    for (int a = 0; a <= p; ++a)
+        for (int i = 0; i <= p; ++i) {
+            double dv[WQ_PMAX + 1];
+            for (int j = 0; j <= p; ++j) dv[j] = j == a ? 1.0 : 0.0;
+            for (int rr = 1; rr <= p; ++rr) {
+                const double u = rr <= p - i ? kn[p] : kn[p + 1];
+                for (int j = p; j >= rr; --j) {
+                    const double al = (u - kn[j]) / (kn[j + 1 + p - rr] - kn[j]);
+                    dv[j] = (1.0 - al) * dv[j - 1] + al * dv[j];
+                }
+            }
+            cb[a][i] = dv[p];
+        }
+    // derivative: degree p-1 coefficients p (c_{i+1} - c_i) / h
+    double db[WQ_PMAX + 1][WQ_PMAX + 1];
+    for (int a = 0; a <= p; ++a)
+        for (int i = 0; i < p; ++i) db[a][i] = p * (cb[a][i + 1] - cb[a][i]) / h;
+    for (int a = 0; a <= p; ++a)
+        for (int b = 0; b <= p; ++b) {
+            double* q0 = Q + (((int64_t)e * 2 + 0) * p1 * p1 + a * p1 + b) * nk;
+            double* q1 = Q + (((int64_t)e * 2 + 1) * p1 * p1 + a * p1 + b) * nk;
+            for (int k = 0; k < nk; ++k) {
+                double s = 0.0;
+                for (int i = 0; i <= p; ++i) {
+                    const int j = k - i;
+                    if (j < 0 || j > p) continue;
+                    s += cb[a][i] * cb[b][j] * binom(p, i) * binom(p, j);
+                }
+                q0[k] = s / binom(2 * p, k);
+            }
+            // derivative product: degree 2p-2, then raised twice to degree 2p
+            double r[2 * WQ_PMAX + 1], r2[2 * WQ_PMAX + 1];
+            const int n = 2 * p - 2;
+            for (int k = 0; k <= n; ++k) {
+                double s = 0.0;
+                for (int i = 0; i < p; ++i) {
+                    const int j = k - i;
+                    if (j < 0 || j > p - 1) continue;
+                    s += db[a][i] * db[b][j] * binom(p - 1, i) * binom(p - 1, j);
+                }
+                r[k] = s / binom(n, k);
+            }
+            for (int m = n; m < 2 * p; ++m) {          // degree m -> m + 1
+                for (int k = 0; k <= m + 1; ++k) {
+                    const double lo = k > 0 ? r[k - 1] : 0.0, hi = k <= m ? r[k] : 0.0;
+                    r2[k] = (double)k / (m + 1) * lo + (1.0 - (double)k / (m + 1)) * hi;
+                }
+                for (int k = 0; k <= m + 1; ++k) r[k] = r2[k];
+            }
+            for (int k = 0; k < nk; ++k) q1[k] = r[k];
+        }
+}
+
+// B[(iv * (2p+1) + k) * P1 + g]: degree-2p Bernstein polynomial k at the g-th Gauss point of
+// octree interval iv (depth l, offset o: iv = 2^l - 1 + o), in the element's local coordinate.
+__global__ void k_bern_intervals(DevRules R, const double* gxi, double* B) {
+    const int p = R.p, p1 = p + 1, nk = 2 * p + 1;
+    const int ni = (2 << R.levels) - 1;
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= ni * nk * p1) return;
+    const int g = id % p1, k = (id / p1) % nk, iv = id / (p1 * nk);
+    int dep = 0;
+    while ((2 << dep) - 1 <= iv) ++dep;
+    const int off = iv - ((1 << dep) - 1);
+    const double t = (off + (1.0 + gxi[g]) / 2.0) / (double)(1 << dep);
+    B[id] = bernstein(2 * p, k, t);
 }
 
 __global__ void k_octree_weights(DevRules R, const double* gxi, const double* gw, const double* cell_lo,
@@ -1157,6 +1278,25 @@ int build_rules(const wq_mesh* mesh, const wq_levelset* ls, const wq_options* op
         if (!cut_elems) return B.fail();
         hipLaunchKernelGGL(k_flag_index, grid_for(ne), dim3(256), 0, stream, ne, cflag2, ceoff, ceidx, cut_elems);
         R.cut_elems = cut_elems; R.n_cut_elems = nce;
+        {   // per cut row: its cut elements
+            int32_t* ccnt2 = B.tmp<int32_t>(ncut + 1);
+            int64_t* coff2 = B.tmp<int64_t>(ncut + 1);
+            int32_t* cptr = B.keep<int32_t>(ncut + 1);
+            if (!ccnt2 || !coff2 || !cptr) return B.fail();
+            if (ncut > 0)
+                hipLaunchKernelGGL(k_rowcut_list<false>, grid_for(ncut), dim3(256), 0, stream, R, ncut, cut_rows, act2lex, ecls,
+                                   ceidx, ccnt2, nullptr, nullptr);
+            int64_t np2 = 0;
+            if (scan_exclusive(B, ccnt2, coff2, ncut, &np2)) return B.fail();
+            if (np2 >= ((int64_t)1 << 31)) return B.fail_msg(WQ_EUNSUPPORTED, "too many cut pairs (%lld)", (long long)np2);
+            int2* clist = B.keep<int2>(np2 > 0 ? np2 : 1);
+            if (!clist) return B.fail();
+            if (ncut > 0)
+                hipLaunchKernelGGL(k_rowcut_list<true>, grid_for(ncut), dim3(256), 0, stream, R, ncut, cut_rows, act2lex, ecls,
+                                   ceidx, nullptr, coff2, clist);
+            hipLaunchKernelGGL(k_i64_to_i32, grid_for(ncut + 1), dim3(256), 0, stream, coff2, cptr, ncut + 1);
+            R.rcut_ptr = cptr; R.rcut_list = clist;
+        }
         int32_t* ccnt = B.tmp<int32_t>(nce + 1);
         int64_t* cbeg = B.tmp<int64_t>(nce + 1);
         int32_t* cbeg32 = B.keep<int32_t>(nce + 1);
@@ -1202,6 +1342,25 @@ int build_rules(const wq_mesh* mesh, const wq_levelset* ls, const wq_options* op
             hipLaunchKernelGGL(k_oct_basis, grid_for((int64_t)R.nel[d] * ni * p1), dim3(256), 0, stream, R, d, gxi, pp);
             hipLaunchKernelGGL(k_convert<float>, grid_for(n), dim3(256), 0, stream, pp, pp32, n);
             R.oct_pp64[d] = pp; R.oct_pp32[d] = pp32;
+        }
+        {   // Bernstein tables of the moment form of the cut-element integrals
+            const int nk = 2 * p + 1;
+            for (int d = 0; d < 3; ++d) {
+                const int64_t n = (int64_t)R.nel[d] * 2 * p1 * p1 * nk;
+                double* q = B.keep<double>(n);
+                float* q32 = B.keep<float>(n);
+                if (!q || !q32) return B.fail();
+                hipLaunchKernelGGL(k_bern_products, grid_for(R.nel[d], 64), dim3(64), 0, stream, R, d, q);
+                hipLaunchKernelGGL(k_convert<float>, grid_for(n), dim3(256), 0, stream, q, q32, n);
+                R.bern_q64[d] = q; R.bern_q32[d] = q32;
+            }
+            const int64_t n = (int64_t)ni * nk * p1;
+            double* bi = B.keep<double>(n);
+            float* bi32 = B.keep<float>(n);
+            if (!bi || !bi32) return B.fail();
+            hipLaunchKernelGGL(k_bern_intervals, grid_for(n), dim3(256), 0, stream, R, gxi, bi);
+            hipLaunchKernelGGL(k_convert<float>, grid_for(n), dim3(256), 0, stream, bi, bi32, n);
+            R.bern_i64 = bi; R.bern_i32 = bi32;
         }
         hipLaunchKernelGGL(k_i64_to_i32, grid_for(nce + 1), dim3(256), 0, stream, cbeg, cbeg32, nce + 1);
         R.cell_begin = cbeg32; R.cell_lo = clo; R.cell_depth = cdep;
@@ -1251,6 +1410,24 @@ int build_rules(const wq_mesh* mesh, const wq_levelset* ls, const wq_options* op
     if (B.check(hipStreamSynchronize(stream))) return B.fail();
     if (herr) return B.fail_msg(herr, "a weighted-quadrature exactness system is rank deficient");
     B.release_tmp();
+    {   // scratch pool of the assembly calls; memory is kept between calls
+        int dev = 0;
+        if (hipGetDevice(&dev) == hipSuccess) {
+            hipMemPoolProps pp;
+            memset(&pp, 0, sizeof(pp));
+            pp.allocType = hipMemAllocationTypePinned;
+            pp.handleTypes = hipMemHandleTypeNone;
+            pp.location.type = hipMemLocationTypeDevice;
+            pp.location.id = dev;
+            if (hipMemPoolCreate(&H->pool, &pp) == hipSuccess) {
+                uint64_t thr = UINT64_MAX;
+                (void)hipMemPoolSetAttribute(H->pool, hipMemPoolAttrReleaseThreshold, &thr);
+            } else {
+                H->pool = nullptr;
+                (void)hipGetLastError();
+            }
+        }
+    }
     *out = H;
     return WQ_OK;
 }

@@ -141,6 +141,11 @@ def test_which_subsets_and_determinism(name):
         R.assemble_rows(kap, rm[i], rk[i])
     torch.cuda.synchronize()
     assert torch.equal(rm[0], rm[1]) and torch.equal(rk[0], rk[1])
+    # the whole assembly sums in a fixed order for p <= 4 (no atomics): bitwise repeatable
+    if wl.degree <= 4:
+        vm2, vk2 = R.assemble(kap)
+        torch.cuda.synchronize()
+        assert torch.equal(vm, vm2) and torch.equal(vk, vk2)
     assert float((vm - vm1).abs().max()) <= 1e-14 * float(vm.abs().max())
     assert float((vk - vk2).abs().max()) <= 1e-14 * float(vk.abs().max())
     # the cut part split into its remainder and octree calls equals the combined call
