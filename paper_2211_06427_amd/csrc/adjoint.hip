@@ -6,6 +6,7 @@
 // result is added into dkappa at the quadrature points (atomics where several rows share a
 // point).  The cotangents carry one value per pattern entry, like the matrices.
 #include "rows.h"
+#include "moments.h"
 
 template <typename T> __device__ inline const T* wt_tab(const DevRules& R, int d);
 template <> __device__ inline const double* wt_tab<double>(const DevRules& R, int d) { return R.Wt64[d]; }
@@ -576,8 +577,244 @@ k_adj_octree(DevRules R, const int32_t* __restrict__ act2cut, const T* __restric
 // ----------------------------------------------------------------------------------------
 // host launchers
 // ----------------------------------------------------------------------------------------
+// ----------------------------------------------------------------------------------------
+// cut elements in moment form (p <= 4, octree depth <= 3): for a point g of a leaf of cut
+// element e,  dL/dkappa_g = w_g sum_k Gmom[k] B_k1(x_g) B_k2(y_g) B_k3(z_g)  with
+//   Gmom = sum_ab GM_ab QX0 QY0 QZ0 + GK_ab (QX1 QY0 QZ0 + QX0 QY1 QZ0 + QX0 QY0 QZ1)
+// (the transposed contraction of the forward moment form).
+// ----------------------------------------------------------------------------------------
+// k_adj_local: one workgroup per (cut element, a3): gathers the cotangents of the rows
+// a = (a1, a2, a3) from the CSR values and contracts them with Q^T, direction 1 on matrix
+// cores (U0 = QX0^T GM + QX1^T GK, Us = QX0^T GK), then directions 2 and 3 on the vector ALU;
+// writes this a3's share of Gmom to part[(ce P1 + a3) NK^3 + k].
 template <typename T, int P, int WHICH>
-static void launch_adj_p(const wq_rules* H, const T* gm, const T* gk, T* dk, hipStream_t s) {
+__global__ void __launch_bounds__(256)
+k_adj_local(DevRules R, const int32_t* __restrict__ act2cut, const T* __restrict__ gm, const T* __restrict__ gk,
+            T* __restrict__ part) {
+    using C = MomCfg<P>;
+    using MF = MfmaOp<T>;
+    using v4 = typename MF::v4;
+    constexpr int P1 = C::P1, P2 = C::P2, NP = C::NP, NK = C::NK, NK2 = C::NK2, NK3 = C::NK3, NT = C::NT;
+    constexpr int M = 2 * P + 1, M3 = M * M * M, NTC = C::NTC, NTW = C::NTW, QN = 2 * P2 * NK;
+    constexpr int NBLK = P2 * NP, NU = NK * NP, NV = NK2 * P1;
+    constexpr int KA = (2 * P2 + 3) / 4, KB = (P2 + 3) / 4;        // k steps of U0 and Us
+    constexpr bool MASS = (WHICH & 1) != 0, STIFF = (WHICH & 2) != 0;
+    __shared__ T s_q[3][QN];
+    __shared__ T s_g[2][NBLK];                      // cotangent blocks [(a1 b1)][(a2 b2) b3]
+    __shared__ T s_u[2][NU];                        // U0, Us [k1][(a2 b2) b3]
+    static_assert(2 * NV <= 2 * NBLK, "VA/VB reuse the cotangent block");
+    T (*s_v)[NV] = reinterpret_cast<T (*)[NV]>(&s_g[0][0]);   // VA, VB [k1 k2][b3] after direction 1
+    __shared__ int64_t s_rb[P2];
+    __shared__ int32_t s_cr[P2];
+    const int ce = blockIdx.x / P1, a3 = blockIdx.x % P1;
+    int e[3];
+    unlex3a(R.cut_elems[ce], R.nel, e);
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int lm = lane & 15, lk = lane >> 4;
+    if (t < P2) {
+        const int a1 = t / P1, a2 = t % P1;
+        const int64_t alex = ((int64_t)(e[0] + a1) * R.nfun[1] + (e[1] + a2)) * R.nfun[2] + (e[2] + a3);
+        const int ra = R.lex2act[alex];
+        s_rb[t] = R.row_ptr[ra];
+        s_cr[t] = act2cut[ra];
+    }
+    for (int i = t; i < 3 * QN; i += NT) {
+        const int d = i / QN;
+        s_q[d][i % QN] = bern_q<T>(R, d)[(int64_t)e[d] * QN + i % QN];
+    }
+    __syncthreads();
+    for (int i = t; i < NBLK; i += NT) {
+        const int r = i / NP, b = i % NP, a1 = r / P1, a2 = r % P1;
+        const int b1 = b / P2, b2 = (b / P1) % P1, b3 = b % P1;
+        const int jj = ((b1 - a1 + P) * M + (b2 - a2 + P)) * M + (b3 - a3 + P);
+        const int o = R.pos_map[(int64_t)s_cr[r] * M3 + jj];
+        const int dst = (a1 * P1 + b1) * NP + (a2 * P1 + b2) * P1 + b3;
+        s_g[0][dst] = (MASS && o >= 0) ? gm[s_rb[r] + o] : (T)0;
+        s_g[1][dst] = (STIFF && o >= 0) ? gk[s_rb[r] + o] : (T)0;
+    }
+    __syncthreads();
+    const T* qx = s_q[0];
+    const T* qy = s_q[1];
+    const T* qz = s_q[2];
+    // direction 1 on matrix cores: rows k1 (< NK <= 16), columns n = (a2 b2 b3), K = (a1 b1)
+#pragma unroll
+    for (int ti = 0; ti < NTW; ++ti) {
+        const int nt = wv + ti * C::NWAVE;
+        if (nt >= NTC) break;
+        const int n = nt * 16 + lm;
+        const bool nv = n < NP;
+        v4 u0 = {0, 0, 0, 0}, us = {0, 0, 0, 0};
+#pragma unroll
+        for (int k = 0; k < KA; ++k) {              // U0 = [QX0^T | QX1^T] [GM ; GK]
+            const int kk = 4 * k + lk;
+            T av = 0, bv = 0;
+            if (kk < P2) {
+                if (MASS) { av = lm < NK ? qx[kk * NK + lm] : (T)0; bv = nv ? s_g[0][kk * NP + n] : (T)0; }
+            } else if (kk < 2 * P2) {
+                if (STIFF) {
+                    av = lm < NK ? qx[P2 * NK + (kk - P2) * NK + lm] : (T)0;
+                    bv = nv ? s_g[1][(kk - P2) * NP + n] : (T)0;
+                }
+            }
+            u0 = MF::mma(av, bv, u0);
+        }
+        if (STIFF) {
+#pragma unroll
+            for (int k = 0; k < KB; ++k) {          // Us = QX0^T GK
+                const int kk = 4 * k + lk;
+                const T av = (kk < P2 && lm < NK) ? qx[kk * NK + lm] : (T)0;
+                const T bv = (kk < P2 && nv) ? s_g[1][kk * NP + n] : (T)0;
+                us = MF::mma(av, bv, us);
+            }
+        }
+        if (nv) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int k1 = MF::row(lane, r);
+                if (k1 < NK) {
+                    s_u[0][k1 * NP + n] = u0[r];
+                    if (STIFF) s_u[1][k1 * NP + n] = us[r];
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // direction 2: VA = QY0^T U0 + QY1^T Us, VB = QY0^T Us
+    for (int i = t; i < NV; i += NT) {
+        const int k1 = i / (NK * P1), k2 = (i / P1) % NK, b3 = i % P1;
+        T va = 0, vb = 0;
+#pragma unroll 5
+        for (int ab2 = 0; ab2 < P2; ++ab2) {
+            const T y0 = qy[ab2 * NK + k2];
+            va += y0 * s_u[0][k1 * NP + ab2 * P1 + b3];
+            if (STIFF) {
+                const T u = s_u[1][k1 * NP + ab2 * P1 + b3];
+                va += qy[P2 * NK + ab2 * NK + k2] * u;
+                vb += y0 * u;
+            }
+        }
+        s_v[0][i] = va;
+        if (STIFF) s_v[1][i] = vb;
+    }
+    __syncthreads();
+    // direction 3: Gmom share = QZ0^T VA + QZ1^T VB for this a3
+    for (int i = t; i < NK3; i += NT) {
+        const int k12 = i / NK, k3 = i % NK;
+        T g = 0;
+#pragma unroll
+        for (int b3 = 0; b3 < P1; ++b3) {
+            g += qz[(a3 * P1 + b3) * NK + k3] * s_v[0][k12 * P1 + b3];
+            if (STIFF) g += qz[P2 * NK + (a3 * P1 + b3) * NK + k3] * s_v[1][k12 * P1 + b3];
+        }
+        part[((int64_t)ce * P1 + a3) * NK3 + i] = g;
+    }
+}
+
+// k_adj_leaves: one workgroup per cut element sums the a3 shares of Gmom and evaluates
+// dL/dkappa at every point of its leaves: direction 1 once per x-group, direction 2 once per
+// column, direction 3 per leaf.  Every octree slot belongs to one element: plain stores.
+template <typename T, int P>
+__global__ void __launch_bounds__(256)
+k_adj_leaves(DevRules R, const T* __restrict__ part, T* __restrict__ dk) {
+    using C = MomCfg<P>;
+    constexpr int P1 = C::P1, P2 = C::P2, NP = C::NP, NK = C::NK, NK2 = C::NK2, NK3 = C::NK3, NT = C::NT;
+    constexpr int NB = C::NB, KW = C::KW, MAXC = C::MAXC, NZ = C::NZ, NY = C::NY;
+    __shared__ int s_cell[MAXC], s_key[MAXC];
+    __shared__ T s_bi[C::NIMAX * NK * P1];
+    __shared__ T s_gmom[NK3];
+    __shared__ T s_gy[NY];                          // [g1][k2 k3]
+    __shared__ T s_gz[NZ];                          // [g1 g2][k3]
+    __shared__ T s_w[2][NB * NP];                   // octree weights of a batch of leaves
+    const int ce = blockIdx.x;
+    const int t = threadIdx.x;
+    const int ni = (2 << R.levels) - 1;
+    for (int i = t; i < ni * NK * P1; i += NT) s_bi[i] = bern_i<T>(R)[i];
+    for (int i = t; i < NK3; i += NT) {
+        T g = 0;
+#pragma unroll
+        for (int a3 = 0; a3 < P1; ++a3) g += part[((int64_t)ce * P1 + a3) * NK3 + i];
+        s_gmom[i] = g;
+    }
+    const int64_t oct0 = R.n_grid + R.n_block;
+    const T* __restrict__ ow = oct_wt_a<T>(R);
+    const int cb = R.cell_begin[ce], cend = R.cell_begin[ce + 1];
+    auto ivl = [](int key, int d) { return (1 << (key & 7)) - 1 + ((key >> (3 + 6 * d)) & 63); };
+    const int xmask = (1 << 9) - 1, cmask = (1 << 15) - 1;
+    int kprev = -1;
+    T pw[KW];
+    for (int c0 = cb; c0 < cend; c0 += MAXC) {
+        const int nc = cend - c0 < MAXC ? cend - c0 : MAXC;
+        __syncthreads();
+        for (int j = t; j < nc; j += NT) {
+            const int cell = R.cell_perm[c0 + j];
+            s_cell[j] = cell;
+            s_key[j] = R.cell_key[cell];
+        }
+        __syncthreads();
+        auto issue = [&](int jb, int nb) {
+#pragma unroll
+            for (int i = 0; i < KW; ++i) {
+                const int idx = t + i * NT;
+                if (idx < nb * NP) pw[i] = ow[(int64_t)s_cell[jb + idx / NP] * NP + idx % NP];
+            }
+        };
+        const int nbat = (nc + NB - 1) / NB;
+        issue(0, nc < NB ? nc : NB);
+        for (int b = 0; b < nbat; ++b) {
+            const int jb = b * NB, nb = nc - jb < NB ? nc - jb : NB, buf = b & 1;
+#pragma unroll
+            for (int i = 0; i < KW; ++i) {
+                const int idx = t + i * NT;
+                if (idx < nb * NP) s_w[buf][idx] = pw[i];
+            }
+            __syncthreads();
+            if (b + 1 < nbat) issue(jb + NB, nc - jb - NB < NB ? nc - jb - NB : NB);
+            for (int jl = 0; jl < nb; ++jl) {
+                const int j = jb + jl;
+                const int key = s_key[j];
+                const bool new_x = kprev < 0 || (key & xmask) != (kprev & xmask);
+                const bool new_col = kprev < 0 || (key & cmask) != (kprev & cmask);
+                kprev = key;
+                if (new_col) {
+                    __syncthreads();                // earlier leaves are done with s_gz (and s_gy)
+                    if (new_x) {                    // Gy[g1][k2 k3] = sum_k1 B_k1(x_g1) Gmom[k1][k2 k3]
+                        const T* bx = s_bi + ivl(key, 0) * NK * P1;
+                        for (int i = t; i < NY; i += NT) {
+                            const int g1 = i / NK2, k23 = i % NK2;
+                            T s = 0;
+#pragma unroll
+                            for (int k1 = 0; k1 < NK; ++k1) s += bx[k1 * P1 + g1] * s_gmom[k1 * NK2 + k23];
+                            s_gy[i] = s;
+                        }
+                        __syncthreads();
+                    }
+                    // Gz[g1 g2][k3] = sum_k2 B_k2(y_g2) Gy[g1][k2][k3]
+                    const T* by = s_bi + ivl(key, 1) * NK * P1;
+                    for (int i = t; i < NZ; i += NT) {
+                        const int g1 = i / (P1 * NK), g2 = (i / NK) % P1, k3 = i % NK;
+                        T s = 0;
+#pragma unroll
+                        for (int k2 = 0; k2 < NK; ++k2) s += by[k2 * P1 + g2] * s_gy[g1 * NK2 + k2 * NK + k3];
+                        s_gz[i] = s;
+                    }
+                    __syncthreads();
+                }
+                // this leaf: dk(g) = w_g sum_k3 B_k3(z_g3) Gz[g1 g2][k3]
+                if (t < NP) {
+                    const T* bz = s_bi + ivl(key, 2) * NK * P1;
+                    const int g12 = t / P1, g3 = t % P1;
+                    T s = 0;
+#pragma unroll
+                    for (int k3 = 0; k3 < NK; ++k3) s += bz[k3 * P1 + g3] * s_gz[g12 * NK + k3];
+                    dk[oct0 + (int64_t)s_cell[j] * NP + t] = s_w[buf][jl * NP + t] * s;
+                }
+            }
+        }
+    }
+}
+
+template <typename T, int P, int WHICH>
+static int launch_adj_p(const wq_rules* H, const T* gm, const T* gk, T* dk, hipStream_t s) {
     const DevRules& R = H->R;
     if (R.n_lblocks > 0) {
         if constexpr (P <= 4) {
@@ -594,37 +831,55 @@ static void launch_adj_p(const wq_rules* H, const T* gm, const T* gk, T* dk, hip
                            dk);
     }
     if (R.n_cut_elems > 0) {
+        if constexpr (P <= 4) {
+            if (R.levels <= 3) {
+                using C = MomCfg<P>;
+                T* part = nullptr;
+                hipError_t err = H->scratch_alloc((void**)&part, sizeof(T) * (size_t)R.n_cut_elems * C::P1 * C::NK3, s);
+                if (err != hipSuccess)
+                    return wq_set_error(WQ_ENOMEM, "wq_assemble_adjoint: scratch allocation failed: %s", hipGetErrorString(err));
+                hipLaunchKernelGGL((k_adj_local<T, P, WHICH>), dim3((unsigned)(R.n_cut_elems * C::P1)), dim3(256), 0, s, R,
+                                   H->act2cut, gm, gk, part);
+                hipLaunchKernelGGL((k_adj_leaves<T, P>), dim3((unsigned)R.n_cut_elems), dim3(256), 0, s, R, (const T*)part, dk);
+                err = hipFreeAsync(part, s);
+                if (err != hipSuccess)
+                    return wq_set_error(WQ_EHIP, "wq_assemble_adjoint: scratch release failed: %s", hipGetErrorString(err));
+                return WQ_OK;
+            }
+        }
         using C = OctAdjCfg<P>;
         hipLaunchKernelGGL((k_adj_octree<T, P, WHICH>), dim3((unsigned)R.n_cut_elems), dim3(C::NT), 0, s, R,
                            H->act2cut, gm, gk, dk);
     }
+    return WQ_OK;
 }
 
 template <typename T, int P>
-static void launch_adj_w(const wq_rules* H, uint32_t which, const T* gm, const T* gk, T* dk, hipStream_t s) {
-    if (which == 1) launch_adj_p<T, P, 1>(H, gm, gk, dk, s);
-    else if (which == 2) launch_adj_p<T, P, 2>(H, gm, gk, dk, s);
-    else launch_adj_p<T, P, 3>(H, gm, gk, dk, s);
+static int launch_adj_w(const wq_rules* H, uint32_t which, const T* gm, const T* gk, T* dk, hipStream_t s) {
+    if (which == 1) return launch_adj_p<T, P, 1>(H, gm, gk, dk, s);
+    if (which == 2) return launch_adj_p<T, P, 2>(H, gm, gk, dk, s);
+    return launch_adj_p<T, P, 3>(H, gm, gk, dk, s);
 }
 
 template <typename T>
-void launch_adjoint(const wq_rules* H, uint32_t which, const T* gm, const T* gk, T* dk, hipStream_t s) {
+int launch_adjoint(const wq_rules* H, uint32_t which, const T* gm, const T* gk, T* dk, hipStream_t s) {
     const int64_t n = H->R.n_kappa;
     if (n > 0) hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, dk, n, (T)0);
-    if (H->nnz == 0) return;
+    if (H->nnz == 0) return WQ_OK;
     switch (H->R.p) {
-        case 1: launch_adj_w<T, 1>(H, which, gm, gk, dk, s); break;
-        case 2: launch_adj_w<T, 2>(H, which, gm, gk, dk, s); break;
-        case 3: launch_adj_w<T, 3>(H, which, gm, gk, dk, s); break;
-        case 4: launch_adj_w<T, 4>(H, which, gm, gk, dk, s); break;
-        case 5: launch_adj_w<T, 5>(H, which, gm, gk, dk, s); break;
-        case 6: launch_adj_w<T, 6>(H, which, gm, gk, dk, s); break;
+        case 1: return launch_adj_w<T, 1>(H, which, gm, gk, dk, s);
+        case 2: return launch_adj_w<T, 2>(H, which, gm, gk, dk, s);
+        case 3: return launch_adj_w<T, 3>(H, which, gm, gk, dk, s);
+        case 4: return launch_adj_w<T, 4>(H, which, gm, gk, dk, s);
+        case 5: return launch_adj_w<T, 5>(H, which, gm, gk, dk, s);
+        case 6: return launch_adj_w<T, 6>(H, which, gm, gk, dk, s);
     }
+    return WQ_OK;
 }
 
 #ifndef WQ_ONLY_F32
-template void launch_adjoint<double>(const wq_rules*, uint32_t, const double*, const double*, double*, hipStream_t);
+template int launch_adjoint<double>(const wq_rules*, uint32_t, const double*, const double*, double*, hipStream_t);
 #endif
 #ifndef WQ_ONLY_F64
-template void launch_adjoint<float>(const wq_rules*, uint32_t, const float*, const float*, float*, hipStream_t);
+template int launch_adjoint<float>(const wq_rules*, uint32_t, const float*, const float*, float*, hipStream_t);
 #endif

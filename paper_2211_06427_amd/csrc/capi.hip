@@ -133,9 +133,10 @@ int wq_assemble_adjoint(const wq_rules* r, int dtype, uint32_t which, const void
     int st = check_values(r, dtype, which, dk, gm, gk, "wq_assemble_adjoint");
     if (st) return st;
     if (dtype == WQ_F64)
-        launch_adjoint<double>(r, which, (const double*)gm, (const double*)gk, (double*)dk, (hipStream_t)stream);
+        st = launch_adjoint<double>(r, which, (const double*)gm, (const double*)gk, (double*)dk, (hipStream_t)stream);
     else
-        launch_adjoint<float>(r, which, (const float*)gm, (const float*)gk, (float*)dk, (hipStream_t)stream);
+        st = launch_adjoint<float>(r, which, (const float*)gm, (const float*)gk, (float*)dk, (hipStream_t)stream);
+    if (st) return st;
     return check_launch("wq_assemble_adjoint");
 }
 

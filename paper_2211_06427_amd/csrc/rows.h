@@ -8,4 +8,4 @@ void launch_rows(const wq_rules* H, uint32_t which, const T* kappa, T* vm, T* vk
 template <typename T>
 int launch_cut(const wq_rules* H, uint32_t which, uint32_t parts, const T* kappa, T* vm, T* vk, hipStream_t s);
 template <typename T>
-void launch_adjoint(const wq_rules* H, uint32_t which, const T* gm, const T* gk, T* dk, hipStream_t s);
+int launch_adjoint(const wq_rules* H, uint32_t which, const T* gm, const T* gk, T* dk, hipStream_t s);
