@@ -31,26 +31,36 @@ struct RowCfg {
     static constexpr int NT = GT >= 256 ? GT : 256;        // threads per block
     static constexpr int NG = NT / GT;                     // row groups
     static constexpr int NQ1 = 2 * RB + 4 * P;             // q1 slab bound
+    static constexpr int NWP = NW + 1;                     // padded stride of staged rows
     static constexpr bool STIFF = (WHICH & 2) != 0;
     static constexpr bool MASS = (WHICH & 1) != 0;
 };
 
-template <typename T, int P, int WHICH, int RB>
+// One workgroup per line block (or half of one: SPLIT = 2 processes RB rows of a block of
+// up to 2 RB).  Stages 1-2 contract directions 3 and 2 once for the block into the LDS slab
+// T2[q1][j2 j3] (mass) and Ts (stiffness, directions 2 and 3); stage 3 runs row by row with
+// the row's direction-1 weights staged in LDS one row ahead.
+template <typename T, int P, int WHICH, int RB, int SPLIT>
 __global__ void __launch_bounds__((RowCfg<T, P, WHICH, RB>::NT))
 k_rows_interior(DevRules R, const T* __restrict__ kappa, T* __restrict__ vm, T* __restrict__ vk) {
     using C = RowCfg<T, P, WHICH, RB>;
-    constexpr int M = C::M, NW = C::NW, MM = C::MM;
+    constexpr int M = C::M, NW = C::NW, MM = C::MM, NWP = C::NWP, NT = C::NT, NG = C::NG;
+    constexpr int W1N = 2 * M * NW;             // direction-1 weights of one row
     __shared__ T s_t00[C::NQ1 * MM];
     __shared__ T s_ts[C::STIFF ? C::NQ1 * MM : 1];
-    constexpr int NWP = NW + 1;                 // padded row stride of the staged weights
     __shared__ T s_w2[2 * M * NWP], s_w3[2 * M * NWP];
+    __shared__ T s_w1[NG][2][W1N];              // per row group, double buffered
 
-    const int4 blk = R.lblocks[blockIdx.x];
-    const int i1s = blk.x, i2 = blk.y, i3 = blk.z, nrows = blk.w;
+    const int4 blk = R.lblocks[blockIdx.x / SPLIT];
+    const int half = blockIdx.x % SPLIT;
+    const int i1s = blk.x + half * RB, i2 = blk.y, i3 = blk.z;
+    const int nrows = blk.w - half * RB < RB ? blk.w - half * RB : RB;
+    if (nrows <= 0) return;
+    const int t = threadIdx.x;
     const T* W1 = wt_table<T>(R, 0);
     const T* W2 = wt_table<T>(R, 1) + (int64_t)i2 * 2 * M * NW;
     const T* W3 = wt_table<T>(R, 2) + (int64_t)i3 * 2 * M * NW;
-    for (int k = threadIdx.x; k < 2 * M * NW; k += C::NT) {
+    for (int k = t; k < 2 * M * NW; k += NT) {
         s_w2[(k / NW) * NWP + k % NW] = W2[k];
         s_w3[(k / NW) * NWP + k % NW] = W3[k];
     }
@@ -60,12 +70,12 @@ k_rows_interior(DevRules R, const T* __restrict__ kappa, T* __restrict__ vm, T* 
     const int xs2 = R.xs[1][i2], nw2 = R.nwin[1][i2];
     const int xs3 = R.xs[2][i3], nw3 = R.nwin[2][i3];
     const int nx2 = R.nx[1], nx3 = R.nx[2];
-    __syncthreads();
 
-    // stages 1-2: one item per (q1, j3).  For each q2 the direction-3 sums T1_a(q1,q2,j3)
-    // are formed and immediately folded into the direction-2 sums over all j2, so only
-    // the 2M stage-2 accumulators stay live.
-    for (int it = threadIdx.x; it < nq1 * M; it += C::NT) {
+    // ---- stages 1-2: one item per (q1, j3).  For each q2 the direction-3 sums T1_v(q1,q2,j3)
+    // are formed from one row of kappa (all its loads issued together) and folded at once
+    // into the direction-2 sums over all j2, so only the 2M stage-2 accumulators stay live.
+    __syncthreads();
+    for (int it = t; it < nq1 * M; it += NT) {
         const int q1 = it / M, j3 = it % M;
         const T* kap = kappa + ((int64_t)(qbase + q1) * nx2 + xs2) * nx3 + xs3;
         T m0[M], ms[M];
@@ -73,11 +83,14 @@ k_rows_interior(DevRules R, const T* __restrict__ kappa, T* __restrict__ vm, T* 
         for (int j2 = 0; j2 < M; ++j2) { m0[j2] = 0; ms[j2] = 0; }
         for (int q2 = 0; q2 < nw2; ++q2) {
             const T* kq = kap + (int64_t)q2 * nx3;
+            T kv[NW];
+#pragma unroll
+            for (int q3 = 0; q3 < NW; ++q3) kv[q3] = q3 < nw3 ? kq[q3] : (T)0;
             T a0 = 0, a1 = 0;
-            for (int q3 = 0; q3 < nw3; ++q3) {
-                const T kv = kq[q3];
-                a0 += s_w3[j3 * NWP + q3] * kv;
-                if (C::STIFF) a1 += s_w3[(M + j3) * NWP + q3] * kv;
+#pragma unroll
+            for (int q3 = 0; q3 < NW; ++q3) {
+                a0 += s_w3[j3 * NWP + q3] * kv[q3];
+                if (C::STIFF) a1 += s_w3[(M + j3) * NWP + q3] * kv[q3];
             }
 #pragma unroll
             for (int j2 = 0; j2 < M; ++j2) {
@@ -92,11 +105,10 @@ k_rows_interior(DevRules R, const T* __restrict__ kappa, T* __restrict__ vm, T* 
             if (C::STIFF) s_ts[q1 * MM + j2 * M + j3] = ms[j2];
         }
     }
-    __syncthreads();
 
-    // stage 3: row groups of GT lanes, one lane per (j2, j3)
-    const int grp = uniform(threadIdx.x / C::GT);
-    const int c = threadIdx.x % C::GT;
+    // ---- stage 3: row groups of GT lanes, one lane per (j2, j3) ----
+    const int grp = __builtin_amdgcn_readfirstlane(t / C::GT);
+    const int c = t % C::GT;
     const int jj2 = c / M, jj3 = c % M;
     const int p = P;
     const int I2 = i2, I3 = i3;
@@ -105,65 +117,91 @@ k_rows_interior(DevRules R, const T* __restrict__ kappa, T* __restrict__ vm, T* 
     const int m2 = hi2 - lo2 + 1, m3 = hi3 - lo3 + 1;
     const bool live = c < MM && jj2 >= lo2 && jj2 <= hi2 && jj3 >= lo3 && jj3 <= hi3;
     const int64_t nl = (int64_t)R.nfun[1] * R.nfun[2];
-    for (int r = grp; r < nrows; r += C::NG) {
-        const int i1 = uniform(i1s + r);
-        const int ra = uniform(R.lex2act[(int64_t)i1 * nl + (int64_t)I2 * R.nfun[2] + I3]);
-        const int64_t base = R.row_ptr[ra];
-        const int off = uniform(R.xs[0][i1] - qbase);
-        const int nw1 = uniform(R.nwin[0][i1]);
-        const int lo1 = i1 - p < 0 ? p - i1 : 0, hi1 = i1 + p > R.nfun[0] - 1 ? R.nfun[0] - 1 - i1 + p : 2 * p;
-        T t00[NW], ts[NW];
+    // first row of each group: its weights
+    if (grp < nrows)
+        for (int k = c; k < W1N; k += C::GT) s_w1[grp][0][k] = W1[(int64_t)(i1s + grp) * W1N + k];
+    __syncthreads();                            // slab and first weights ready
+    int wb = 0;
+    for (int r0 = 0; r0 < nrows; r0 += NG) {
+        const int r = r0 + grp;
+        const bool active = r < nrows;
+        // weights of this group's next row, loaded now and stored after this row
+        T nw[(W1N + C::GT - 1) / C::GT];
+        const bool has_next = r + NG < nrows;
 #pragma unroll
-        for (int q = 0; q < NW; ++q) {
-            t00[q] = 0; ts[q] = 0;
-            if (live && q < nw1) {
-                t00[q] = s_t00[(off + q) * MM + c];
-                if (C::STIFF) ts[q] = s_ts[(off + q) * MM + c];
-            }
+        for (int i = 0; i < (W1N + C::GT - 1) / C::GT; ++i) {
+            const int k = c + i * C::GT;
+            nw[i] = (has_next && k < W1N) ? W1[(int64_t)(i1s + r + NG) * W1N + k] : (T)0;
         }
-        const T* w10 = W1 + (int64_t)i1 * 2 * M * NW;
-        const T* w11 = w10 + M * NW;
-        // A row whose window has two points in each of its p+1 elements (no boundary
-        // element) has W1[jj1][q] != 0 only for q in [2 max(0, jj1-p), 2 (min(p, jj1)+1)):
-        // that range is a compile-time constant.  Other rows loop over the padded window.
-        const bool regular = nw1 == 2 * P + 2 && lo1 == 0 && hi1 == 2 * P;
-        if (regular) {
+        if (active) {
+            const int i1 = __builtin_amdgcn_readfirstlane(i1s + r);
+            const int ra = __builtin_amdgcn_readfirstlane(R.lex2act[(int64_t)i1 * nl + (int64_t)I2 * R.nfun[2] + I3]);
+            const int64_t base = R.row_ptr[ra];
+            const int off = __builtin_amdgcn_readfirstlane(R.xs[0][i1] - qbase);
+            const int nw1 = __builtin_amdgcn_readfirstlane(R.nwin[0][i1]);
+            const int lo1 = i1 - p < 0 ? p - i1 : 0, hi1 = i1 + p > R.nfun[0] - 1 ? R.nfun[0] - 1 - i1 + p : 2 * p;
+            T t00[NW], ts[NW];
 #pragma unroll
-            for (int jj1 = 0; jj1 < M; ++jj1) {
-                const int qa = 2 * (jj1 - P > 0 ? jj1 - P : 0);
-                const int qb = 2 * ((jj1 < P ? jj1 : P) + 1);
-                T am = 0, ak = 0;
+            for (int q = 0; q < NW; ++q) {
+                t00[q] = 0; ts[q] = 0;
+                if (live && q < nw1) {
+                    t00[q] = s_t00[(off + q) * MM + c];
+                    if (C::STIFF) ts[q] = s_ts[(off + q) * MM + c];
+                }
+            }
+            const T* w10 = s_w1[grp][wb];
+            const T* w11 = w10 + M * NW;
+            // A row whose window has two points in each of its p+1 elements (no boundary
+            // element) has W1[jj1][q] != 0 only for q in [2 max(0, jj1-p), 2 (min(p, jj1)+1)):
+            // that range is a compile-time constant.  Other rows loop over the padded window.
+            const bool regular = nw1 == 2 * P + 2 && lo1 == 0 && hi1 == 2 * P;
+            if (regular) {
 #pragma unroll
-                for (int q = 0; q < 2 * P + 2; ++q) {
-                    if (q >= qa && q < qb) {
+                for (int jj1 = 0; jj1 < M; ++jj1) {
+                    const int qa = 2 * (jj1 - P > 0 ? jj1 - P : 0);
+                    const int qb = 2 * ((jj1 < P ? jj1 : P) + 1);
+                    T am = 0, ak = 0;
+#pragma unroll
+                    for (int q = 0; q < 2 * P + 2; ++q) {
+                        if (q >= qa && q < qb) {
+                            const T a = w10[jj1 * NW + q];
+                            if (C::MASS) am += a * t00[q];
+                            if (C::STIFF) ak += w11[jj1 * NW + q] * t00[q] + a * ts[q];
+                        }
+                    }
+                    if (live) {
+                        const int64_t o = base + ((int64_t)jj1 * m2 + (jj2 - lo2)) * m3 + (jj3 - lo3);
+                        if (C::MASS) vm[o] = am;
+                        if (C::STIFF) vk[o] = ak;
+                    }
+                }
+            } else {
+#pragma unroll 1
+                for (int jj1 = lo1; jj1 <= hi1; ++jj1) {
+                    T am = 0, ak = 0;
+#pragma unroll
+                    for (int q = 0; q < NW; ++q) {
                         const T a = w10[jj1 * NW + q];
                         if (C::MASS) am += a * t00[q];
                         if (C::STIFF) ak += w11[jj1 * NW + q] * t00[q] + a * ts[q];
                     }
-                }
-                if (live) {
-                    const int64_t o = base + ((int64_t)jj1 * m2 + (jj2 - lo2)) * m3 + (jj3 - lo3);
-                    if (C::MASS) vm[o] = am;
-                    if (C::STIFF) vk[o] = ak;
-                }
-            }
-        } else {
-#pragma unroll 1
-            for (int jj1 = lo1; jj1 <= hi1; ++jj1) {
-                T am = 0, ak = 0;
-#pragma unroll
-                for (int q = 0; q < NW; ++q) {
-                    const T a = w10[jj1 * NW + q];
-                    if (C::MASS) am += a * t00[q];
-                    if (C::STIFF) ak += w11[jj1 * NW + q] * t00[q] + a * ts[q];
-                }
-                if (live) {
-                    const int64_t o = base + ((int64_t)(jj1 - lo1) * m2 + (jj2 - lo2)) * m3 + (jj3 - lo3);
-                    if (C::MASS) vm[o] = am;
-                    if (C::STIFF) vk[o] = ak;
+                    if (live) {
+                        const int64_t o = base + ((int64_t)(jj1 - lo1) * m2 + (jj2 - lo2)) * m3 + (jj3 - lo3);
+                        if (C::MASS) vm[o] = am;
+                        if (C::STIFF) vk[o] = ak;
+                    }
                 }
             }
         }
+        if (has_next) {
+#pragma unroll
+            for (int i = 0; i < (W1N + C::GT - 1) / C::GT; ++i) {
+                const int k = c + i * C::GT;
+                if (k < W1N) s_w1[grp][wb ^ 1][k] = nw[i];
+            }
+        }
+        wb ^= 1;
+        __syncthreads();
     }
 }
 
@@ -308,12 +346,20 @@ template <typename T, int P, int WHICH>
 static void launch_rows_p(const wq_rules* H, const T* kappa, T* vm, T* vk, hipStream_t s) {
     const DevRules& R = H->R;
     if (R.n_lblocks > 0) {
-        if constexpr (P <= 4) {
+        // line blocks hold up to 16 rows for p <= 4 and 8 above; FP64 at p <= 4 takes half a
+        // block per workgroup to bound its LDS slab
+        if constexpr (P <= 4 && sizeof(T) == 4) {
             using C = RowCfg<T, P, WHICH, 16>;
-            hipLaunchKernelGGL((k_rows_interior<T, P, WHICH, 16>), dim3((unsigned)R.n_lblocks), dim3(C::NT), 0, s, R, kappa, vm, vk);
+            hipLaunchKernelGGL((k_rows_interior<T, P, WHICH, 16, 1>), dim3((unsigned)R.n_lblocks), dim3(C::NT), 0, s, R, kappa,
+                               vm, vk);
+        } else if constexpr (P <= 4) {
+            using C = RowCfg<T, P, WHICH, 8>;
+            hipLaunchKernelGGL((k_rows_interior<T, P, WHICH, 8, 2>), dim3((unsigned)(2 * R.n_lblocks)), dim3(C::NT), 0, s, R,
+                               kappa, vm, vk);
         } else {
             using C = RowCfg<T, P, WHICH, 8>;
-            hipLaunchKernelGGL((k_rows_interior<T, P, WHICH, 8>), dim3((unsigned)R.n_lblocks), dim3(C::NT), 0, s, R, kappa, vm, vk);
+            hipLaunchKernelGGL((k_rows_interior<T, P, WHICH, 8, 1>), dim3((unsigned)R.n_lblocks), dim3(C::NT), 0, s, R, kappa,
+                               vm, vk);
         }
     }
     if (R.n_cut > 0)
