@@ -96,6 +96,7 @@ typedef struct {
     int64_t n_oct_xgroups;   /* octree leaves grouped by (cut element, depth, x offset) */
     int64_t n_oct_columns;   /* octree leaves grouped by (cut element, depth, x and y offsets) */
     int64_t n_rem_pairs;     /* (cut row, element Gauss remainder element) pairs */
+    int64_t n_gauss_elems;   /* interior elements (inputs of gauss_assemble) */
     int32_t grid_dims[3];    /* |X_d| */
     int32_t nfun[3];         /* functions per direction, nel[d] + p */
     const int64_t* row_ptr;        /* (n_active+1) CSR row pointer */
@@ -144,6 +145,20 @@ int cut_assemble(const wq_rules* rules, int dtype, uint32_t which, const void* k
  * its bit is absent from which. */
 int wq_assemble_adjoint(const wq_rules* rules, int dtype, uint32_t which, const void* G_mass,
                         const void* G_stiff, void* dkappa, void* stream);
+
+/* Conventional assembly for comparison (Section 3.1, "Standard Gauss"): element by element,
+ * (p+1)^3 Gauss points on every interior element and the octree points on every cut element,
+ * local matrices added into the same pattern.  OVERWRITES all nnz entries of each requested
+ * matrix.  kappa_gauss: (n_gauss_elems * (p+1)^3) values at the points wq_gauss_coords lists;
+ * kappa: the slot vector of the other calls (its octree slots are read).  p <= 4 and octree
+ * depth <= 3 only (WQ_EUNSUPPORTED otherwise).  Uses atomics: summation order varies. */
+int gauss_assemble(const wq_rules* rules, int dtype, uint32_t which, const void* kappa_gauss, const void* kappa,
+                   void* vals_mass, void* vals_stiff, void* stream);
+
+/* Coordinates of the Gauss points of every interior element, (n_gauss_elems * (p+1)^3, 3)
+ * doubles written to the caller's device buffer xyz: elements in lexicographic order, points
+ * in lexicographic Gauss order (first direction slowest). */
+int wq_gauss_coords(const wq_rules* rules, double* xyz, void* stream);
 
 void wq_rules_free(wq_rules* rules);
 const char* wq_last_error(void);

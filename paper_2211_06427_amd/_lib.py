@@ -13,7 +13,7 @@ WQ_CUT_REMAINDER, WQ_CUT_OCTREE = 4, 8
 STATUS = {0: "WQ_OK", -1: "WQ_EINVAL", -2: "WQ_ENOMEM", -3: "WQ_EHIP", -4: "WQ_ESINGULAR", -5: "WQ_EUNSUPPORTED"}
 
 EXPORTS = ["wq_build_rules", "wq_rules_info_get", "wq_assemble_rows", "cut_assemble", "wq_assemble_adjoint",
-           "wq_rules_free", "wq_last_error"]
+           "wq_rules_free", "wq_last_error", "gauss_assemble", "wq_gauss_coords"]
 
 
 class WqMesh(C.Structure):
@@ -33,7 +33,7 @@ class WqRulesInfo(C.Structure):
     _fields_ = [(k, C.c_int64) for k in ("n_active", "nnz", "n_rows_interior", "n_rows_cut", "n_rows_split",
                                          "n_dwq_rules", "n_kappa", "n_grid", "n_block", "n_octree",
                                          "n_block_elems", "n_cut_elems", "n_cells", "n_line_blocks",
-                                         "n_oct_xgroups", "n_oct_columns", "n_rem_pairs")] + [
+                                         "n_oct_xgroups", "n_oct_columns", "n_rem_pairs", "n_gauss_elems")] + [
         ("grid_dims", C.c_int32 * 3), ("nfun", C.c_int32 * 3),
         ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p), ("active_to_lex", C.c_void_p),
         ("kappa_xyz", C.c_void_p), ("octree_w", C.c_void_p), ("block_elems", C.c_void_p),
@@ -63,6 +63,8 @@ def load(path: str = LIB_PATH):
     for f in (lib.wq_assemble_rows, lib.cut_assemble):
         f.argtypes = [vp, i32, u32, vp, vp, vp, vp]
     lib.wq_assemble_adjoint.argtypes = [vp, i32, u32, vp, vp, vp, vp]
+    lib.gauss_assemble.argtypes = [vp, i32, u32, vp, vp, vp, vp, vp]
+    lib.wq_gauss_coords.argtypes = [vp, vp, vp]
     lib.wq_rules_free.argtypes = [vp]
     lib.wq_rules_free.restype = None
     lib.wq_last_error.restype = C.c_char_p

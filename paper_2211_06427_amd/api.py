@@ -60,7 +60,7 @@ class Rules:
         self._info = info
         for k in ("n_active", "nnz", "n_rows_interior", "n_rows_cut", "n_rows_split", "n_dwq_rules", "n_kappa",
                   "n_grid", "n_block", "n_octree", "n_block_elems", "n_cut_elems", "n_cells", "n_line_blocks",
-                  "n_oct_xgroups", "n_oct_columns", "n_rem_pairs"):
+                  "n_oct_xgroups", "n_oct_columns", "n_rem_pairs", "n_gauss_elems"):
             setattr(self, k, int(getattr(info, k)))
         self.grid_dims = tuple(info.grid_dims)
         self.nfun = tuple(info.nfun)
@@ -148,6 +148,27 @@ class Rules:
         vk = torch.empty(self.nnz, dtype=kappa.dtype, device=self.device) if which & L.WQ_STIFF else None
         self.assemble_rows(kappa, vm, vk, which)
         self.cut_assemble(kappa, vm, vk, which)
+        return vm, vk
+
+    def gauss_coords(self):
+        """(n_gauss_elems * (p+1)^3, 3) coordinates of the interior elements' Gauss points."""
+        n = self.n_gauss_elems * (self.degree + 1) ** 3
+        out = torch.empty((n, 3), dtype=torch.float64, device=self.device)
+        if n > 0:
+            with torch.cuda.device(self.device):
+                L.check(L.load().wq_gauss_coords(self._h, C.c_void_p(out.data_ptr()),
+                                                 C.c_void_p(_stream_handle(self.device))))
+        return out
+
+    def gauss_assemble(self, kappa_gauss, kappa, which=L.WQ_MASS | L.WQ_STIFF):
+        """Conventional element-by-element Gauss assembly of the same matrices (comparison)."""
+        dtype = kappa.dtype
+        _need(kappa_gauss, self.n_gauss_elems * (self.degree + 1) ** 3, dtype, self.device, "kappa_gauss")
+        _need(kappa, self.n_kappa, dtype, self.device, "kappa")
+        vm = torch.empty(self.nnz, dtype=dtype, device=self.device) if which & L.WQ_MASS else None
+        vk = torch.empty(self.nnz, dtype=dtype, device=self.device) if which & L.WQ_STIFF else None
+        L.check(L.load().gauss_assemble(self._h, _DT[dtype], int(which), _ptr(kappa_gauss), _ptr(kappa), _ptr(vm),
+                                        _ptr(vk), C.c_void_p(_stream_handle(self.device))))
         return vm, vk
 
     def adjoint(self, g_mass=None, g_stiff=None, out=None):

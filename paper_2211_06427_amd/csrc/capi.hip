@@ -89,6 +89,7 @@ int wq_rules_info_get(const wq_rules* r, wq_rules_info* out) {
     out->n_oct_xgroups = r->n_oct_xgroups;
     out->n_oct_columns = r->n_oct_columns;
     out->n_rem_pairs = r->n_rem_pairs;
+    out->n_gauss_elems = r->n_int_elems;
     for (int d = 0; d < 3; ++d) { out->grid_dims[d] = R.nx[d]; out->nfun[d] = R.nfun[d]; }
     out->row_ptr = R.row_ptr;
     out->col_idx = R.col_idx;
@@ -138,6 +139,28 @@ int wq_assemble_adjoint(const wq_rules* r, int dtype, uint32_t which, const void
         st = launch_adjoint<float>(r, which, (const float*)gm, (const float*)gk, (float*)dk, (hipStream_t)stream);
     if (st) return st;
     return check_launch("wq_assemble_adjoint");
+}
+
+int wq_gauss_coords(const wq_rules* r, double* xyz, void* stream) {
+    if (!r || !xyz) return wq_set_error(WQ_EINVAL, "wq_gauss_coords: NULL argument");
+    launch_gauss_coords(r, xyz, (hipStream_t)stream);
+    return check_launch("wq_gauss_coords");
+}
+
+int gauss_assemble(const wq_rules* r, int dtype, uint32_t which, const void* kappa_gauss, const void* kappa, void* vm,
+                   void* vk, void* stream) {
+    int st = check_values(r, dtype, which, kappa, vm, vk, "gauss_assemble");
+    if (st) return st;
+    if (!kappa_gauss && r->n_int_elems > 0) return wq_set_error(WQ_EINVAL, "gauss_assemble: kappa_gauss is NULL");
+    if (r->nnz == 0) return WQ_OK;
+    if (dtype == WQ_F64)
+        st = launch_gauss<double>(r, which, (const double*)kappa_gauss, (const double*)kappa, (double*)vm, (double*)vk,
+                                  (hipStream_t)stream);
+    else
+        st = launch_gauss<float>(r, which, (const float*)kappa_gauss, (const float*)kappa, (float*)vm, (float*)vk,
+                                 (hipStream_t)stream);
+    if (st) return st;
+    return check_launch("gauss_assemble");
 }
 
 void wq_rules_free(wq_rules* r) {

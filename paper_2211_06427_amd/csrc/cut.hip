@@ -546,9 +546,12 @@ k_cut_moments(DevRules R, const T* __restrict__ kappa, T* __restrict__ mom) {
 // (directions 3 and 2 on the vector ALU, direction 1 on matrix cores) and stores the local
 // rows a = (a1, a2, a3) of both matrices, loc[((ce P1 + a3) 2 + v) P1^2 + (a1 P1 + a2)][b],
 // through LDS so that every row is one contiguous run.
-template <typename T, int P, int WHICH>
+// SCATTER = false: store the local rows (cut-element path).  SCATTER = true: add them into
+// the CSR values with atomics, element by element (the conventional assembly).
+template <typename T, int P, int WHICH, bool SCATTER = false>
 __global__ void __launch_bounds__(256)
-k_cut_local(DevRules R, const T* __restrict__ mom, T* __restrict__ loc) {
+k_cut_local(DevRules R, const int32_t* __restrict__ elems, const T* __restrict__ mom, T* __restrict__ loc,
+            const int32_t* __restrict__ act2cut, T* __restrict__ vm, T* __restrict__ vk) {
     using C = MomCfg<P>;
     using MF = MfmaOp<T>;
     using v4 = typename MF::v4;
@@ -565,8 +568,10 @@ k_cut_local(DevRules R, const T* __restrict__ mom, T* __restrict__ loc) {
     T* s_s2 = s_u + 2 * NS1;                        // [2][NS2]
     T* s_blk = s_u;                                 // [(a1 a2)][b] after the contractions
 
+    __shared__ int64_t s_rb[SCATTER ? P2 : 1];
+    __shared__ int32_t s_cr[SCATTER ? P2 : 1];
     const int ce = blockIdx.x / P1, a3 = blockIdx.x % P1;
-    const int64_t eid = R.cut_elems[ce];
+    const int64_t eid = elems[ce];
     int e[3];
     unlex3i(eid, R.nel, e);
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
@@ -576,6 +581,13 @@ k_cut_local(DevRules R, const T* __restrict__ mom, T* __restrict__ loc) {
         s_q[d][i % QN] = bern_q<T>(R, d)[(int64_t)e[d] * QN + i % QN];
     }
     for (int i = t; i < NK3; i += NT) s_mom[i] = mom[(int64_t)ce * NK3 + i];
+    if (SCATTER && t < P2) {                        // rows a = e + (a1, a2, a3)
+        const int a1 = t / P1, a2 = t % P1;
+        const int64_t alex = ((int64_t)(e[0] + a1) * R.nfun[1] + (e[1] + a2)) * R.nfun[2] + (e[2] + a3);
+        const int ra = R.lex2act[alex];
+        s_rb[t] = R.row_ptr[ra];
+        s_cr[t] = act2cut[ra];
+    }
     __syncthreads();
     const T* qx = s_q[0];
     const T* qy = s_q[1];
@@ -655,11 +667,11 @@ k_cut_local(DevRules R, const T* __restrict__ mom, T* __restrict__ loc) {
             }
         }
     }
-    // stage each matrix's block as [(a1 a2)][(b1 b2 b3)] and store it
+    // stage each matrix's block as [(a1 a2)][(b1 b2 b3)] and store (or add) it
 #pragma unroll
     for (int v = 0; v < 2; ++v) {
         if ((v == 0 && !MASS) || (v == 1 && !STIFF)) continue;
-        T* out = loc + ((int64_t)(ce * P1 + a3) * 2 + v) * NBLK;
+        T* out = SCATTER ? (v == 0 ? vm : vk) : loc + ((int64_t)(ce * P1 + a3) * 2 + v) * NBLK;
         __syncthreads();                            // s_u is free (contractions / previous scatter done)
 #pragma unroll
         for (int ti = 0; ti < NTW; ++ti) {
@@ -679,7 +691,26 @@ k_cut_local(DevRules R, const T* __restrict__ mom, T* __restrict__ loc) {
                 }
         }
         __syncthreads();
-        for (int i = t; i < NBLK; i += NT) out[i] = s_blk[i];
+        if (!SCATTER) {
+            for (int i = t; i < NBLK; i += NT) out[i] = s_blk[i];
+        } else {
+            for (int i = t; i < NBLK; i += NT) {
+                const int r = i / NP, b = i % NP, a1 = r / P1, a2 = r % P1;
+                const int b1 = b / P2, b2 = (b / P1) % P1, b3 = b % P1;
+                const int jj1 = b1 - a1 + P, jj2 = b2 - a2 + P, jj3 = b3 - a3 + P;
+                int o;
+                if (s_cr[r] >= 0) {
+                    o = R.pos_map[(int64_t)s_cr[r] * M3 + (jj1 * M + jj2) * M + jj3];
+                } else {                            // interior row: its full window is stored
+                    const int I1 = e[0] + a1, I2 = e[1] + a2, I3 = e[2] + a3;
+                    const int lo1 = I1 - P < 0 ? P - I1 : 0;
+                    const int lo2 = I2 - P < 0 ? P - I2 : 0, hi2 = I2 + P > R.nfun[1] - 1 ? R.nfun[1] - 1 - I2 + P : 2 * P;
+                    const int lo3 = I3 - P < 0 ? P - I3 : 0, hi3 = I3 + P > R.nfun[2] - 1 ? R.nfun[2] - 1 - I3 + P : 2 * P;
+                    o = ((jj1 - lo1) * (hi2 - lo2 + 1) + (jj2 - lo2)) * (hi3 - lo3 + 1) + (jj3 - lo3);
+                }
+                if (o >= 0) atomicAdd(&out[s_rb[r] + o], s_blk[i]);
+            }
+        }
     }
 }
 
@@ -754,6 +785,134 @@ k_cut_gather(DevRules R, const T* __restrict__ loc, T* __restrict__ vm, T* __res
 }
 
 // ----------------------------------------------------------------------------------------
+// Conventional element-by-element Gauss assembly (the reference scheme of Section 3.1:
+// Gauss rules on every interior element, the octree on cut elements), for comparison.
+// Every element's local matrices are formed from its moments (Gauss points for interior
+// elements, octree points for cut elements) and added into the values with atomics.
+// ----------------------------------------------------------------------------------------
+// Moments of one interior element from its (p+1)^3 Gauss points (kappa_gauss in the
+// element's lexicographic Gauss order); the Bernstein values at the Gauss points of the
+// whole element are the depth-0 row of the interval table.
+template <typename T, int P>
+__global__ void __launch_bounds__(256)
+k_gauss_moments(DevRules R, const T* __restrict__ kg, const double* __restrict__ gw, T* __restrict__ mom) {
+    using C = MomCfg<P>;
+    constexpr int P1 = C::P1, P2 = C::P2, NP = C::NP, NK = C::NK, NK2 = C::NK2, NK3 = C::NK3, NT = C::NT;
+    __shared__ T s_wk[NP], s_mz[P2 * NK], s_my[P1 * NK2], s_b[NK * P1];
+    const int64_t el = blockIdx.x;
+    const int t = threadIdx.x;
+    const double vol = R.h[0] * R.h[1] * R.h[2] / 8.0;
+    if (t < NP) {
+        const int g1 = t / P2, g2 = (t / P1) % P1, g3 = t % P1;
+        s_wk[t] = (T)(gw[g1] * gw[g2] * gw[g3] * vol) * kg[el * NP + t];
+    }
+    if (t < NK * P1) s_b[t] = bern_i<T>(R)[t];
+    __syncthreads();
+    for (int i = t; i < P2 * NK; i += NT) {          // [g1 g2][k3]
+        const int g12 = i / NK, k3 = i % NK;
+        T s = 0;
+#pragma unroll
+        for (int g3 = 0; g3 < P1; ++g3) s += s_b[k3 * P1 + g3] * s_wk[g12 * P1 + g3];
+        s_mz[i] = s;
+    }
+    __syncthreads();
+    for (int i = t; i < P1 * NK2; i += NT) {         // [g1][k2 k3]
+        const int g1 = i / NK2, k2 = (i / NK) % NK, k3 = i % NK;
+        T s = 0;
+#pragma unroll
+        for (int g2 = 0; g2 < P1; ++g2) s += s_b[k2 * P1 + g2] * s_mz[(g1 * P1 + g2) * NK + k3];
+        s_my[i] = s;
+    }
+    __syncthreads();
+    for (int i = t; i < NK3; i += NT) {              // [k1][k2 k3]
+        const int k1 = i / NK2, k23 = i % NK2;
+        T s = 0;
+#pragma unroll
+        for (int g1 = 0; g1 < P1; ++g1) s += s_b[k1 * P1 + g1] * s_my[g1 * NK2 + k23];
+        mom[el * NK3 + i] = s;
+    }
+}
+
+template <typename T>
+__global__ void k_zero(T* p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = (T)0;
+}
+
+template <typename T, int P, int WHICH>
+static int launch_gauss_p(const wq_rules* H, const T* kg, const T* kappa, T* vm, T* vk, hipStream_t s) {
+    const DevRules& R = H->R;
+    using C = MomCfg<P>;
+    const int64_t ni = H->n_int_elems, nc = R.n_cut_elems, ne = ni + nc;
+    const unsigned zb = (unsigned)((H->nnz + 255) / 256);
+    if ((WHICH & 1)) hipLaunchKernelGGL(k_zero<T>, dim3(zb), dim3(256), 0, s, vm, H->nnz);
+    if ((WHICH & 2)) hipLaunchKernelGGL(k_zero<T>, dim3(zb), dim3(256), 0, s, vk, H->nnz);
+    if (ne == 0) return WQ_OK;
+    T* mom = nullptr;
+    hipError_t err = H->scratch_alloc((void**)&mom, sizeof(T) * (size_t)ne * C::NK3, s);
+    if (err != hipSuccess) return wq_set_error(WQ_ENOMEM, "gauss_assemble: scratch allocation failed: %s", hipGetErrorString(err));
+    if (ni > 0) {
+        hipLaunchKernelGGL((k_gauss_moments<T, P>), dim3((unsigned)ni), dim3(256), 0, s, R, kg, (const double*)H->gw, mom);
+        hipLaunchKernelGGL((k_cut_local<T, P, WHICH, true>), dim3((unsigned)(ni * (P + 1))), dim3(256), 0, s, R, H->int_elems,
+                           (const T*)mom, (T*)nullptr, H->act2cut, vm, vk);
+    }
+    if (nc > 0) {
+        T* mc = mom + (size_t)ni * C::NK3;
+        hipLaunchKernelGGL((k_cut_moments<T, P>), dim3((unsigned)nc), dim3(256), 0, s, R, kappa, mc);
+        hipLaunchKernelGGL((k_cut_local<T, P, WHICH, true>), dim3((unsigned)(nc * (P + 1))), dim3(256), 0, s, R, R.cut_elems,
+                           (const T*)mc, (T*)nullptr, H->act2cut, vm, vk);
+    }
+    err = hipFreeAsync(mom, s);
+    if (err != hipSuccess) return wq_set_error(WQ_EHIP, "gauss_assemble: scratch release failed: %s", hipGetErrorString(err));
+    return WQ_OK;
+}
+
+template <typename T>
+int launch_gauss(const wq_rules* H, uint32_t which, const T* kg, const T* kappa, T* vm, T* vk, hipStream_t s) {
+    if (H->R.levels > 3) return wq_set_error(WQ_EUNSUPPORTED, "gauss_assemble: octree depth above 3 is not supported");
+    switch (H->R.p) {
+#define WQ_GAUSS_CASE(PP)                                                                                          \
+    case PP:                                                                                                       \
+        if (which == 1) return launch_gauss_p<T, PP, 1>(H, kg, kappa, vm, vk, s);                                  \
+        if (which == 2) return launch_gauss_p<T, PP, 2>(H, kg, kappa, vm, vk, s);                                  \
+        return launch_gauss_p<T, PP, 3>(H, kg, kappa, vm, vk, s);
+        WQ_GAUSS_CASE(1)
+        WQ_GAUSS_CASE(2)
+        WQ_GAUSS_CASE(3)
+        WQ_GAUSS_CASE(4)
+#undef WQ_GAUSS_CASE
+    }
+    return wq_set_error(WQ_EUNSUPPORTED, "gauss_assemble: degree above 4 is not supported");
+}
+
+#ifndef WQ_ONLY_F32
+// coordinates of the Gauss points of every interior element (lexicographic elements, then
+// lexicographic Gauss points), the order kappa_gauss is read in
+__global__ void k_gauss_coords(DevRules R, const int32_t* elems, int64_t n, const double* gxi, double* xyz) {
+    const int p1 = R.p + 1, np = p1 * p1 * p1;
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= n * np) return;
+    const int64_t el = id / np;
+    const int q = (int)(id % np), g[3] = {q / (p1 * p1), (q / p1) % p1, q % p1};
+    int e[3];
+    unlex3i(elems[el], R.nel, e);
+    for (int d = 0; d < 3; ++d) xyz[id * 3 + d] = R.lo[d] + (e[d] + (1.0 + gxi[g[d]]) / 2.0) * R.h[d];
+}
+
+int launch_gauss_coords(const wq_rules* H, double* xyz, hipStream_t s) {
+    const int64_t n = H->n_int_elems * (int64_t)(H->R.p + 1) * (H->R.p + 1) * (H->R.p + 1);
+    if (n > 0)
+        hipLaunchKernelGGL(k_gauss_coords, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, H->R, H->int_elems,
+                           H->n_int_elems, (const double*)H->gxi, xyz);
+    return WQ_OK;
+}
+template int launch_gauss<double>(const wq_rules*, uint32_t, const double*, const double*, double*, double*, hipStream_t);
+#endif
+#ifndef WQ_ONLY_F64
+template int launch_gauss<float>(const wq_rules*, uint32_t, const float*, const float*, float*, float*, hipStream_t);
+#endif
+
+// ----------------------------------------------------------------------------------------
 // host launchers
 // ----------------------------------------------------------------------------------------
 template <typename T, int P, int WHICH>
@@ -777,7 +936,7 @@ static int launch_cut_p(const wq_rules* H, uint32_t parts, const T* kappa, T* vm
                 T* loc = mom + nmom;
                 hipLaunchKernelGGL((k_cut_moments<T, P>), dim3((unsigned)R.n_cut_elems), dim3(256), 0, s, R, kappa, mom);
                 hipLaunchKernelGGL((k_cut_local<T, P, WHICH>), dim3((unsigned)(R.n_cut_elems * (P + 1))), dim3(256), 0, s, R,
-                                   (const T*)mom, loc);
+                                   R.cut_elems, (const T*)mom, loc, nullptr, nullptr, nullptr);
                 if (R.n_cut > 0)
                     hipLaunchKernelGGL((k_cut_gather<T, P, WHICH>), dim3((unsigned)R.n_cut), dim3(RemCfg<P>::NT), 0, s, R,
                                        (const T*)loc, vm, vk);

@@ -9,3 +9,6 @@ template <typename T>
 int launch_cut(const wq_rules* H, uint32_t which, uint32_t parts, const T* kappa, T* vm, T* vk, hipStream_t s);
 template <typename T>
 int launch_adjoint(const wq_rules* H, uint32_t which, const T* gm, const T* gk, T* dk, hipStream_t s);
+template <typename T>
+int launch_gauss(const wq_rules* H, uint32_t which, const T* kg, const T* kappa, T* vm, T* vk, hipStream_t s);
+int launch_gauss_coords(const wq_rules* H, double* xyz, hipStream_t s);

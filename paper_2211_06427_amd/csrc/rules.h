@@ -19,6 +19,8 @@ struct wq_rules {
     int64_t n_block_elems = 0, n_cells = 0, n_oct = 0;
     int64_t n_oct_xgroups = 0, n_oct_columns = 0;    // octree leaf groups of the cut kernels
     int64_t n_rem_pairs = 0;                         // (cut row, remainder element) pairs
+    int32_t* int_elems = nullptr;                    // interior elements, lexicographic
+    int64_t n_int_elems = 0;
     int row_block = 16;
     int32_t* act2cut = nullptr;         // active row -> cut row or -1
     int32_t* box = nullptr;             // [cut row][6] DWQ box (inclusive element ranges)

@@ -1278,6 +1278,19 @@ int build_rules(const wq_mesh* mesh, const wq_levelset* ls, const wq_options* op
         if (!cut_elems) return B.fail();
         hipLaunchKernelGGL(k_flag_index, grid_for(ne), dim3(256), 0, stream, ne, cflag2, ceoff, ceidx, cut_elems);
         R.cut_elems = cut_elems; R.n_cut_elems = nce;
+        {   // interior elements (conventional Gauss assembly)
+            int32_t* iflag = B.tmp<int32_t>(ne);
+            int64_t* ioff = B.tmp<int64_t>(ne + 1);
+            int32_t* iidx = B.tmp<int32_t>(ne);
+            if (!iflag || !ioff || !iidx) return B.fail();
+            hipLaunchKernelGGL(k_flag_eq, grid_for(ne), dim3(256), 0, stream, ne, ecls, (int8_t)CLS_IN, iflag);
+            int64_t nie = 0;
+            if (scan_exclusive(B, iflag, ioff, ne, &nie)) return B.fail();
+            int32_t* ilist = B.keep<int32_t>(nie > 0 ? nie : 1);
+            if (!ilist) return B.fail();
+            hipLaunchKernelGGL(k_flag_index, grid_for(ne), dim3(256), 0, stream, ne, iflag, ioff, iidx, ilist);
+            H->int_elems = ilist; H->n_int_elems = nie;
+        }
         {   // per cut row: its cut elements
             int32_t* ccnt2 = B.tmp<int32_t>(ncut + 1);
             int64_t* coff2 = B.tmp<int64_t>(ncut + 1);

@@ -159,6 +159,46 @@ def test_which_subsets_and_determinism(name):
     assert float((vk - pk).abs().max()) <= 1e-14 * float(vk.abs().max())
 
 
+_GAUSS = {}
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+@pytest.mark.parametrize("name", ["uncut4_p1", "ball6_p2", "plane6_p3", "torus8_p2", "ball5_p4"])
+def test_gauss_assemble_matches_oracle(name, dtype):
+    """Conventional element-by-element Gauss assembly against the oracle's element loop."""
+    wl = SMALL[name]
+    print("case gauss", name, dtype, flush=True)
+    if name not in _GAUSS:
+        P = Problem(wl)
+        _GAUSS[name] = (P, P.assemble_full_gauss(kappa_numpy(wl)))
+    P, (M, K) = _GAUSS[name]
+    R = rules_for(wl)
+    xg = R.gauss_coords()
+    assert xg.shape == (R.n_gauss_elems * (wl.degree + 1) ** 3, 3)
+    kg = W.kappa_at(wl, xg).to(dtype)
+    vm, vk = R.gauss_assemble(kg, kappa_slots(R, wl, dtype))
+    torch.cuda.synchronize()
+    rp = P.row_ptr()
+    em = row_errors(vm.cpu().numpy(), M, rp)
+    ek = row_errors(vk.cpu().numpy(), K, rp)
+    print(f"gauss {name} {dtype}: mass e_row={em[0]:.2e} stiff e_row={ek[0]:.2e}")
+    assert em[0] <= TOL[dtype] and ek[0] <= TOL[dtype]
+
+
+def test_gauss_equals_wq_for_unit_kappa():
+    """kappa = 1: WQ is exact, so the WQ matrices equal the Gauss ones (uncut and cut)."""
+    for name in ("uncut5_p3", "ball6_p2"):
+        wl = SMALL[name]
+        R = rules_for(wl)
+        one = torch.ones(R.n_kappa, dtype=torch.float64, device=R.device)
+        og = torch.ones(R.n_gauss_elems * (wl.degree + 1) ** 3, dtype=torch.float64, device=R.device)
+        vm, vk = R.assemble(one)
+        gm, gk = R.gauss_assemble(og, one)
+        torch.cuda.synchronize()
+        assert float((vm - gm).abs().max()) <= 1e-12 * float(gm.abs().max())
+        assert float((vk - gk).abs().max()) <= 1e-12 * float(gk.abs().max())
+
+
 def test_plane48_sampled_rows():
     """Full-size 48^3 p=4 plane cut: sampled rows of every class against the oracle row by row."""
     wl = W.workload("plane48_p4")
