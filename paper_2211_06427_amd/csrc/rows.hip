@@ -211,21 +211,27 @@ k_rows_interior(DevRules R, const T* __restrict__ kappa, T* __restrict__ vm, T* 
 template <typename T, int P, int WHICH>
 struct CutCfg {
     static constexpr int M = 2 * P + 1, NW = 4 * P, NDQ = P * (P + 1), MM = M * M;
+    static constexpr int NA = NDQ > NW ? NDQ : NW;         // the split direction may hold a DWQ rule
     static constexpr int NT = 256;
+    static constexpr int QCH = sizeof(T) == 4 ? 8 : (P <= 4 ? 8 : 4);   // direction-C points per chunk
     static constexpr bool STIFF = (WHICH & 2) != 0;
     static constexpr bool MASS = (WHICH & 1) != 0;
 };
 
+// One workgroup per cut row.  Rows without a DWQ box are zero-filled.  For a row with a box
+// the contraction runs split direction first (A, with the one-sided rule), then B, then C;
+// kappa of a chunk of C points is gathered into LDS with independent loads (through the
+// slot map), then stage A (items (qC, qB, jA)), stage B (items (qC, jB, jA)) and, after all
+// chunks, stage C (items (jC, jB, jA)) write the row through its position map.
 template <typename T, int P, int WHICH>
 __global__ void __launch_bounds__(256)
 k_rows_cut(DevRules R, const T* __restrict__ kappa, T* __restrict__ vm, T* __restrict__ vk) {
     using C = CutCfg<T, P, WHICH>;
-    constexpr int M = C::M, NW = C::NW, NDQ = C::NDQ, MM = C::MM;
-    constexpr int NA = NDQ > NW ? NDQ : NW;        // the split direction may hold a DWQ rule
+    constexpr int M = C::M, NW = C::NW, NDQ = C::NDQ, MM = C::MM, NA = C::NA, QCH = C::QCH, NT = C::NT;
     __shared__ T s_w[3][2 * M * NA];
     __shared__ int s_y[3][NA];
     __shared__ int s_n[3];
-    constexpr int QCH = (32768 / (NW * M * 2 * (int)sizeof(T))) < NW ? (32768 / (NW * M * 2 * (int)sizeof(T))) : NW;
+    __shared__ T s_k[QCH * NW * NA];                // kappa [qC in chunk][qB][qA]
     __shared__ T s_t1[2 * QCH * NW * M];            // [v][qC in chunk][qB][jA]
     __shared__ T s_t2[2 * NW * MM];                 // [v][qC][jB jA]
 
@@ -234,12 +240,13 @@ k_rows_cut(DevRules R, const T* __restrict__ kappa, T* __restrict__ vm, T* __res
     const int4 sp = R.split[cr];
     const int64_t rb = R.row_ptr[ra], re = R.row_ptr[ra + 1];
     if (sp.x < 0) {
-        for (int64_t k = rb + threadIdx.x; k < re; k += C::NT) {
+        for (int64_t k = rb + threadIdx.x; k < re; k += NT) {
             if (C::MASS) vm[k] = 0;
             if (C::STIFF) vk[k] = 0;
         }
         return;
     }
+    const int t = threadIdx.x;
     const int lex = R.act2lex[ra];
     int I[3];
     I[2] = lex % R.nfun[2]; I[1] = (lex / R.nfun[2]) % R.nfun[1]; I[0] = lex / (R.nfun[1] * R.nfun[2]);
@@ -253,88 +260,83 @@ k_rows_cut(DevRules R, const T* __restrict__ kappa, T* __restrict__ vm, T* __res
             const int r = sp.w;
             const int np = R.dwq_np[r];
             const T* W = dwq_table<T>(R) + (int64_t)r * 2 * M * NDQ;
-            for (int k = threadIdx.x; k < 2 * M * NA; k += C::NT) {
+            for (int k = t; k < 2 * M * NA; k += NT) {
                 const int q = k % NA, row = k / NA;
                 s_w[sl][k] = q < NDQ ? W[row * NDQ + q] : (T)0;
             }
-            for (int q = threadIdx.x; q < NA; q += C::NT) s_y[sl][q] = q < np ? R.dwq_y[(int64_t)r * NDQ + q] : 0;
-            if (threadIdx.x == 0) s_n[sl] = np;
+            for (int q = t; q < NA; q += NT) s_y[sl][q] = q < np ? R.dwq_y[(int64_t)r * NDQ + q] : 0;
+            if (t == 0) s_n[sl] = np;
         } else {
             const int i = I[d];
             const int xs = R.xs[d][i], nw = R.nwin[d][i];
             const T* W = wt_table<T>(R, d) + (int64_t)i * 2 * M * NW;
-            for (int k = threadIdx.x; k < 2 * M * NA; k += C::NT) {
+            for (int k = t; k < 2 * M * NA; k += NT) {
                 const int q = k % NA, row = k / NA;
                 s_w[sl][k] = q < NW ? W[row * NW + q] : (T)0;
             }
-            for (int q = threadIdx.x; q < NA; q += C::NT) s_y[sl][q] = q < nw ? R.x2y[d][xs + q] : 0;
-            if (threadIdx.x == 0) s_n[sl] = nw;
+            for (int q = t; q < NA; q += NT) s_y[sl][q] = q < nw ? R.x2y[d][xs + q] : 0;
+            if (t == 0) s_n[sl] = nw;
         }
     }
     __syncthreads();
     const int nA = s_n[0], nB = s_n[1], nCc = s_n[2];
     for (int qc0 = 0; qc0 < nCc; qc0 += QCH) {
         const int nch = nCc - qc0 < QCH ? nCc - qc0 : QCH;
-        // stage A: T1[v][qC][qB][jA] = sum_qA W_A^v[jA][qA] kappa(qA, qB, qC)
-        for (int it = threadIdx.x; it < nch * nB; it += C::NT) {
-            const int qCl = it / nB, qB = it % nB;
+        // kappa of the chunk, all loads independent
+        for (int k = t; k < nch * nB * nA; k += NT) {
+            const int qCl = k / (nB * nA), qB = (k / nA) % nB, qA = k % nA;
             int y[3];
-            y[dB] = s_y[1][qB]; y[dC] = s_y[2][qc0 + qCl];
-            T a0[M], a1[M];
-#pragma unroll
-            for (int j = 0; j < M; ++j) { a0[j] = 0; a1[j] = 0; }
+            y[dA] = s_y[0][qA]; y[dB] = s_y[1][qB]; y[dC] = s_y[2][qc0 + qCl];
+            s_k[(qCl * NW + qB) * NA + qA] = kappa[slot_of(R, y[0], y[1], y[2])];
+        }
+        __syncthreads();
+        // stage A: T1[v][qC][qB][jA] = sum_qA W_A^v[jA][qA] kappa(qA, qB, qC)
+        for (int it = t; it < nch * nB * M; it += NT) {
+            const int qCl = it / (nB * M), qB = (it / M) % nB, jA = it % M;
+            const T* kr = s_k + (qCl * NW + qB) * NA;
+            T a0 = 0, a1 = 0;
             for (int qA = 0; qA < nA; ++qA) {
-                y[dA] = s_y[0][qA];
-                const T kv = kappa[slot_of(R, y[0], y[1], y[2])];
-#pragma unroll
-                for (int j = 0; j < M; ++j) {
-                    a0[j] += s_w[0][j * NA + qA] * kv;
-                    if (C::STIFF) a1[j] += s_w[0][(M + j) * NA + qA] * kv;
-                }
+                const T kv = kr[qA];
+                a0 += s_w[0][jA * NA + qA] * kv;
+                if (C::STIFF) a1 += s_w[0][(M + jA) * NA + qA] * kv;
             }
-#pragma unroll
-            for (int j = 0; j < M; ++j) {
-                s_t1[((0 * QCH + qCl) * NW + qB) * M + j] = a0[j];
-                if (C::STIFF) s_t1[((1 * QCH + qCl) * NW + qB) * M + j] = a1[j];
-            }
+            s_t1[((0 * QCH + qCl) * NW + qB) * M + jA] = a0;
+            if (C::STIFF) s_t1[((1 * QCH + qCl) * NW + qB) * M + jA] = a1;
         }
         __syncthreads();
         // stage B: T2_00[qC][jB jA] = sum_qB W_B^0 T1_0; T2_s = sum W_B^1 T1_0 + W_B^0 T1_1
-        for (int it = threadIdx.x; it < nch * M; it += C::NT) {
-            const int qCl = it / M, jA = it % M;
+        for (int it = t; it < nch * MM; it += NT) {
+            const int qCl = it / MM, jB = (it / M) % M, jA = it % M;
             const int qC = qc0 + qCl;
-            for (int jB = 0; jB < M; ++jB) {
-                T m0 = 0, ms = 0;
-                for (int qB = 0; qB < nB; ++qB) {
-                    const T t0 = s_t1[((0 * QCH + qCl) * NW + qB) * M + jA];
-                    m0 += s_w[1][jB * NA + qB] * t0;
-                    if (C::STIFF) ms += s_w[1][(M + jB) * NA + qB] * t0 + s_w[1][jB * NA + qB] * s_t1[((1 * QCH + qCl) * NW + qB) * M + jA];
-                }
-                s_t2[(0 * NW + qC) * MM + jB * M + jA] = m0;
-                if (C::STIFF) s_t2[(1 * NW + qC) * MM + jB * M + jA] = ms;
+            T m0 = 0, ms = 0;
+            for (int qB = 0; qB < nB; ++qB) {
+                const T t0 = s_t1[((0 * QCH + qCl) * NW + qB) * M + jA];
+                const T w0 = s_w[1][jB * NA + qB];
+                m0 += w0 * t0;
+                if (C::STIFF) ms += s_w[1][(M + jB) * NA + qB] * t0 + w0 * s_t1[((1 * QCH + qCl) * NW + qB) * M + jA];
             }
+            s_t2[(0 * NW + qC) * MM + jB * M + jA] = m0;
+            if (C::STIFF) s_t2[(1 * NW + qC) * MM + jB * M + jA] = ms;
         }
-        __syncthreads();
+        __syncthreads();                            // s_k / s_t1 are rewritten by the next chunk
     }
-    // stage C: one thread per (jB, jA); out[jC][jB][jA]
+    // stage C: items (jC, jB, jA); out[jC][jB][jA]
     const int32_t* pos = R.pos_map + cr * (int64_t)M * M * M;
-    for (int cc = threadIdx.x; cc < MM; cc += C::NT) {
-        const int jB = cc / M, jA = cc % M;
-        for (int jC = 0; jC < M; ++jC) {
-            T am = 0, ak = 0;
-            for (int qC = 0; qC < nCc; ++qC) {
-                const T t0 = s_t2[(0 * NW + qC) * MM + cc];
-                const T a = s_w[2][jC * NA + qC];
-                if (C::MASS) am += a * t0;
-                if (C::STIFF) ak += s_w[2][(M + jC) * NA + qC] * t0 + a * s_t2[(1 * NW + qC) * MM + cc];
-            }
-            int jj[3];
-            jj[dA] = jA; jj[dB] = jB; jj[dC] = jC;
-            const int k = pos[(jj[0] * M + jj[1]) * M + jj[2]];
-            if (k >= 0) {
-                if (C::MASS) vm[rb + k] = am;
-                if (C::STIFF) vk[rb + k] = ak;
-            }
+    for (int it = t; it < M * MM; it += NT) {
+        const int jC = it / MM, cc = it % MM, jB = cc / M, jA = cc % M;
+        T am = 0, ak = 0;
+        for (int qC = 0; qC < nCc; ++qC) {
+            const T t0 = s_t2[(0 * NW + qC) * MM + cc];
+            const T a = s_w[2][jC * NA + qC];
+            if (C::MASS) am += a * t0;
+            if (C::STIFF) ak += s_w[2][(M + jC) * NA + qC] * t0 + a * s_t2[(1 * NW + qC) * MM + cc];
+        }
+        int jj[3];
+        jj[dA] = jA; jj[dB] = jB; jj[dC] = jC;
+        const int k = pos[(jj[0] * M + jj[1]) * M + jj[2]];
+        if (k >= 0) {
+            if (C::MASS) vm[rb + k] = am;
+            if (C::STIFF) vk[rb + k] = ak;
         }
     }
 }
