@@ -28,6 +28,11 @@ SMALL = {
     "torus8_p2": W.custom(8, 2, TORUS, kappa="rf", seed=4),
     "ball5_p4": W.custom(5, 4, BALL, kappa="rf", seed=5),
 }
+# degrees 5 and 6 (general cut-element and row kernels)
+HIGH = {
+    "ball4_p5": W.custom(4, 5, BALL, kappa="rf", seed=6),
+    "ball4_p6": W.custom(4, 6, BALL, kappa="rf", seed=6),
+}
 
 
 def rules_for(wl):
@@ -109,9 +114,9 @@ def test_structure_matches_oracle(name):
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
-@pytest.mark.parametrize("name", list(SMALL) + ["uncut8_p2", "ball16_p3"])
+@pytest.mark.parametrize("name", list(SMALL) + ["uncut8_p2", "ball16_p3"] + list(HIGH))
 def test_forward_full_matrices(name, dtype):
-    wl = SMALL.get(name) or W.workload(name)
+    wl = SMALL.get(name) or HIGH.get(name) or W.workload(name)
     print("case", name, dtype, flush=True)
     P, Mr, Kr = oracle_full(name, wl)
     R = rules_for(wl)
@@ -231,9 +236,9 @@ def test_plane48_sampled_rows():
 
 
 # ------------------------------------------------------------------------------------------
-@pytest.mark.parametrize("name", ["ball6_p2", "torus8_p2", "plane6_p3", "uncut5_p3"])
+@pytest.mark.parametrize("name", ["ball6_p2", "torus8_p2", "plane6_p3", "uncut5_p3", "ball5_p4", "ball4_p5"])
 def test_adjoint_matches_oracle(name):
-    wl = SMALL[name]
+    wl = SMALL.get(name) or HIGH[name]
     print("case adjoint", name, flush=True)
     P = Problem(wl)
     R = rules_for(wl)
