@@ -195,6 +195,30 @@ def wq_rule(line: Line, tk: np.ndarray, pts, full_gauss: set, i: int, a: int):
     return Q, w
 
 
+def wq_condition(line: Line, a: int) -> float:
+    """Largest 2-norm condition number, over the nonzero singular values that the solve in
+    `wq_rule` keeps, of the min-norm systems of the standard rules of one direction (0 when
+    every rule takes the Gauss shortcut).  The individual weights of a min-norm rule are
+    fixed by floating point only to about this many units of roundoff; sums that the
+    exactness conditions constrain (a matrix entry with a smooth coefficient) are not
+    affected, a single weight is.  Used to set tolerances, not part of the method."""
+    p = line.p
+    tk = line.tk
+    t = line.knot_coord(tk)
+    nfun = len(tk) - p - 1
+    worst = 0.0
+    for i in range(nfun):
+        sa, sb = support(tk, p, i)
+        if all(e in line.full_gauss_elems for e in range(sa, sb)):
+            continue
+        xq = line.coord([(e, g) for (e, g) in line.X if sa <= e < sb])
+        J = [j for j in range(nfun) if max(sa, support(tk, p, j)[0]) < min(sb, support(tk, p, j)[1])]
+        s = np.linalg.svd(np.array([bspline(t, p, j, xq, a) for j in J]), compute_uv=False)
+        s = s[s > 1e-11 * s[0]]
+        worst = max(worst, float(s[0] / s[-1]))
+    return worst
+
+
 class Rules1D:
     """All standard WQ rules of one direction: rule[a][i] = (points, weights)."""
 

@@ -41,9 +41,9 @@ __global__ void k_fill(T* p, int64_t n, T v) {
 template <typename T, int P, int WHICH, int RB>
 struct AdjCfg {
     static constexpr int M = 2 * P + 1, NW = 4 * P, MM = M * M;
-    static constexpr int GT = ((MM + 63) / 64) * 64;
-    static constexpr int NT = GT >= 256 ? GT : 256;
-    static constexpr int NG = NT / GT;
+    static constexpr int GT = ((MM + 63) / 64) * 64;       // threads per stage-3 row group
+    static constexpr int NG = GT >= 256 ? 1 : 256 / GT;    // row groups
+    static constexpr int NT = NG * GT;                     // threads per block: whole groups only
     static constexpr int NQ1 = 2 * RB + 4 * P;
     static constexpr int QC = P <= 4 ? 8 : 4;             // q1 chunk of the stage-2/1 pass
     static constexpr bool STIFF = (WHICH & 2) != 0, MASS = (WHICH & 1) != 0;

@@ -28,8 +28,8 @@ template <typename T, int P, int WHICH, int RB>
 struct RowCfg {
     static constexpr int M = 2 * P + 1, NW = 4 * P, MM = M * M;
     static constexpr int GT = ((MM + 63) / 64) * 64;       // threads per stage-3 row group
-    static constexpr int NT = GT >= 256 ? GT : 256;        // threads per block
-    static constexpr int NG = NT / GT;                     // row groups
+    static constexpr int NG = GT >= 256 ? 1 : 256 / GT;    // row groups
+    static constexpr int NT = NG * GT;                     // threads per block: whole groups only
     static constexpr int NQ1 = 2 * RB + 4 * P;             // q1 slab bound
     static constexpr int NWP = NW + 1;                     // padded stride of staged rows
     static constexpr bool STIFF = (WHICH & 2) != 0;

@@ -12,6 +12,7 @@ import torch
 
 import workloads as W
 from oracle.assemble import Problem, kappa_numpy
+from oracle.spline import wq_condition
 
 pytestmark = pytest.mark.gpu
 
@@ -233,6 +234,100 @@ def test_plane48_sampled_rows():
             em = np.abs(vmh[s:t] - m).max() / np.abs(m).max()
             ek = np.abs(vkh[s:t] - k).max() / np.abs(k).max()
             assert em <= TOL[dtype] and ek <= TOL[dtype], (r, fc[r], em, ek)
+
+
+# Uncut meshes large enough for whole line blocks at degrees 5 and 6 (every row interior);
+# the oracle's full assembly is too slow there, so rows are sampled across the line blocks.
+BLOCKS = {
+    "uncut_p5_blocks": W.custom((8, 9, 7), 5, kappa="rf", seed=9),
+    "uncut_p6_blocks": W.custom((9, 8, 10), 6, kappa="rf", seed=8),
+}
+
+
+def _sampled_rows_check(R, P, rows, kap_fn, wl):
+    res = P.assemble_rows(rows, kap_fn)
+    rp = R.row_ptr().cpu().numpy()
+    for dtype in (torch.float64, torch.float32):
+        vm, vk = R.assemble(kappa_slots(R, wl, dtype))
+        torch.cuda.synchronize()
+        vmh = vm.cpu().numpy(); vkh = vk.cpu().numpy()
+        for r, (pat, m, k) in zip(rows, res):
+            s, t = rp[r], rp[r + 1]
+            assert t - s == len(m)
+            em = np.abs(vmh[s:t] - m).max() / np.abs(m).max()
+            ek = np.abs(vkh[s:t] - k).max() / np.abs(k).max()
+            assert em <= TOL[dtype] and ek <= TOL[dtype], (dtype, r, em, ek)
+    return res
+
+
+@pytest.mark.parametrize("name", list(BLOCKS))
+def test_line_blocks_high_degree(name):
+    """Degrees 5 and 6 with full line blocks: sampled rows (forward, FP64 and FP32) and the
+    adjoint of a cotangent supported on those rows, against the oracle row by row."""
+    wl = BLOCKS[name]
+    print("case blocks", name, flush=True)
+    R = rules_for(wl)
+    P = Problem(wl)
+    assert R.n_active == P.dom.n_active and R.n_rows_cut == 0
+    n1, n2, n3 = R.nfun
+    # first, last and middle rows of line blocks plus seeded picks
+    lex = [(0, 0, 0), (n1 - 1, n2 - 1, n3 - 1), (n1 // 2, n2 // 2, n3 // 2), (n1 - 1, 0, n3 // 2),
+           (wl.degree, n2 // 3, 1), (n1 // 2 + 1, n2 - 2, n3 - 1)]
+    a2l = {int(v): i for i, v in enumerate(R.active_to_lex().cpu().numpy())}
+    rows = [a2l[(i * n2 + j) * n3 + k] for i, j, k in lex]
+    rows = np.unique(np.concatenate([rows, W.sample_indices(41, R.n_active, 8)]))
+    kap_fn = kappa_numpy(wl)
+    res = _sampled_rows_check(R, P, rows, kap_fn, wl)
+    # adjoint restricted to the sampled rows
+    rp = R.row_ptr().cpu().numpy()
+    GM = np.zeros(R.nnz); GK = np.zeros(R.nnz)
+    gm_rows, gk_rows = [], []
+    for j, (r, (pat, m, k)) in enumerate(zip(rows, res)):
+        g1 = W.random_values(200 + j, len(m)); g2 = W.random_values(300 + j, len(m))
+        GM[rp[r]:rp[r + 1]] = g1; GK[rp[r]:rp[r + 1]] = g2
+        gm_rows.append(g1); gk_rows.append(g2)
+    ref = P.adjoint_rows(rows, gm_rows, gk_rows)
+    dev = R.device
+    got = R.adjoint(torch.tensor(GM, device=dev), torch.tensor(GK, device=dev)).cpu().numpy()
+    assert got.shape == ref.shape
+    # a slot's adjoint value carries a single 1D weight per direction, which the min-norm
+    # solve fixes only to about u cond(A) (cond up to ~5e6 at p = 6); smooth-kappa forward
+    # entries are sums that the exactness conditions pin and stay at 1e-12
+    cond = max(wq_condition(l, a) for l in P.lines for a in (0, 1))
+    tol = max(1e-12, np.finfo(np.float64).eps / 2 * cond)
+    assert np.abs(got - ref).max() <= tol * np.abs(ref).max(), (cond, np.abs(got - ref).max() / np.abs(ref).max())
+
+
+def test_ball64_p6_sampled_rows():
+    """Full-size 64^3 p=6 ball: sampled rows of every class against the oracle row by row."""
+    wl = W.workload("ball64_p6")
+    print("case ball64_p6 sampled", flush=True)
+    R = rules_for(wl)
+    P = Problem(wl)
+    dom = P.dom
+    assert R.n_active == dom.n_active
+    fc = dom.fcls.ravel()[dom.active_lex]
+    cut = np.nonzero(fc == 2)[0]
+    sp = R.split().cpu().numpy()
+    interior = W.sample_indices(51, dom.n_active, 4000)
+    interior = interior[fc[interior] == 1][:6]
+    boxed = cut[sp[:, 0] >= 0][W.sample_indices(52, int((sp[:, 0] >= 0).sum()), 4)]
+    unboxed = cut[sp[:, 0] < 0][W.sample_indices(53, int((sp[:, 0] < 0).sum()), 3)]
+    _sampled_rows_check(R, P, np.concatenate([interior, boxed, unboxed]), kappa_numpy(wl), wl)
+    # every row: FP32 against FP64 wherever FP32 can carry the row (row maximum at least
+    # 2^-100, 26 bits above FP32's smallest normal; thinner slivers of the ball underflow)
+    v64 = R.assemble(kappa_slots(R, wl, torch.float64))
+    v32 = R.assemble(kappa_slots(R, wl, torch.float32))
+    rp = R.row_ptr()
+    rows = torch.repeat_interleave(torch.arange(R.n_active, device=rp.device), torch.diff(rp))
+    for a, b in zip(v32, v64):
+        d = torch.zeros(R.n_active, dtype=torch.float64, device=a.device)
+        m = torch.zeros_like(d)
+        d.scatter_reduce_(0, rows, (a.double() - b).abs(), "amax")
+        m.scatter_reduce_(0, rows, b.abs(), "amax")
+        ok = m >= 2.0 ** -100
+        assert int(ok.sum()) >= 0.95 * R.n_active
+        assert float((d[ok] / m[ok]).max()) <= TOL[torch.float32]
 
 
 # ------------------------------------------------------------------------------------------
