@@ -249,6 +249,21 @@ def main():
     rp = R.row_ptr()
     err32 = {"mass": row_scaled_err(vals["f32"][0], vals["f64"][0], rp, torch),
              "stiff": row_scaled_err(vals["f32"][1], vals["f64"][1], rp, torch)}
+    # BF16x3 experiment: interior rows' direction-1 contraction on matrix cores with split
+    # bf16 operands (the rest as FP32); rows pass time and error of the whole matrices
+    vb = (torch.empty(R.nnz, device=dev), torch.empty(R.nnz, device=dev))
+
+    def step_bf3():
+        R.assemble_rows(kap["f32"], vb[0], vb[1], bf16x3=True)
+        R.cut_assemble(kap["f32"], vb[0], vb[1])
+
+    step_bf3()
+    bf3 = {"rows_ms": timed(lambda: R.assemble_rows(kap["f32"], vb[0], vb[1], bf16x3=True), nrep, torch),
+           "step_ms": timed(step_bf3, nrep, torch)}
+    step_bf3()
+    torch.cuda.synchronize()
+    bf3["rel_err_vs_fp64"] = {"mass": row_scaled_err(vb[0], vals["f64"][0], rp, torch),
+                              "stiff": row_scaled_err(vb[1], vals["f64"][1], rp, torch)}
 
     # --- rooflines (durations from the timed region) -----------------------------------
     esz = 8 if main_dt == "f64" else 4
@@ -299,6 +314,7 @@ def main():
         "speedup_vs_gauss_assembly": ({k: parts[k]["gauss_ms"] / parts[k]["step_ms"] for k in parts}
                                       if kg is not None else None),
         "fp32_rel_err_vs_fp64": err32,
+        "bf16x3_experiment": bf3,
         "build_rules_ms": {"cold": build_cold_ms, "warm": build_ms},
     }
     if not args.skip_cpu_baseline:

@@ -18,7 +18,7 @@
  *    detected before any device work is enqueued; nothing is written in that case.
  *  - Device pointers (kappa, vals_*, G_*, dkappa) are caller-owned, contiguous, and must
  *    hold the documented number of elements of the value type (double for WQ_F64,
- *    float for WQ_F32).  The library never frees caller memory.
+ *    float for WQ_F32 and WQ_BF16X3).  The library never frees caller memory.
  *  - Every call except wq_build_rules is asynchronous on the given HIP stream
  *    (hipStream_t passed as void*; NULL = the default stream).  A rules handle is
  *    immutable after wq_build_rules, so calls on different streams may share it.
@@ -44,7 +44,13 @@ typedef enum {
     WQ_EUNSUPPORTED = -5  /* valid request outside this build's limits (e.g. p > 6) */
 } wq_status;
 
-typedef enum { WQ_F64 = 0, WQ_F32 = 1 } wq_dtype;
+/* WQ_BF16X3 (an experiment, forward assembly only): values and kappa are float as for
+ * WQ_F32; in wq_assemble_rows the direction-1 contraction of the interior rows runs on
+ * the matrix cores with each FP32 operand split into two bf16 parts, x = hi + lo, and
+ * products taken as hi*hi + hi*lo + lo*hi accumulated in FP32 (about 2^-16 relative per
+ * product); every other step of wq_assemble_rows and cut_assemble runs as WQ_F32.
+ * wq_assemble_adjoint and gauss_assemble return WQ_EUNSUPPORTED for it. */
+typedef enum { WQ_F64 = 0, WQ_F32 = 1, WQ_BF16X3 = 2 } wq_dtype;
 
 enum { WQ_MASS = 1u, WQ_STIFF = 2u };   /* 'which' bit mask */
 

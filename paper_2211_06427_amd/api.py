@@ -121,20 +121,25 @@ class Rules:
         return self._view("cut_rows", self.n_rows_cut, torch.int32)
 
     # --- assembly -----------------------------------------------------------------------
-    def _call(self, fn, kappa, vm, vk, which):
+    def _call(self, fn, kappa, vm, vk, which, bf16x3=False):
         dtype = kappa.dtype
         if dtype not in _DT:
             raise ValueError(f"unsupported dtype {dtype}")
+        if bf16x3 and dtype != torch.float32:
+            raise ValueError("the BF16x3 split takes float32 kappa and values")
         _need(kappa, self.n_kappa, dtype, self.device, "kappa")
         _need(vm, self.nnz, dtype, self.device, "vals_mass")
         _need(vk, self.nnz, dtype, self.device, "vals_stiff")
-        L.check(fn(self._h, _DT[dtype], int(which), _ptr(kappa), _ptr(vm), _ptr(vk),
+        code = L.WQ_BF16X3 if bf16x3 else _DT[dtype]
+        L.check(fn(self._h, code, int(which), _ptr(kappa), _ptr(vm), _ptr(vk),
                    C.c_void_p(_stream_handle(self.device))))
 
-    def assemble_rows(self, kappa, vals_mass=None, vals_stiff=None, which=None):
+    def assemble_rows(self, kappa, vals_mass=None, vals_stiff=None, which=None, bf16x3=False):
+        """Overwrites the values.  bf16x3=True (float32 only): the interior rows' direction-1
+        contraction runs on matrix cores with bf16 hi/lo split operands (an experiment)."""
         which = which if which is not None else (L.WQ_MASS if vals_mass is not None else 0) | \
             (L.WQ_STIFF if vals_stiff is not None else 0)
-        self._call(L.load().wq_assemble_rows, kappa, vals_mass, vals_stiff, which)
+        self._call(L.load().wq_assemble_rows, kappa, vals_mass, vals_stiff, which, bf16x3)
 
     def cut_assemble(self, kappa, vals_mass=None, vals_stiff=None, which=None, parts=0):
         """Accumulates the cut part; parts = WQ_CUT_REMAINDER and/or WQ_CUT_OCTREE (0: both)."""
@@ -142,11 +147,11 @@ class Rules:
             (L.WQ_STIFF if vals_stiff is not None else 0)
         self._call(L.load().cut_assemble, kappa, vals_mass, vals_stiff, which | parts)
 
-    def assemble(self, kappa, which=L.WQ_MASS | L.WQ_STIFF):
+    def assemble(self, kappa, which=L.WQ_MASS | L.WQ_STIFF, bf16x3=False):
         """Whole matrices: rows, then the cut part. Returns (M values or None, K values or None)."""
         vm = torch.empty(self.nnz, dtype=kappa.dtype, device=self.device) if which & L.WQ_MASS else None
         vk = torch.empty(self.nnz, dtype=kappa.dtype, device=self.device) if which & L.WQ_STIFF else None
-        self.assemble_rows(kappa, vm, vk, which)
+        self.assemble_rows(kappa, vm, vk, which, bf16x3)
         self.cut_assemble(kappa, vm, vk, which)
         return vm, vk
 

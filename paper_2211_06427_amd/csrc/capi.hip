@@ -25,7 +25,8 @@ static int check_launch(const char* what) {
 static int check_values(const wq_rules* r, int dtype, uint32_t which, const void* kappa, const void* a,
                         const void* b, const char* what, uint32_t extra_bits = 0) {
     if (!r) return wq_set_error(WQ_EINVAL, "%s: rules handle is NULL", what);
-    if (dtype != WQ_F64 && dtype != WQ_F32) return wq_set_error(WQ_EINVAL, "%s: unknown dtype %d", what, dtype);
+    if (dtype != WQ_F64 && dtype != WQ_F32 && dtype != WQ_BF16X3)
+        return wq_set_error(WQ_EINVAL, "%s: unknown dtype %d", what, dtype);
     if ((which & 3u) == 0 || (which & ~(3u | extra_bits)))
         return wq_set_error(WQ_EINVAL, "%s: which must hold a non-empty subset of MASS|STIFF%s", what,
                             extra_bits ? " (plus optional part bits)" : "");
@@ -110,6 +111,8 @@ int wq_assemble_rows(const wq_rules* r, int dtype, uint32_t which, const void* k
     if (r->nnz == 0) return WQ_OK;
     if (dtype == WQ_F64)
         launch_rows<double>(r, which, (const double*)kappa, (double*)vm, (double*)vk, (hipStream_t)stream);
+    else if (dtype == WQ_BF16X3)
+        launch_rows_bf16x3(r, which, (const float*)kappa, (float*)vm, (float*)vk, (hipStream_t)stream);
     else
         launch_rows<float>(r, which, (const float*)kappa, (float*)vm, (float*)vk, (hipStream_t)stream);
     return check_launch("wq_assemble_rows");
@@ -133,6 +136,8 @@ int wq_assemble_adjoint(const wq_rules* r, int dtype, uint32_t which, const void
                         void* stream) {
     int st = check_values(r, dtype, which, dk, gm, gk, "wq_assemble_adjoint");
     if (st) return st;
+    if (dtype == WQ_BF16X3)
+        return wq_set_error(WQ_EUNSUPPORTED, "wq_assemble_adjoint: the BF16x3 split covers the forward rows only");
     if (dtype == WQ_F64)
         st = launch_adjoint<double>(r, which, (const double*)gm, (const double*)gk, (double*)dk, (hipStream_t)stream);
     else
@@ -151,6 +156,8 @@ int gauss_assemble(const wq_rules* r, int dtype, uint32_t which, const void* kap
                    void* vk, void* stream) {
     int st = check_values(r, dtype, which, kappa, vm, vk, "gauss_assemble");
     if (st) return st;
+    if (dtype == WQ_BF16X3)
+        return wq_set_error(WQ_EUNSUPPORTED, "gauss_assemble: the BF16x3 split covers the forward rows only");
     if (!kappa_gauss && r->n_int_elems > 0) return wq_set_error(WQ_EINVAL, "gauss_assemble: kappa_gauss is NULL");
     if (r->nnz == 0) return WQ_OK;
     if (dtype == WQ_F64)

@@ -5,6 +5,7 @@
 
 template <typename T>
 void launch_rows(const wq_rules* H, uint32_t which, const T* kappa, T* vm, T* vk, hipStream_t s);
+void launch_rows_bf16x3(const wq_rules* H, uint32_t which, const float* kappa, float* vm, float* vk, hipStream_t s);
 template <typename T>
 int launch_cut(const wq_rules* H, uint32_t which, uint32_t parts, const T* kappa, T* vm, T* vk, hipStream_t s);
 template <typename T>

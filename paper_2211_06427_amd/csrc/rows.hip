@@ -36,11 +36,119 @@ struct RowCfg {
     static constexpr bool MASS = (WHICH & 1) != 0;
 };
 
+// ---- BF16x3 experiment: stage 3 on matrix cores with split operands ----
+// x = hi + lo with hi = bf16(x) and lo = bf16(x - hi) (round to nearest even, finite x);
+// a product is taken as hi*hi + hi*lo + lo*hi (the lo*lo term is dropped), accumulated in
+// FP32 by v_mfma_f32_16x16x16_bf16.  Operand layout of that instruction: A (16 x 16, M x K)
+// element (m, k) in lane m + 16 (k / 4), slot k % 4; B (K x N) element (k, n) in lane
+// n + 16 (k / 4), slot k % 4; D as for the FP32 16x16x4 form (column lane % 16, row
+// 4 (lane / 16) + r).
+typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+__device__ inline short bf16_rn(float x) {
+    uint32_t u = __float_as_uint(x);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (short)(u >> 16);
+}
+__device__ inline float bf16_up(short h) { return __uint_as_float((uint32_t)(uint16_t)h << 16); }
+__device__ inline void split4(const float v[4], bf16x4_t& hi, bf16x4_t& lo) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const short h = bf16_rn(v[i]);
+        hi[i] = h;
+        lo[i] = bf16_rn(v[i] - bf16_up(h));
+    }
+}
+__device__ inline f32x4_t mma3(const bf16x4_t& ah, const bf16x4_t& al, const bf16x4_t& bh, const bf16x4_t& bl,
+                               f32x4_t c) {
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, c, 0, 0, 0);
+}
+
+// One wave per row of the block (rows wave, wave + nwaves, ...): out[jj1][c] = sum_q
+// W1[jj1][q] T2[off + q][c] with rows m = jj1 (M <= 16), K = q in chunks of 16, columns
+// c = (j2 j3) in tiles of 16.  Stiffness: W1^11 T2_00 + W1^00 T2_s.
+template <int P, int WHICH>
+__device__ void stage3_bf16x3(const DevRules& R, const float* s_t00, const float* s_ts, int i1s, int I2, int I3,
+                              int nrows, int qbase, float* __restrict__ vm, float* __restrict__ vk) {
+    constexpr int M = 2 * P + 1, NW = 4 * P, MM = M * M, KC = (NW + 15) / 16, NTILE = (MM + 15) / 16;
+    constexpr bool MASS = (WHICH & 1) != 0, STIFF = (WHICH & 2) != 0;
+    static_assert(M <= 16 && NW % 4 == 0, "one M tile, float4 weight loads");
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
+    const int lm = lane & 15, lk = lane >> 4;
+    const int p = P;
+    const int lo2 = I2 - p < 0 ? p - I2 : 0, hi2 = I2 + p > R.nfun[1] - 1 ? R.nfun[1] - 1 - I2 + p : 2 * p;
+    const int lo3 = I3 - p < 0 ? p - I3 : 0, hi3 = I3 + p > R.nfun[2] - 1 ? R.nfun[2] - 1 - I3 + p : 2 * p;
+    const int m2 = hi2 - lo2 + 1, m3 = hi3 - lo3 + 1;
+    const int64_t nl = (int64_t)R.nfun[1] * R.nfun[2];
+    const float* W1 = R.Wt32[0];
+    for (int r = wv; r < nrows; r += nwv) {
+        const int i1 = i1s + r;
+        const int ra = __builtin_amdgcn_readfirstlane(R.lex2act[(int64_t)i1 * nl + (int64_t)I2 * R.nfun[2] + I3]);
+        const int64_t base = R.row_ptr[ra];
+        const int off = R.xs[0][i1] - qbase;
+        const int nw1 = R.nwin[0][i1];
+        const int lo1 = i1 - p < 0 ? p - i1 : 0, hi1 = i1 + p > R.nfun[0] - 1 ? R.nfun[0] - 1 - i1 + p : 2 * p;
+        // A operands: W1^00 and W1^11 rows m = jj1, K slots q = 16 kc + 4 lk + i
+        bf16x4_t a0h[KC], a0l[KC], a1h[KC], a1l[KC];
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc) {
+            const int q = 16 * kc + 4 * lk;
+            float w0[4] = {0, 0, 0, 0}, w1[4] = {0, 0, 0, 0};
+            if (lm < M && q < NW) {
+                const float4 v0 = *(const float4*)(W1 + ((int64_t)i1 * 2 * M + lm) * NW + q);
+                const float4 v1 = *(const float4*)(W1 + ((int64_t)i1 * 2 * M + M + lm) * NW + q);
+                w0[0] = v0.x; w0[1] = v0.y; w0[2] = v0.z; w0[3] = v0.w;
+                w1[0] = v1.x; w1[1] = v1.y; w1[2] = v1.z; w1[3] = v1.w;
+            }
+            split4(w0, a0h[kc], a0l[kc]);
+            split4(w1, a1h[kc], a1l[kc]);
+        }
+        for (int tile = 0; tile < NTILE; ++tile) {
+            const int c = tile * 16 + lm;
+            f32x4_t accM = {0, 0, 0, 0}, accK = {0, 0, 0, 0};
+#pragma unroll
+            for (int kc = 0; kc < KC; ++kc) {
+                float t0[4], ts[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int q = 16 * kc + 4 * lk + i;
+                    const bool ok = c < MM && q < nw1;
+                    t0[i] = ok ? s_t00[(off + q) * MM + c] : 0.0f;
+                    ts[i] = (ok && STIFF) ? s_ts[(off + q) * MM + c] : 0.0f;
+                }
+                bf16x4_t b0h, b0l;
+                split4(t0, b0h, b0l);
+                if (MASS) accM = mma3(a0h[kc], a0l[kc], b0h, b0l, accM);
+                if (STIFF) {
+                    bf16x4_t bsh, bsl;
+                    split4(ts, bsh, bsl);
+                    accK = mma3(a1h[kc], a1l[kc], b0h, b0l, accK);
+                    accK = mma3(a0h[kc], a0l[kc], bsh, bsl, accK);
+                }
+            }
+            const int jj2 = c / M, jj3 = c % M;
+            if (c < MM && jj2 >= lo2 && jj2 <= hi2 && jj3 >= lo3 && jj3 <= hi3) {
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr) {
+                    const int jj1 = 4 * lk + rr;
+                    if (jj1 < lo1 || jj1 > hi1) continue;
+                    const int64_t o = base + ((int64_t)(jj1 - lo1) * m2 + (jj2 - lo2)) * m3 + (jj3 - lo3);
+                    if (MASS) vm[o] = accM[rr];
+                    if (STIFF) vk[o] = accK[rr];
+                }
+            }
+        }
+    }
+}
+
 // One workgroup per line block (or half of one: SPLIT = 2 processes RB rows of a block of
 // up to 2 RB).  Stages 1-2 contract directions 3 and 2 once for the block into the LDS slab
 // T2[q1][j2 j3] (mass) and Ts (stiffness, directions 2 and 3); stage 3 runs row by row with
 // the row's direction-1 weights staged in LDS one row ahead.
-template <typename T, int P, int WHICH, int RB, int SPLIT>
+template <typename T, int P, int WHICH, int RB, int SPLIT, bool BF3 = false>
 __global__ void __launch_bounds__((RowCfg<T, P, WHICH, RB>::NT))
 k_rows_interior(DevRules R, const T* __restrict__ kappa, T* __restrict__ vm, T* __restrict__ vk) {
     using C = RowCfg<T, P, WHICH, RB>;
@@ -104,6 +212,12 @@ k_rows_interior(DevRules R, const T* __restrict__ kappa, T* __restrict__ vm, T* 
             s_t00[q1 * MM + j2 * M + j3] = m0[j2];
             if (C::STIFF) s_ts[q1 * MM + j2 * M + j3] = ms[j2];
         }
+    }
+
+    if constexpr (BF3) {
+        __syncthreads();                        // slab ready
+        stage3_bf16x3<P, WHICH>(R, s_t00, s_ts, i1s, i2, i3, nrows, qbase, vm, vk);
+        return;
     }
 
     // ---- stage 3: row groups of GT lanes, one lane per (j2, j3) ----
@@ -367,6 +481,46 @@ static void launch_rows_p(const wq_rules* H, const T* kappa, T* vm, T* vk, hipSt
     if (R.n_cut > 0)
         hipLaunchKernelGGL((k_rows_cut<T, P, WHICH>), dim3((unsigned)R.n_cut), dim3(256), 0, s, R, kappa, vm, vk);
 }
+
+#ifndef WQ_ONLY_F64
+// BF16x3 experiment: interior rows with the split-operand stage 3, cut rows as in FP32
+template <int P, int WHICH>
+static void launch_rows_bf3_p(const wq_rules* H, const float* kappa, float* vm, float* vk, hipStream_t s) {
+    const DevRules& R = H->R;
+    if (R.n_lblocks > 0) {
+        if constexpr (P <= 4) {
+            using C = RowCfg<float, P, WHICH, 16>;
+            hipLaunchKernelGGL((k_rows_interior<float, P, WHICH, 16, 1, true>), dim3((unsigned)R.n_lblocks), dim3(C::NT), 0,
+                               s, R, kappa, vm, vk);
+        } else {
+            using C = RowCfg<float, P, WHICH, 8>;
+            hipLaunchKernelGGL((k_rows_interior<float, P, WHICH, 8, 1, true>), dim3((unsigned)R.n_lblocks), dim3(C::NT), 0,
+                               s, R, kappa, vm, vk);
+        }
+    }
+    if (R.n_cut > 0)
+        hipLaunchKernelGGL((k_rows_cut<float, P, WHICH>), dim3((unsigned)R.n_cut), dim3(256), 0, s, R, kappa, vm, vk);
+}
+
+template <int P>
+static void launch_rows_bf3_w(const wq_rules* H, uint32_t which, const float* kappa, float* vm, float* vk,
+                              hipStream_t s) {
+    if (which == 1) launch_rows_bf3_p<P, 1>(H, kappa, vm, vk, s);
+    else if (which == 2) launch_rows_bf3_p<P, 2>(H, kappa, vm, vk, s);
+    else launch_rows_bf3_p<P, 3>(H, kappa, vm, vk, s);
+}
+
+void launch_rows_bf16x3(const wq_rules* H, uint32_t which, const float* kappa, float* vm, float* vk, hipStream_t s) {
+    switch (H->R.p) {
+        case 1: launch_rows_bf3_w<1>(H, which, kappa, vm, vk, s); break;
+        case 2: launch_rows_bf3_w<2>(H, which, kappa, vm, vk, s); break;
+        case 3: launch_rows_bf3_w<3>(H, which, kappa, vm, vk, s); break;
+        case 4: launch_rows_bf3_w<4>(H, which, kappa, vm, vk, s); break;
+        case 5: launch_rows_bf3_w<5>(H, which, kappa, vm, vk, s); break;
+        case 6: launch_rows_bf3_w<6>(H, which, kappa, vm, vk, s); break;
+    }
+}
+#endif
 
 template <typename T, int P>
 static void launch_rows_w(const wq_rules* H, uint32_t which, const T* kappa, T* vm, T* vk, hipStream_t s) {
