@@ -48,6 +48,8 @@ struct DevRules {
     const int4* split;                  // d, s, high, dwq rule (-1: none)
     const int32_t* pos_map;             // [cut row][m^3]: offset in row or -1
     int64_t n_cut;
+    const int32_t* box_rows;            // cut-row indices with a DWQ box, ascending
+    int64_t n_box;
     // DWQ rules
     const int32_t* dwq_np;
     const int32_t* dwq_y;               // [r][ndq]

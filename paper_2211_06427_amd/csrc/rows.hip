@@ -168,6 +168,35 @@ k_rows_interior(DevRules R, const T* __restrict__ kappa, T* __restrict__ vm, T* 
     const T* W1 = wt_table<T>(R, 0);
     const T* W2 = wt_table<T>(R, 1) + (int64_t)i2 * 2 * M * NW;
     const T* W3 = wt_table<T>(R, 2) + (int64_t)i3 * 2 * M * NW;
+    // Stage-3 weights of every row this lane's group will handle, loaded into registers now:
+    // their loads are older than every row store, so moving them to LDS row by row never
+    // waits for stores to complete.
+    constexpr int RPG = (RB + NG - 1) / NG;     // rows per group
+    constexpr int WPL = (W1N + C::GT - 1) / C::GT;   // weights per lane per row
+    const int grp = __builtin_amdgcn_readfirstlane(t / C::GT);
+    const int c = t % C::GT;
+    static_assert(RPG >= 2, "the queue holds the current and the next row");
+    T wq[RPG][WPL];
+    // and the rows' active indices and windows (their CSR offsets are fetched after stages
+    // 1-2, once these have arrived)
+    int rq_act[RPG], rq_xs[RPG], rq_nw[RPG];
+    int64_t rq_base[RPG];
+    if constexpr (!BF3) {
+        const int64_t nl0 = (int64_t)R.nfun[1] * R.nfun[2];
+#pragma unroll
+        for (int j = 0; j < RPG; ++j) {
+            const int r = grp + j * NG;
+#pragma unroll
+            for (int i = 0; i < WPL; ++i) {
+                const int k = c + i * C::GT;
+                wq[j][i] = (r < nrows && k < W1N) ? W1[(int64_t)(i1s + r) * W1N + k] : (T)0;
+            }
+            const int i1 = i1s + (r < nrows ? r : 0);
+            rq_act[j] = __builtin_amdgcn_readfirstlane(R.lex2act[(int64_t)i1 * nl0 + (int64_t)i2 * R.nfun[2] + i3]);
+            rq_xs[j] = __builtin_amdgcn_readfirstlane(R.xs[0][i1]);
+            rq_nw[j] = __builtin_amdgcn_readfirstlane(R.nwin[0][i1]);
+        }
+    }
     for (int k = t; k < 2 * M * NW; k += NT) {
         s_w2[(k / NW) * NWP + k % NW] = W2[k];
         s_w3[(k / NW) * NWP + k % NW] = W3[k];
@@ -221,8 +250,6 @@ k_rows_interior(DevRules R, const T* __restrict__ kappa, T* __restrict__ vm, T* 
     }
 
     // ---- stage 3: row groups of GT lanes, one lane per (j2, j3) ----
-    const int grp = __builtin_amdgcn_readfirstlane(t / C::GT);
-    const int c = t % C::GT;
     const int jj2 = c / M, jj3 = c % M;
     const int p = P;
     const int I2 = i2, I3 = i3;
@@ -231,28 +258,25 @@ k_rows_interior(DevRules R, const T* __restrict__ kappa, T* __restrict__ vm, T* 
     const int m2 = hi2 - lo2 + 1, m3 = hi3 - lo3 + 1;
     const bool live = c < MM && jj2 >= lo2 && jj2 <= hi2 && jj3 >= lo3 && jj3 <= hi3;
     const int64_t nl = (int64_t)R.nfun[1] * R.nfun[2];
-    // first row of each group: its weights
-    if (grp < nrows)
-        for (int k = c; k < W1N; k += C::GT) s_w1[grp][0][k] = W1[(int64_t)(i1s + grp) * W1N + k];
+    // first row of each group: its weights; every row's CSR offset
+#pragma unroll
+    for (int i = 0; i < WPL; ++i) {
+        const int k = c + i * C::GT;
+        if (grp < nrows && k < W1N) s_w1[grp][0][k] = wq[0][i];
+    }
+#pragma unroll
+    for (int j = 0; j < RPG; ++j) rq_base[j] = R.row_ptr[rq_act[j]];
     __syncthreads();                            // slab and first weights ready
     int wb = 0;
     for (int r0 = 0; r0 < nrows; r0 += NG) {
         const int r = r0 + grp;
         const bool active = r < nrows;
-        // weights of this group's next row, loaded now and stored after this row
-        T nw[(W1N + C::GT - 1) / C::GT];
         const bool has_next = r + NG < nrows;
-#pragma unroll
-        for (int i = 0; i < (W1N + C::GT - 1) / C::GT; ++i) {
-            const int k = c + i * C::GT;
-            nw[i] = (has_next && k < W1N) ? W1[(int64_t)(i1s + r + NG) * W1N + k] : (T)0;
-        }
         if (active) {
             const int i1 = __builtin_amdgcn_readfirstlane(i1s + r);
-            const int ra = __builtin_amdgcn_readfirstlane(R.lex2act[(int64_t)i1 * nl + (int64_t)I2 * R.nfun[2] + I3]);
-            const int64_t base = R.row_ptr[ra];
-            const int off = __builtin_amdgcn_readfirstlane(R.xs[0][i1] - qbase);
-            const int nw1 = __builtin_amdgcn_readfirstlane(R.nwin[0][i1]);
+            const int64_t base = rq_base[0];
+            const int off = rq_xs[0] - qbase;
+            const int nw1 = rq_nw[0];
             const int lo1 = i1 - p < 0 ? p - i1 : 0, hi1 = i1 + p > R.nfun[0] - 1 ? R.nfun[0] - 1 - i1 + p : 2 * p;
             T t00[NW], ts[NW];
 #pragma unroll
@@ -309,10 +333,19 @@ k_rows_interior(DevRules R, const T* __restrict__ kappa, T* __restrict__ vm, T* 
         }
         if (has_next) {
 #pragma unroll
-            for (int i = 0; i < (W1N + C::GT - 1) / C::GT; ++i) {
+            for (int i = 0; i < WPL; ++i) {
                 const int k = c + i * C::GT;
-                if (k < W1N) s_w1[grp][wb ^ 1][k] = nw[i];
+                if (k < W1N) s_w1[grp][wb ^ 1][k] = wq[1][i];
             }
+        }
+        // advance the register queues (static indices: the rows stay in registers)
+#pragma unroll
+        for (int j = 0; j + 1 < RPG; ++j) {
+#pragma unroll
+            for (int i = 0; i < WPL; ++i) wq[j][i] = wq[j + 1][i];
+            rq_base[j] = rq_base[j + 1];
+            rq_xs[j] = rq_xs[j + 1];
+            rq_nw[j] = rq_nw[j + 1];
         }
         wb ^= 1;
         __syncthreads();
@@ -332,11 +365,27 @@ struct CutCfg {
     static constexpr bool MASS = (WHICH & 1) != 0;
 };
 
-// One workgroup per cut row.  Rows without a DWQ box are zero-filled.  For a row with a box
-// the contraction runs split direction first (A, with the one-sided rule), then B, then C;
-// kappa of a chunk of C points is gathered into LDS with independent loads (through the
-// slot map), then stage A (items (qC, qB, jA)), stage B (items (qC, jB, jA)) and, after all
-// chunks, stage C (items (jC, jB, jA)) write the row through its position map.
+// Cut rows without a DWQ box: one wave per row writes zeros over the row (their values come
+// from cut_assemble alone).
+template <typename T, int WHICH>
+__global__ void __launch_bounds__(256)
+k_rows_zero(DevRules R, T* __restrict__ vm, T* __restrict__ vk) {
+    const int64_t cr = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (cr >= R.n_cut || R.split[cr].x >= 0) return;
+    const int ra = R.cut_rows[cr];
+    const int64_t rb = R.row_ptr[ra], re = R.row_ptr[ra + 1];
+    for (int64_t k = rb + (threadIdx.x & 63); k < re; k += 64) {
+        if (WHICH & 1) vm[k] = 0;
+        if (WHICH & 2) vk[k] = 0;
+    }
+}
+
+// One workgroup per cut row with a DWQ box (the box-row list).  The contraction runs split
+// direction first (A, with the one-sided rule), then B, then C; kappa of a chunk of C points
+// is gathered into LDS with independent loads (through the slot map; the next chunk's loads
+// are issued before the current chunk is contracted), then stage A (items (qC, qB, jA)),
+// stage B (items (qC, jB, jA)) and, after all chunks, stage C (items (jC, jB, jA)) write
+// the row through its position map (read at the start).
 template <typename T, int P, int WHICH>
 __global__ void __launch_bounds__(256)
 k_rows_cut(DevRules R, const T* __restrict__ kappa, T* __restrict__ vm, T* __restrict__ vk) {
@@ -349,17 +398,11 @@ k_rows_cut(DevRules R, const T* __restrict__ kappa, T* __restrict__ vm, T* __res
     __shared__ T s_t1[2 * QCH * NW * M];            // [v][qC in chunk][qB][jA]
     __shared__ T s_t2[2 * NW * MM];                 // [v][qC][jB jA]
 
-    const int64_t cr = blockIdx.x;
+    const int64_t cr = R.box_rows[blockIdx.x];
     const int ra = R.cut_rows[cr];
     const int4 sp = R.split[cr];
-    const int64_t rb = R.row_ptr[ra], re = R.row_ptr[ra + 1];
-    if (sp.x < 0) {
-        for (int64_t k = rb + threadIdx.x; k < re; k += NT) {
-            if (C::MASS) vm[k] = 0;
-            if (C::STIFF) vk[k] = 0;
-        }
-        return;
-    }
+    const int64_t rb = R.row_ptr[ra];
+    if (sp.x < 0) return;
     const int t = threadIdx.x;
     const int lex = R.act2lex[ra];
     int I[3];
@@ -367,6 +410,20 @@ k_rows_cut(DevRules R, const T* __restrict__ kappa, T* __restrict__ vm, T* __res
     // contraction order: A = split direction, then the other two ascending
     const int dA = sp.x, dB = dA == 0 ? 1 : 0, dC = dA == 2 ? 1 : 2;
     const int dirs[3] = {dA, dB, dC};
+    // position map entries of this thread's stage-C items, loaded now
+    constexpr int NPOS = (M * MM + NT - 1) / NT;
+    const int32_t* pos = R.pos_map + cr * (int64_t)M * M * M;
+    int pq[NPOS];
+#pragma unroll
+    for (int i = 0; i < NPOS; ++i) {
+        const int it = t + i * NT;
+        pq[i] = -1;
+        if (it < M * MM) {
+            int jj[3];
+            jj[dA] = it % M; jj[dB] = (it / M) % M; jj[dC] = it / MM;
+            pq[i] = pos[(jj[0] * M + jj[1]) * M + jj[2]];
+        }
+    }
     // rules into LDS: s_w[slot][a][jj][q] with q stride NA
     for (int sl = 0; sl < 3; ++sl) {
         const int d = dirs[sl];
@@ -394,16 +451,35 @@ k_rows_cut(DevRules R, const T* __restrict__ kappa, T* __restrict__ vm, T* __res
     }
     __syncthreads();
     const int nA = s_n[0], nB = s_n[1], nCc = s_n[2];
+    // kappa of a chunk: KQ values per thread, all loads independent
+    constexpr int KQ = (QCH * NW * NA + NT - 1) / NT;
+    T kq[KQ];
+    auto gather = [&](int qc0) {
+        const int nch = nCc - qc0 < QCH ? nCc - qc0 : QCH;
+#pragma unroll
+        for (int i = 0; i < KQ; ++i) {
+            const int k = t + i * NT;
+            if (k < nch * nB * nA) {
+                const int qCl = k / (nB * nA), qB = (k / nA) % nB, qA = k % nA;
+                int y[3];
+                y[dA] = s_y[0][qA]; y[dB] = s_y[1][qB]; y[dC] = s_y[2][qc0 + qCl];
+                kq[i] = kappa[slot_of(R, y[0], y[1], y[2])];
+            }
+        }
+    };
+    gather(0);
     for (int qc0 = 0; qc0 < nCc; qc0 += QCH) {
         const int nch = nCc - qc0 < QCH ? nCc - qc0 : QCH;
-        // kappa of the chunk, all loads independent
-        for (int k = t; k < nch * nB * nA; k += NT) {
-            const int qCl = k / (nB * nA), qB = (k / nA) % nB, qA = k % nA;
-            int y[3];
-            y[dA] = s_y[0][qA]; y[dB] = s_y[1][qB]; y[dC] = s_y[2][qc0 + qCl];
-            s_k[(qCl * NW + qB) * NA + qA] = kappa[slot_of(R, y[0], y[1], y[2])];
+#pragma unroll
+        for (int i = 0; i < KQ; ++i) {
+            const int k = t + i * NT;
+            if (k < nch * nB * nA) {
+                const int qCl = k / (nB * nA), qB = (k / nA) % nB, qA = k % nA;
+                s_k[(qCl * NW + qB) * NA + qA] = kq[i];
+            }
         }
         __syncthreads();
+        if (qc0 + QCH < nCc) gather(qc0 + QCH);     // in flight during this chunk's stages
         // stage A: T1[v][qC][qB][jA] = sum_qA W_A^v[jA][qA] kappa(qA, qB, qC)
         for (int it = t; it < nch * nB * M; it += NT) {
             const int qCl = it / (nB * M), qB = (it / M) % nB, jA = it % M;
@@ -435,8 +511,10 @@ k_rows_cut(DevRules R, const T* __restrict__ kappa, T* __restrict__ vm, T* __res
         __syncthreads();                            // s_k / s_t1 are rewritten by the next chunk
     }
     // stage C: items (jC, jB, jA); out[jC][jB][jA]
-    const int32_t* pos = R.pos_map + cr * (int64_t)M * M * M;
-    for (int it = t; it < M * MM; it += NT) {
+#pragma unroll
+    for (int i = 0; i < NPOS; ++i) {
+        const int it = t + i * NT;
+        if (it >= M * MM) break;
         const int jC = it / MM, cc = it % MM, jB = cc / M, jA = cc % M;
         T am = 0, ak = 0;
         for (int qC = 0; qC < nCc; ++qC) {
@@ -445,9 +523,7 @@ k_rows_cut(DevRules R, const T* __restrict__ kappa, T* __restrict__ vm, T* __res
             if (C::MASS) am += a * t0;
             if (C::STIFF) ak += s_w[2][(M + jC) * NA + qC] * t0 + a * s_t2[(1 * NW + qC) * MM + cc];
         }
-        int jj[3];
-        jj[dA] = jA; jj[dB] = jB; jj[dC] = jC;
-        const int k = pos[(jj[0] * M + jj[1]) * M + jj[2]];
+        const int k = pq[i];
         if (k >= 0) {
             if (C::MASS) vm[rb + k] = am;
             if (C::STIFF) vk[rb + k] = ak;
@@ -478,8 +554,10 @@ static void launch_rows_p(const wq_rules* H, const T* kappa, T* vm, T* vk, hipSt
                                vm, vk);
         }
     }
-    if (R.n_cut > 0)
-        hipLaunchKernelGGL((k_rows_cut<T, P, WHICH>), dim3((unsigned)R.n_cut), dim3(256), 0, s, R, kappa, vm, vk);
+    if (R.n_box > 0)
+        hipLaunchKernelGGL((k_rows_cut<T, P, WHICH>), dim3((unsigned)R.n_box), dim3(256), 0, s, R, kappa, vm, vk);
+    if (R.n_cut > R.n_box)
+        hipLaunchKernelGGL((k_rows_zero<T, WHICH>), dim3((unsigned)((R.n_cut + 3) / 4)), dim3(256), 0, s, R, vm, vk);
 }
 
 #ifndef WQ_ONLY_F64
@@ -498,8 +576,10 @@ static void launch_rows_bf3_p(const wq_rules* H, const float* kappa, float* vm, 
                                s, R, kappa, vm, vk);
         }
     }
-    if (R.n_cut > 0)
-        hipLaunchKernelGGL((k_rows_cut<float, P, WHICH>), dim3((unsigned)R.n_cut), dim3(256), 0, s, R, kappa, vm, vk);
+    if (R.n_box > 0)
+        hipLaunchKernelGGL((k_rows_cut<float, P, WHICH>), dim3((unsigned)R.n_box), dim3(256), 0, s, R, kappa, vm, vk);
+    if (R.n_cut > R.n_box)
+        hipLaunchKernelGGL((k_rows_zero<float, WHICH>), dim3((unsigned)((R.n_cut + 3) / 4)), dim3(256), 0, s, R, vm, vk);
 }
 
 template <int P>

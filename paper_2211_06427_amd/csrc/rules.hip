@@ -1180,6 +1180,11 @@ int build_rules(const wq_mesh* mesh, const wq_levelset* ls, const wq_options* op
         if (!sflag || !soff) return B.fail();
         if (ncut > 0) hipLaunchKernelGGL(k_split_flag, grid_for(ncut), dim3(256), 0, stream, ncut, split, sflag);
         if (scan_exclusive(B, sflag, soff, ncut, &H->n_split)) return B.fail();
+        int32_t* sidx = B.tmp<int32_t>(ncut + 1);
+        int32_t* box_rows = B.keep<int32_t>(H->n_split > 0 ? H->n_split : 1);
+        if (!sidx || !box_rows) return B.fail();
+        if (ncut > 0) hipLaunchKernelGGL(k_flag_index, grid_for(ncut), dim3(256), 0, stream, ncut, sflag, soff, sidx, box_rows);
+        R.box_rows = box_rows; R.n_box = H->n_split;
     }
     int64_t ndwq = 0;
     if (scan_exclusive(B, key_used, key_off, nkeys, &ndwq)) return B.fail();
