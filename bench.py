@@ -264,6 +264,21 @@ def main():
     torch.cuda.synchronize()
     bf3["rel_err_vs_fp64"] = {"mass": row_scaled_err(vb[0], vals["f64"][0], rp, torch),
                               "stiff": row_scaled_err(vb[1], vals["f64"][1], rp, torch)}
+    del vb
+    # the three schemes the paper compares: conventional Gauss (Ref), Hybrid Gauss (interior
+    # rows by WQ, the regular support of cut rows by element Gauss) and DWQ (this path)
+    Rh = Rules.from_workload(wl, hybrid_gauss=True)
+    schemes = {k: {"ref_gauss_ms": parts[k].get("gauss_ms"), "dwq_ms": parts[k]["step_ms"]} for k in parts}
+    for k in ("f64", "f32"):
+        vm, vk = vals[k]
+
+        def step_h():
+            Rh.assemble_rows(kap[k], vm, vk)
+            Rh.cut_assemble(kap[k], vm, vk)
+
+        step_h()
+        schemes[k]["hybrid_gauss_ms"] = timed(step_h, nrep, torch)
+    del Rh
 
     # --- rooflines (durations from the timed region) -----------------------------------
     esz = 8 if main_dt == "f64" else 4
@@ -315,6 +330,7 @@ def main():
                                       if kg is not None else None),
         "fp32_rel_err_vs_fp64": err32,
         "bf16x3_experiment": bf3,
+        "schemes_ms": schemes,
         "build_rules_ms": {"cold": build_cold_ms, "warm": build_ms},
     }
     if not args.skip_cpu_baseline:

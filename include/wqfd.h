@@ -77,8 +77,14 @@ typedef struct {
 
 typedef struct {
     int32_t octree_levels;   /* depth of the cut-element octree, 0..5 (default 3) */
-    int32_t flags;           /* reserved, must be 0 */
+    int32_t flags;           /* 0 or WQ_OPT_HYBRID_GAUSS */
 } wq_options;
+
+/* Option flag: the "Hybrid Gauss" scheme of Section 3.1 (list of compared schemes) instead of
+ * DWQ.  Interior rows keep weighted quadrature; no cut row gets a DWQ box, so the whole
+ * regular support of every cut row (its interior elements) is integrated by element Gauss
+ * rules with sum factorization in cut_assemble.  Slots and pattern are unchanged. */
+enum { WQ_OPT_HYBRID_GAUSS = 1 };
 
 typedef struct wq_rules wq_rules;   /* opaque; owns its device buffers */
 

@@ -44,7 +44,7 @@ MASS, STIFF = 1, 2
 class Problem:
     """Everything the oracle derives from a workload (lazily where it is costly)."""
 
-    def __init__(self, wl):
+    def __init__(self, wl, hybrid_gauss=False):
         self.wl = wl
         p = wl.degree
         self.p = p
@@ -61,7 +61,7 @@ class Problem:
             if id(l) not in rcache:
                 rcache[id(l)] = Rules1D(l)
             self.rules.append(rcache[id(l)])
-        self.dom = Domain(self.lines, wl.levelset)
+        self.dom = Domain(self.lines, wl.levelset, hybrid_gauss)
         self._slots = None
         self._dwq = {}
         self._rowptr = None

@@ -87,8 +87,9 @@ def classify_box(ls, lo, hi) -> int:
 class Domain:
     """Element / function types, active numbering, pattern and splits for one workload."""
 
-    def __init__(self, lines, ls):
+    def __init__(self, lines, ls, hybrid_gauss=False):
         self.lines, self.ls = lines, ls
+        self.hybrid_gauss = hybrid_gauss
         self.p = lines[0].p
         p = self.p
         self.nel = tuple(l.nel for l in lines)
@@ -157,7 +158,11 @@ class Domain:
     def split(self, I):
         """(d, s, high, box) for a cut function, or None when no candidate is valid.
 
-        box = ((lo1,hi1),(lo2,hi2),(lo3,hi3)) inclusive element ranges."""
+        box = ((lo1,hi1),(lo2,hi2),(lo3,hi3)) inclusive element ranges.  In the Hybrid Gauss
+        scheme (Section 3.1, the compared schemes) no cut function gets a box: its whole
+        regular support is integrated element by element with Gauss rules."""
+        if self.hybrid_gauss:
+            return None
         if I in self._split:
             return self._split[I]
         best, best_count = None, 0

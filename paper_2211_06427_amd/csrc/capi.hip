@@ -65,7 +65,7 @@ int wq_build_rules(const wq_mesh* mesh, const wq_levelset* ls, const wq_options*
     if (opts) o = *opts;
     if (o.octree_levels < 0 || o.octree_levels > 5)
         return wq_set_error(WQ_EINVAL, "wq_build_rules: octree_levels must be in 0..5 (got %d)", o.octree_levels);
-    if (o.flags != 0) return wq_set_error(WQ_EINVAL, "wq_build_rules: flags must be 0");
+    if (o.flags & ~WQ_OPT_HYBRID_GAUSS) return wq_set_error(WQ_EINVAL, "wq_build_rules: unknown option flags 0x%x", o.flags);
     return build_rules(mesh, ls, &o, (hipStream_t)stream, out);
 }
 

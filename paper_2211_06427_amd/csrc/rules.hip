@@ -447,15 +447,16 @@ __device__ inline int dwq_key(const DevRules& R, int d, int i, int s, int high, 
     return (((d * nmax) + i) * R.p + o) * 2 + (high ? 0 : 1);
 }
 
+// hybrid: no search, every cut row keeps its whole support for the element Gauss part.
 __global__ void k_split(DevRules R, int64_t ncut, const int32_t* cut_rows, const int32_t* act2lex, const int8_t* ecls,
-                        int4* split, int32_t* box, int32_t* key_used, int nmax) {
+                        int4* split, int32_t* box, int32_t* key_used, int nmax, int hybrid) {
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncut) return;
     int I[3], lo[3], hi[3];
     unlex3(act2lex[cut_rows[c]], R.nfun, I);
     fun_support(R, I, lo, hi);
     int best = 0, bd = -1, bs = 0, bh = 0;
-    for (int d = 0; d < 3; ++d) {
+    for (int d = 0; d < (hybrid ? 0 : 3); ++d) {
         for (int s = lo[d] + 1; s <= hi[d]; ++s) {
             for (int side = 0; side < 2; ++side) {
                 int blo[3] = {lo[0], lo[1], lo[2]}, bhi[3] = {hi[0], hi[1], hi[2]};
@@ -1173,7 +1174,7 @@ int build_rules(const wq_mesh* mesh, const wq_levelset* ls, const wq_options* op
     if (na > 0) hipLaunchKernelGGL(k_cut_list, grid_for(na), dim3(256), 0, stream, na, cflag, coff, cut_rows, act2cut);
     if (ncut > 0)
         hipLaunchKernelGGL(k_split, grid_for(ncut, 64), dim3(64), 0, stream, R, ncut, cut_rows, act2lex, ecls, split, box,
-                           key_used, nmax);
+                           key_used, nmax, (opts && (opts->flags & WQ_OPT_HYBRID_GAUSS)) ? 1 : 0);
     {
         int32_t* sflag = B.tmp<int32_t>(ncut + 1);
         int64_t* soff = B.tmp<int64_t>(ncut + 1);

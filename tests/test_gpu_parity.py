@@ -487,6 +487,60 @@ def test_bf16x3_plane48():
         assert e <= BF3_TOL
 
 
+# ------------------------------------------------------------------------------------------
+# Hybrid Gauss scheme (no DWQ boxes)
+@pytest.mark.parametrize("name", ["ball6_p2", "plane6_p3", "torus8_p2", "ball5_p4"])
+def test_hybrid_gauss_matches_oracle(name):
+    wl = SMALL[name]
+    print("case hybrid", name, flush=True)
+    from paper_2211_06427_amd import Rules
+    R = Rules.from_workload(wl, hybrid_gauss=True)
+    P = Problem(wl, hybrid_gauss=True)
+    assert R.n_rows_split == 0 and R.n_dwq_rules == 0
+    assert np.array_equal(R.row_ptr().cpu().numpy(), P.row_ptr())
+    assert R.n_rem_pairs == sum(len(P.remainder_elements(P.dom.unlex(k)))
+                                for k in P.dom.active_lex if P.dom.fcls.ravel()[k] == 2)
+    M, K = P.assemble_full_wq(kappa_numpy(wl))
+    rp = R.row_ptr().cpu().numpy()
+    for dtype in (torch.float64, torch.float32):
+        vm, vk = R.assemble(kappa_slots(R, wl, dtype))
+        torch.cuda.synchronize()
+        for got, ref in ((vm, M), (vk, K)):
+            e_row, e_f = row_errors(got.cpu().numpy(), ref, rp)
+            assert e_row <= TOL[dtype] and e_f <= TOL[dtype], (dtype, e_row, e_f)
+    GM = W.random_values(111, R.nnz)
+    GK = W.random_values(112, R.nnz)
+    ref = P.adjoint(GM, GK)
+    got = R.adjoint(torch.tensor(GM, device=R.device), torch.tensor(GK, device=R.device)).cpu().numpy()
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_hybrid_gauss_plane48():
+    """Full size, 48^3 p=4: Hybrid Gauss cut rows equal the conventional Gauss assembly's rows
+    (the same integrals, element by element) and its interior rows equal the DWQ run's."""
+    wl = W.workload("plane48_p4")
+    print("case hybrid plane48_p4", flush=True)
+    from paper_2211_06427_amd import Rules
+    Rh = Rules.from_workload(wl, hybrid_gauss=True)
+    Rd = rules_for(wl)
+    assert Rh.n_rows_split == 0 and Rh.nnz == Rd.nnz and Rh.n_kappa == Rd.n_kappa
+    rp = Rd.row_ptr()
+    assert torch.equal(rp, Rh.row_ptr())
+    k64 = kappa_slots(Rd, wl, torch.float64)
+    assert torch.equal(Rh.kappa_xyz(), Rd.kappa_xyz())
+    h = Rh.assemble(k64)
+    d = Rd.assemble(k64)
+    g = Rd.gauss_assemble(W.kappa_at(wl, Rd.gauss_coords()), k64)
+    torch.cuda.synchronize()
+    fc = Rd.fun_class().long()[Rd.active_to_lex().long()]
+    rows = torch.repeat_interleave(torch.arange(Rd.n_active, device=rp.device), torch.diff(rp))
+    cut_ent = (fc == 2)[rows]
+    for a, b, c in zip(h, d, g):
+        assert torch.equal(a[~cut_ent], b[~cut_ent])
+        assert _row_scaled(a, c, rp, fc == 2) <= 1e-12
+    del h, d, g
+
+
 def test_errors_are_reported():
     from paper_2211_06427_amd import Rules, WqError
     with pytest.raises(WqError):
