@@ -714,6 +714,151 @@ k_cut_local(DevRules R, const int32_t* __restrict__ elems, const T* __restrict__
     }
 }
 
+// k_cut_local_a2 (degrees 5 and 6): as k_cut_local with one workgroup per (cut element,
+// a3, a2), so that the LDS block of one workgroup is P1 local rows (a1) instead of P1^2:
+// direction 3 is contracted for every a2 (recomputed per workgroup), direction 2 for this
+// a2 only, direction 1 on matrix cores with rows (a1 b1) and columns (b2 b3).
+template <typename T, int P, int WHICH>
+__global__ void __launch_bounds__(256)
+k_cut_local_a2(DevRules R, const int32_t* __restrict__ elems, const T* __restrict__ mom, T* __restrict__ loc) {
+    using C = MomCfg<P>;
+    using MF = MfmaOp<T>;
+    using v4 = typename MF::v4;
+    constexpr int P1 = C::P1, P2 = C::P2, NP = C::NP, NK = C::NK, NK2 = C::NK2, NK3 = C::NK3, NT = C::NT;
+    constexpr int NS1 = C::NS1, NS2 = NK * P2, QN = 2 * P2 * NK;
+    constexpr int MT = (P2 + 15) / 16, NTC = (P2 + 15) / 16, NTW = (NTC + C::NWAVE - 1) / C::NWAVE;
+    constexpr int KS1 = C::KS1, KS2 = C::KS2;
+    constexpr int NROW = P1 * NP;                   // this workgroup's rows a1 x columns b
+    constexpr int NBLK = P2 * NP;                   // one (element, a3, matrix) block of loc
+    constexpr int NSU = (2 * NS1 + 2 * NS2) > NROW ? (2 * NS1 + 2 * NS2) : NROW;
+    constexpr bool MASS = (WHICH & 1) != 0, STIFF = (WHICH & 2) != 0;
+    __shared__ T s_q[3][QN];
+    __shared__ T s_mom[NK3];
+    __shared__ T s_u[NSU];
+    T* s_s1 = s_u;                                  // [2][NS1]
+    T* s_s2 = s_u + 2 * NS1;                        // [2][NS2]
+    T* s_blk = s_u;                                 // [a1][b] after the contractions
+
+    const int ce = blockIdx.x / P2, a3 = (blockIdx.x / P1) % P1, a2 = blockIdx.x % P1;
+    const int64_t eid = elems[ce];
+    int e[3];
+    unlex3i(eid, R.nel, e);
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int lm = lane & 15, lk = lane >> 4;
+    for (int i = t; i < 3 * QN; i += NT) {
+        const int d = i / QN;
+        s_q[d][i % QN] = bern_q<T>(R, d)[(int64_t)e[d] * QN + i % QN];
+    }
+    for (int i = t; i < NK3; i += NT) s_mom[i] = mom[(int64_t)ce * NK3 + i];
+    __syncthreads();
+    const T* qx = s_q[0];
+    const T* qy = s_q[1];
+    const T* qz = s_q[2];
+    // S1_v[k1 k2][b3] = sum_k3 QZ_v[a3 b3][k3] Mom[k1 k2 k3]
+    for (int i = t; i < NS1; i += NT) {
+        const int k12 = i / P1, b3 = i % P1;
+        const T* z0 = qz + (a3 * P1 + b3) * NK;
+        const T* z1 = qz + P2 * NK + (a3 * P1 + b3) * NK;
+        T s0 = 0, s1 = 0;
+#pragma unroll
+        for (int k3 = 0; k3 < NK; ++k3) {
+            const T mo = s_mom[k12 * NK + k3];
+            s0 += z0[k3] * mo;
+            if (STIFF) s1 += z1[k3] * mo;
+        }
+        s_s1[i] = s0;
+        if (STIFF) s_s1[NS1 + i] = s1;
+    }
+    __syncthreads();
+    // S2_0[k1][b2 b3] = sum_k2 QY0[a2 b2][k2] S1_0,  S2_s = sum_k2 (QY1 S1_0 + QY0 S1_1)
+    for (int i = t; i < NS2; i += NT) {
+        const int k1 = i / P2, c = i % P2, b2 = c / P1, b3 = c % P1;
+        const T* y0 = qy + (a2 * P1 + b2) * NK;
+        const T* y1 = qy + P2 * NK + (a2 * P1 + b2) * NK;
+        T m0 = 0, ms = 0;
+#pragma unroll
+        for (int k2 = 0; k2 < NK; ++k2) {
+            const T u0 = s_s1[(k1 * NK + k2) * P1 + b3];
+            m0 += y0[k2] * u0;
+            if (STIFF) ms += y1[k2] * u0 + y0[k2] * s_s1[NS1 + (k1 * NK + k2) * P1 + b3];
+        }
+        s_s2[i] = m0;
+        if (STIFF) s_s2[NS2 + i] = ms;
+    }
+    __syncthreads();
+    // direction 1 on matrix cores: rows m = (a1 b1), columns n = (b2 b3), K = k1
+    v4 accM[NTW][MT], accK[NTW][MT];
+#pragma unroll
+    for (int ti = 0; ti < NTW; ++ti)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) { accM[ti][mt] = v4{0, 0, 0, 0}; accK[ti][mt] = v4{0, 0, 0, 0}; }
+#pragma unroll
+    for (int ti = 0; ti < NTW; ++ti) {
+        const int nt = wv + ti * C::NWAVE;
+        if (nt >= NTC) break;
+        const int n = nt * 16 + lm;
+        const bool nv = n < P2;
+        if (MASS) {
+#pragma unroll
+            for (int k = 0; k < KS1; ++k) {
+                const int k1 = 4 * k + lk;
+                const T bv = (nv && k1 < NK) ? s_s2[k1 * P2 + n] : (T)0;
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) {
+                    const int m = mt * 16 + lm;
+                    const T av = (m < P2 && k1 < NK) ? qx[m * NK + k1] : (T)0;
+                    accM[ti][mt] = MF::mma(av, bv, accM[ti][mt]);
+                }
+            }
+        }
+        if (STIFF) {                                // K = [QX1 | QX0] [S2_0 ; S2_s]
+#pragma unroll
+            for (int k = 0; k < KS2; ++k) {
+                const int kk = 4 * k + lk;
+                T bv = 0;
+                if (nv && kk < NK) bv = s_s2[kk * P2 + n];
+                else if (nv && kk < 2 * NK) bv = s_s2[NS2 + (kk - NK) * P2 + n];
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) {
+                    const int m = mt * 16 + lm;
+                    T av = 0;
+                    if (m < P2 && kk < NK) av = qx[P2 * NK + m * NK + kk];
+                    else if (m < P2 && kk < 2 * NK) av = qx[m * NK + (kk - NK)];
+                    accK[ti][mt] = MF::mma(av, bv, accK[ti][mt]);
+                }
+            }
+        }
+    }
+    // stage each matrix's rows as [a1][(b1 b2 b3)] and store them at rows (a1 P1 + a2)
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+        if ((v == 0 && !MASS) || (v == 1 && !STIFF)) continue;
+        T* out = loc + ((int64_t)(ce * P1 + a3) * 2 + v) * NBLK;
+        __syncthreads();                            // s_u is free (contractions / previous matrix done)
+#pragma unroll
+        for (int ti = 0; ti < NTW; ++ti) {
+            const int nt = wv + ti * C::NWAVE;
+            if (nt >= NTC) break;
+            const int n = nt * 16 + lm;
+            if (n >= P2) continue;
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int m = mt * 16 + MF::row(lane, r);
+                    if (m >= P2) continue;
+                    const int a1 = m / P1, b1 = m % P1;
+                    s_blk[a1 * NP + b1 * P2 + n] = v == 0 ? accM[ti][mt][r] : accK[ti][mt][r];
+                }
+        }
+        __syncthreads();
+        for (int i = t; i < NROW; i += NT) {
+            const int a1 = i / NP, b = i % NP;
+            out[(int64_t)(a1 * P1 + a2) * NP + b] = s_blk[i];
+        }
+    }
+}
+
 // k_cut_gather: one workgroup per cut row adds the local rows of its cut elements (a fixed
 // order, no atomics): NSLOT elements in flight, one lane per column b of the element,
 // per-slot LDS accumulators over the row's (2p+1)^3 window, then one pass over the row.
@@ -922,7 +1067,7 @@ static int launch_cut_p(const wq_rules* H, uint32_t parts, const T* kappa, T* vm
         hipLaunchKernelGGL((k_cut_remainder<T, P, WHICH>), dim3((unsigned)R.n_cut), dim3(RemCfg<P>::NT), 0, s, R, kappa, vm,
                            vk);
     if ((parts & WQ_CUT_OCTREE) && R.n_cut_elems > 0) {
-        if constexpr (P <= 4) {
+        {
             if (R.levels <= 3) {
                 // moments scratch, stream ordered
                 // scratch (stream ordered): moments and local rows of every cut element
@@ -935,8 +1080,12 @@ static int launch_cut_p(const wq_rules* H, uint32_t parts, const T* kappa, T* vm
                     return wq_set_error(WQ_ENOMEM, "cut_assemble: scratch allocation failed: %s", hipGetErrorString(err));
                 T* loc = mom + nmom;
                 hipLaunchKernelGGL((k_cut_moments<T, P>), dim3((unsigned)R.n_cut_elems), dim3(256), 0, s, R, kappa, mom);
-                hipLaunchKernelGGL((k_cut_local<T, P, WHICH>), dim3((unsigned)(R.n_cut_elems * (P + 1))), dim3(256), 0, s, R,
-                                   R.cut_elems, (const T*)mom, loc, nullptr, nullptr, nullptr);
+                if constexpr (P <= 4)
+                    hipLaunchKernelGGL((k_cut_local<T, P, WHICH>), dim3((unsigned)(R.n_cut_elems * (P + 1))), dim3(256), 0, s,
+                                       R, R.cut_elems, (const T*)mom, loc, nullptr, nullptr, nullptr);
+                else
+                    hipLaunchKernelGGL((k_cut_local_a2<T, P, WHICH>), dim3((unsigned)(R.n_cut_elems * (P + 1) * (P + 1))),
+                                       dim3(256), 0, s, R, R.cut_elems, (const T*)mom, loc);
                 if (R.n_cut > 0)
                     hipLaunchKernelGGL((k_cut_gather<T, P, WHICH>), dim3((unsigned)R.n_cut), dim3(RemCfg<P>::NT), 0, s, R,
                                        (const T*)loc, vm, vk);
