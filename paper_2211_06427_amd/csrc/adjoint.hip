@@ -710,6 +710,149 @@ k_adj_local(DevRules R, const int32_t* __restrict__ act2cut, const T* __restrict
     }
 }
 
+// k_adj_local_a2 (degrees 5 and 6): as k_adj_local, with the rows a = (a1, a2, a3) of the
+// workgroup's a3 taken one a2 at a time, so that LDS holds the cotangent block of one a2
+// ([(a1 b1)][(b2 b3)]) instead of all of them; the direction-2 sums VA, VB are accumulated
+// over a2 in registers.
+template <typename T, int P, int WHICH>
+__global__ void __launch_bounds__(256)
+k_adj_local_a2(DevRules R, const int32_t* __restrict__ act2cut, const T* __restrict__ gm, const T* __restrict__ gk,
+               T* __restrict__ part) {
+    using C = MomCfg<P>;
+    using MF = MfmaOp<T>;
+    using v4 = typename MF::v4;
+    constexpr int P1 = C::P1, P2 = C::P2, NP = C::NP, NK = C::NK, NK2 = C::NK2, NK3 = C::NK3, NT = C::NT;
+    constexpr int M = 2 * P + 1, M3 = M * M * M, QN = 2 * P2 * NK;
+    constexpr int NB2 = P2 * P2, NU = NK * P2, NV = NK2 * P1, RV = (NV + NT - 1) / NT;
+    constexpr int NTC = (P2 + 15) / 16, NTW = (NTC + C::NWAVE - 1) / C::NWAVE;
+    constexpr int KA = (2 * P2 + 3) / 4, KB = (P2 + 3) / 4;        // k steps of U0 and Us
+    constexpr bool MASS = (WHICH & 1) != 0, STIFF = (WHICH & 2) != 0;
+    static_assert(NK <= 16, "rows k1 of one MFMA tile");
+    __shared__ T s_q[3][QN];
+    __shared__ T s_g[2][NB2];                       // cotangents of one a2: [(a1 b1)][(b2 b3)]
+    __shared__ T s_u[2][NU];                        // U0, Us [k1][(b2 b3)]
+    __shared__ T s_v[2][NV];                        // VA, VB [k1 k2][b3]
+    __shared__ int64_t s_rb[P2];
+    __shared__ int32_t s_cr[P2];
+    const int ce = blockIdx.x / P1, a3 = blockIdx.x % P1;
+    int e[3];
+    unlex3a(R.cut_elems[ce], R.nel, e);
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int lm = lane & 15, lk = lane >> 4;
+    if (t < P2) {
+        const int a1 = t / P1, a2 = t % P1;
+        const int64_t alex = ((int64_t)(e[0] + a1) * R.nfun[1] + (e[1] + a2)) * R.nfun[2] + (e[2] + a3);
+        const int ra = R.lex2act[alex];
+        s_rb[t] = R.row_ptr[ra];
+        s_cr[t] = act2cut[ra];
+    }
+    for (int i = t; i < 3 * QN; i += NT) {
+        const int d = i / QN;
+        s_q[d][i % QN] = bern_q<T>(R, d)[(int64_t)e[d] * QN + i % QN];
+    }
+    const T* qx = s_q[0];
+    const T* qy = s_q[1];
+    const T* qz = s_q[2];
+    T va_acc[RV], vb_acc[RV];
+#pragma unroll
+    for (int r = 0; r < RV; ++r) { va_acc[r] = 0; vb_acc[r] = 0; }
+    __syncthreads();
+    for (int a2 = 0; a2 < P1; ++a2) {
+        for (int i = t; i < P1 * NP; i += NT) {
+            const int a1 = i / NP, b = i % NP, r = a1 * P1 + a2;
+            const int b1 = b / P2, b2 = (b / P1) % P1, b3 = b % P1;
+            const int jj = ((b1 - a1 + P) * M + (b2 - a2 + P)) * M + (b3 - a3 + P);
+            const int o = R.pos_map[(int64_t)s_cr[r] * M3 + jj];
+            const int dst = (a1 * P1 + b1) * P2 + b2 * P1 + b3;
+            s_g[0][dst] = (MASS && o >= 0) ? gm[s_rb[r] + o] : (T)0;
+            s_g[1][dst] = (STIFF && o >= 0) ? gk[s_rb[r] + o] : (T)0;
+        }
+        __syncthreads();
+        // direction 1 on matrix cores: rows k1, columns n = (b2 b3), K = (a1 b1)
+#pragma unroll
+        for (int ti = 0; ti < NTW; ++ti) {
+            const int nt = wv + ti * C::NWAVE;
+            if (nt >= NTC) break;
+            const int n = nt * 16 + lm;
+            const bool nv = n < P2;
+            v4 u0 = {0, 0, 0, 0}, us = {0, 0, 0, 0};
+#pragma unroll
+            for (int k = 0; k < KA; ++k) {          // U0 = [QX0^T | QX1^T] [GM ; GK]
+                const int kk = 4 * k + lk;
+                T av = 0, bv = 0;
+                if (kk < P2) {
+                    if (MASS) { av = lm < NK ? qx[kk * NK + lm] : (T)0; bv = nv ? s_g[0][kk * P2 + n] : (T)0; }
+                } else if (kk < 2 * P2) {
+                    if (STIFF) {
+                        av = lm < NK ? qx[P2 * NK + (kk - P2) * NK + lm] : (T)0;
+                        bv = nv ? s_g[1][(kk - P2) * P2 + n] : (T)0;
+                    }
+                }
+                u0 = MF::mma(av, bv, u0);
+            }
+            if (STIFF) {
+#pragma unroll
+                for (int k = 0; k < KB; ++k) {      // Us = QX0^T GK
+                    const int kk = 4 * k + lk;
+                    const T av = (kk < P2 && lm < NK) ? qx[kk * NK + lm] : (T)0;
+                    const T bv = (kk < P2 && nv) ? s_g[1][kk * P2 + n] : (T)0;
+                    us = MF::mma(av, bv, us);
+                }
+            }
+            if (nv) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int k1 = MF::row(lane, r);
+                    if (k1 < NK) {
+                        s_u[0][k1 * P2 + n] = u0[r];
+                        if (STIFF) s_u[1][k1 * P2 + n] = us[r];
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // direction 2 for this a2: VA += QY0^T U0 + QY1^T Us, VB += QY0^T Us (sums over b2)
+#pragma unroll
+        for (int r = 0; r < RV; ++r) {
+            const int i = t + r * NT;
+            if (i >= NV) break;
+            const int k1 = i / (NK * P1), k2 = (i / P1) % NK, b3 = i % P1;
+#pragma unroll
+            for (int b2 = 0; b2 < P1; ++b2) {
+                const int ab2 = a2 * P1 + b2;
+                const T y0 = qy[ab2 * NK + k2];
+                va_acc[r] += y0 * s_u[0][k1 * P2 + b2 * P1 + b3];
+                if (STIFF) {
+                    const T u = s_u[1][k1 * P2 + b2 * P1 + b3];
+                    va_acc[r] += qy[P2 * NK + ab2 * NK + k2] * u;
+                    vb_acc[r] += y0 * u;
+                }
+            }
+        }
+        // the next a2 rewrites s_g, then s_u after the barrier that follows its gather
+    }
+#pragma unroll
+    for (int r = 0; r < RV; ++r) {
+        const int i = t + r * NT;
+        if (i < NV) {
+            s_v[0][i] = va_acc[r];
+            s_v[1][i] = vb_acc[r];
+        }
+    }
+    __syncthreads();
+    // direction 3: Gmom share = QZ0^T VA + QZ1^T VB for this a3
+    for (int i = t; i < NK3; i += NT) {
+        const int k12 = i / NK, k3 = i % NK;
+        T g = 0;
+#pragma unroll
+        for (int b3 = 0; b3 < P1; ++b3) {
+            g += qz[(a3 * P1 + b3) * NK + k3] * s_v[0][k12 * P1 + b3];
+            if (STIFF) g += qz[P2 * NK + (a3 * P1 + b3) * NK + k3] * s_v[1][k12 * P1 + b3];
+        }
+        part[((int64_t)ce * P1 + a3) * NK3 + i] = g;
+    }
+}
+
 // k_adj_leaves: one workgroup per cut element sums the a3 shares of Gmom and evaluates
 // dL/dkappa at every point of its leaves: direction 1 once per x-group, direction 2 once per
 // column, direction 3 per leaf.  Every octree slot belongs to one element: plain stores.
@@ -800,13 +943,13 @@ k_adj_leaves(DevRules R, const T* __restrict__ part, T* __restrict__ dk) {
                     __syncthreads();
                 }
                 // this leaf: dk(g) = w_g sum_k3 B_k3(z_g3) Gz[g1 g2][k3]
-                if (t < NP) {
+                for (int g = t; g < NP; g += NT) {         // NP > NT from p = 6 on
                     const T* bz = s_bi + ivl(key, 2) * NK * P1;
-                    const int g12 = t / P1, g3 = t % P1;
+                    const int g12 = g / P1, g3 = g % P1;
                     T s = 0;
 #pragma unroll
                     for (int k3 = 0; k3 < NK; ++k3) s += bz[k3 * P1 + g3] * s_gz[g12 * NK + k3];
-                    dk[oct0 + (int64_t)s_cell[j] * NP + t] = s_w[buf][jl * NP + t] * s;
+                    dk[oct0 + (int64_t)s_cell[j] * NP + g] = s_w[buf][jl * NP + g] * s;
                 }
             }
         }
@@ -831,15 +974,19 @@ static int launch_adj_p(const wq_rules* H, const T* gm, const T* gk, T* dk, hipS
                            dk);
     }
     if (R.n_cut_elems > 0) {
-        if constexpr (P <= 4) {
+        {
             if (R.levels <= 3) {
                 using C = MomCfg<P>;
                 T* part = nullptr;
                 hipError_t err = H->scratch_alloc((void**)&part, sizeof(T) * (size_t)R.n_cut_elems * C::P1 * C::NK3, s);
                 if (err != hipSuccess)
                     return wq_set_error(WQ_ENOMEM, "wq_assemble_adjoint: scratch allocation failed: %s", hipGetErrorString(err));
-                hipLaunchKernelGGL((k_adj_local<T, P, WHICH>), dim3((unsigned)(R.n_cut_elems * C::P1)), dim3(256), 0, s, R,
-                                   H->act2cut, gm, gk, part);
+                if constexpr (P <= 4)
+                    hipLaunchKernelGGL((k_adj_local<T, P, WHICH>), dim3((unsigned)(R.n_cut_elems * C::P1)), dim3(256), 0, s,
+                                       R, H->act2cut, gm, gk, part);
+                else
+                    hipLaunchKernelGGL((k_adj_local_a2<T, P, WHICH>), dim3((unsigned)(R.n_cut_elems * C::P1)), dim3(256), 0,
+                                       s, R, H->act2cut, gm, gk, part);
                 hipLaunchKernelGGL((k_adj_leaves<T, P>), dim3((unsigned)R.n_cut_elems), dim3(256), 0, s, R, (const T*)part, dk);
                 err = hipFreeAsync(part, s);
                 if (err != hipSuccess)
