@@ -566,6 +566,46 @@ def test_hybrid_gauss_plane48():
     del h, d, g
 
 
+# ------------------------------------------------------------------------------------------
+# octree depths other than 3: the moment form covers depths 0-3, deeper octrees take the
+# direct per-point cut-element kernels (forward and adjoint)
+DEPTHS = {
+    "ball5_p2_L0": W.custom(5, 2, BALL, kappa="sin3", octree_levels=0),
+    "ball5_p2_L1": W.custom(5, 2, BALL, kappa="sin3", octree_levels=1),
+    "ball5_p2_L2": W.custom(5, 2, BALL, kappa="sin3", octree_levels=2),
+    "ball5_p2_L4": W.custom(5, 2, BALL, kappa="sin3", octree_levels=4),
+    "ball4_p4_L4": W.custom(4, 4, BALL, kappa="rf", seed=7, octree_levels=4),
+    "ball4_p3_L5": W.custom(4, 3, BALL, kappa="rf", seed=7, octree_levels=5),
+}
+
+
+@pytest.mark.parametrize("name", list(DEPTHS))
+def test_octree_depths_match_oracle(name):
+    wl = DEPTHS[name]
+    print("case depth", name, flush=True)
+    R = rules_for(wl)
+    P = Problem(wl)
+    assert R.n_kappa == P.slots().n_slots
+    ow = R.octree_w().cpu().numpy()
+    sl = P.slots()
+    ref_w = np.concatenate([sl.octree(e)[1] for e in sl.cut]) if sl.cut else np.zeros(0)
+    assert np.abs(ow - ref_w).max(initial=0.0) <= 8e-15 * max(np.abs(ref_w).max(initial=0.0), 1e-300)
+    M, K = P.assemble_full_wq(kappa_numpy(wl))
+    rp = R.row_ptr().cpu().numpy()
+    for dtype in (torch.float64, torch.float32):
+        vm, vk = R.assemble(kappa_slots(R, wl, dtype))
+        torch.cuda.synchronize()
+        for got, ref in ((vm, M), (vk, K)):
+            e_row, e_f = row_errors(got.cpu().numpy(), ref, rp)
+            assert e_row <= TOL[dtype] and e_f <= TOL[dtype], (dtype, e_row, e_f)
+    GM = W.random_values(121, R.nnz)
+    GK = W.random_values(122, R.nnz)
+    ref = P.adjoint(GM, GK)
+    got = R.adjoint(torch.tensor(GM, device=R.device), torch.tensor(GK, device=R.device)).cpu().numpy()
+    tol = max(1e-12, np.finfo(np.float64).eps / 2 * max(wq_condition(l, a) for l in P.lines for a in (0, 1)))
+    assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
+
+
 def test_errors_are_reported():
     from paper_2211_06427_amd import Rules, WqError
     with pytest.raises(WqError):
