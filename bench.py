@@ -160,8 +160,8 @@ def main():
         copy_probe()
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the row assembly is not "
-              f"distributed in this build.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the library assembles on a "
+              f"single device.", file=sys.stderr)
         sys.exit(2)
     import torch
 

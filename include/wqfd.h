@@ -41,7 +41,7 @@ typedef enum {
     WQ_ENOMEM = -2,       /* device allocation failed */
     WQ_EHIP = -3,         /* HIP runtime error (message has the HIP error string) */
     WQ_ESINGULAR = -4,    /* a WQ exactness system was rank deficient */
-    WQ_EUNSUPPORTED = -5  /* valid request outside this build's limits (e.g. p > 6) */
+    WQ_EUNSUPPORTED = -5  /* valid request outside the library's limits (e.g. p > 6) */
 } wq_status;
 
 /* WQ_BF16X3 (an experiment, forward assembly only): values and kappa are float as for
