@@ -21,6 +21,10 @@ template <> __device__ inline const float* dwq_table<float>(const DevRules& R) {
 
 __device__ inline int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// value along direction d of a triple given in the order (A, B, C) of directions (dA, dB,
+// the remaining one): selects rather than an indexed array, so nothing goes to scratch
+__device__ inline int pick3(int d, int dA, int dB, int a, int b, int c) { return d == dA ? a : (d == dB ? b : c); }
+
 // ----------------------------------------------------------------------------------------
 // interior rows
 // ----------------------------------------------------------------------------------------
@@ -360,7 +364,7 @@ struct CutCfg {
     static constexpr int M = 2 * P + 1, NW = 4 * P, NDQ = P * (P + 1), MM = M * M;
     static constexpr int NA = NDQ > NW ? NDQ : NW;         // the split direction may hold a DWQ rule
     static constexpr int NT = 256;
-    static constexpr int QCH = sizeof(T) == 4 ? 8 : (P <= 4 ? 8 : 4);   // direction-C points per chunk
+    static constexpr int QCH = sizeof(T) == 8 && P > 4 ? 4 : 2;   // direction-C points per chunk (small: occupancy)
     static constexpr bool STIFF = (WHICH & 2) != 0;
     static constexpr bool MASS = (WHICH & 1) != 0;
 };
@@ -419,9 +423,8 @@ k_rows_cut(DevRules R, const T* __restrict__ kappa, T* __restrict__ vm, T* __res
         const int it = t + i * NT;
         pq[i] = -1;
         if (it < M * MM) {
-            int jj[3];
-            jj[dA] = it % M; jj[dB] = (it / M) % M; jj[dC] = it / MM;
-            pq[i] = pos[(jj[0] * M + jj[1]) * M + jj[2]];
+            const int jA = it % M, jB = (it / M) % M, jC = it / MM;
+            pq[i] = pos[(pick3(0, dA, dB, jA, jB, jC) * M + pick3(1, dA, dB, jA, jB, jC)) * M + pick3(2, dA, dB, jA, jB, jC)];
         }
     }
     // rules into LDS: s_w[slot][a][jj][q] with q stride NA
@@ -461,9 +464,9 @@ k_rows_cut(DevRules R, const T* __restrict__ kappa, T* __restrict__ vm, T* __res
             const int k = t + i * NT;
             if (k < nch * nB * nA) {
                 const int qCl = k / (nB * nA), qB = (k / nA) % nB, qA = k % nA;
-                int y[3];
-                y[dA] = s_y[0][qA]; y[dB] = s_y[1][qB]; y[dC] = s_y[2][qc0 + qCl];
-                kq[i] = kappa[slot_of(R, y[0], y[1], y[2])];
+                const int yA = s_y[0][qA], yB = s_y[1][qB], yC = s_y[2][qc0 + qCl];
+                kq[i] = kappa[slot_of(R, pick3(0, dA, dB, yA, yB, yC), pick3(1, dA, dB, yA, yB, yC),
+                                      pick3(2, dA, dB, yA, yB, yC))];
             }
         }
     };
