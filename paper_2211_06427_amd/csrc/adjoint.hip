@@ -188,7 +188,7 @@ k_adj_cut(DevRules R, const T* __restrict__ gm, const T* __restrict__ gk, T* __r
     __shared__ int s_n[3];
     __shared__ T s_g[2][M3];                      // cotangent window [v][jC][jB][jA]
     __shared__ T s_c[2][NW * MM];                 // [v][qC][jB jA]
-    const int64_t cr = blockIdx.x;
+    const int64_t cr = R.box_rows[blockIdx.x];     // cut rows with a DWQ box only
     const int4 sp = R.split[cr];
     if (sp.x < 0) return;
     const int ra = R.cut_rows[cr];
@@ -225,9 +225,10 @@ k_adj_cut(DevRules R, const T* __restrict__ gm, const T* __restrict__ gk, T* __r
     const int64_t rb = R.row_ptr[ra];
     for (int k = threadIdx.x; k < M3; k += 256) {
         const int jj0 = k / (M * M), jj1 = (k / M) % M, jj2 = k % M;
-        const int jj[3] = {jj0, jj1, jj2};
         const int o = pos[k];
-        const int l = (jj[dC] * M + jj[dB]) * M + jj[dA];
+        // the component of (jj0, jj1, jj2) along direction d
+        auto along = [&](int d) { return d == 0 ? jj0 : (d == 1 ? jj1 : jj2); };
+        const int l = (along(dC) * M + along(dB)) * M + along(dA);
         s_g[0][l] = (o >= 0 && MASS) ? gm[rb + o] : (T)0;
         s_g[1][l] = (o >= 0 && STIFF) ? gk[rb + o] : (T)0;
     }
@@ -265,17 +266,17 @@ k_adj_cut(DevRules R, const T* __restrict__ gm, const T* __restrict__ gk, T* __r
             }
             b0[jA] = s0; b1[jA] = s1;
         }
-        int y[3];
-        y[dB] = s_y[1][qB]; y[dC] = s_y[2][qC];
+        const int yB = s_y[1][qB], yC = s_y[2][qC];
         for (int qA = 0; qA < nA; ++qA) {
-            y[dA] = s_y[0][qA];
+            const int yA = s_y[0][qA];
             T v = 0;
 #pragma unroll
             for (int jA = 0; jA < M; ++jA) {
                 v += s_w[0][jA * NA + qA] * b0[jA];
                 if (STIFF) v += s_w[0][(M + jA) * NA + qA] * b1[jA];
             }
-            atomicAdd(&dk[slot_of(R, y[0], y[1], y[2])], v);
+            atomicAdd(&dk[slot_of(R, pick3(0, dA, dB, yA, yB, yC), pick3(1, dA, dB, yA, yB, yC),
+                                  pick3(2, dA, dB, yA, yB, yC))], v);
         }
     }
 }
@@ -969,7 +970,8 @@ static int launch_adj_p(const wq_rules* H, const T* gm, const T* gk, T* dk, hipS
         }
     }
     if (R.n_cut > 0) {
-        hipLaunchKernelGGL((k_adj_cut<T, P, WHICH>), dim3((unsigned)R.n_cut), dim3(256), 0, s, R, gm, gk, dk);
+        if (R.n_box > 0)
+            hipLaunchKernelGGL((k_adj_cut<T, P, WHICH>), dim3((unsigned)R.n_box), dim3(256), 0, s, R, gm, gk, dk);
         hipLaunchKernelGGL((k_adj_remainder<T, P, WHICH>), dim3((unsigned)R.n_cut), dim3(RemAdjCfg<P>::NT), 0, s, R, gm, gk,
                            dk);
     }

@@ -205,6 +205,10 @@ __device__ __host__ inline int classify_box(const wq_levelset& ls, const double*
 // Slot of a Gauss point (y1, y2, y3): the WQ grid when all three are WQ points, else the
 // element's Gauss block.
 // ----------------------------------------------------------------------------------------
+// value along direction d of a triple given in the order (A, B, C) of directions (dA, dB,
+// the remaining one): selects rather than an indexed array, so nothing goes to scratch
+__device__ inline int pick3(int d, int dA, int dB, int a, int b, int c) { return d == dA ? a : (d == dB ? b : c); }
+
 __device__ inline int64_t slot_of(const DevRules& R, int y1, int y2, int y3) {
     int x1 = R.y2x[0][y1], x2 = R.y2x[1][y2], x3 = R.y2x[2][y3];
     if (x1 >= 0 && x2 >= 0 && x3 >= 0) return ((int64_t)x1 * R.nx[1] + x2) * R.nx[2] + x3;

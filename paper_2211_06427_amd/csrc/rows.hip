@@ -21,10 +21,6 @@ template <> __device__ inline const float* dwq_table<float>(const DevRules& R) {
 
 __device__ inline int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// value along direction d of a triple given in the order (A, B, C) of directions (dA, dB,
-// the remaining one): selects rather than an indexed array, so nothing goes to scratch
-__device__ inline int pick3(int d, int dA, int dB, int a, int b, int c) { return d == dA ? a : (d == dB ? b : c); }
-
 // ----------------------------------------------------------------------------------------
 // interior rows
 // ----------------------------------------------------------------------------------------
