@@ -75,8 +75,8 @@ def copy_probe():
 # kernel source they were taken on: the digest of its text is checked, else traffic is null.
 TRAFFIC = {
     # (kernel, workload, dtype): (sha1 of the kernel's source text, fetch KiB, write KiB)
-    ("k_cut_remainder", "plane48_p4", "f32"): ("4702b1d161c06f3db40fc5605189d82d9b73aec3", 159328.8, 115167.4),
-    ("k_cut_remainder", "plane48_p4", "f64"): ("4702b1d161c06f3db40fc5605189d82d9b73aec3", 250609.2, 228916.3),
+    ("k_cut_remainder", "plane48_p4", "f32"): ("4702b1d161c06f3db40fc5605189d82d9b73aec3", 159367.3, 115167.4),
+    ("k_cut_remainder", "plane48_p4", "f64"): ("4702b1d161c06f3db40fc5605189d82d9b73aec3", 250484.9, 228916.3),
 }
 
 
