@@ -166,6 +166,38 @@ def exact_gram(line: Line, tk: np.ndarray, i: int, j: int, a: int) -> float:
     return s
 
 
+def exactness_system(line: Line, tk: np.ndarray, i: int, a: int, xq: np.ndarray):
+    """Exactness conditions of the rule of test function i at points xq: (A, b), one row
+    per condition, A[c, q] = (condition function c)(x_q).
+
+    a = 0: the conditions are sum_q w_q B_j(x_q) = int B_i B_j for every j whose support
+    overlaps supp B_i in positive measure.
+    a = 1: the conditions sum_q w_q B_j'(x_q) = int B_i' B_j' for those j span, on supp B_i,
+    the same space as the degree p-1 B-splines N_k over the same knots that are nonzero
+    there (each B_j' is a combination of N_j and N_{j+1}; the B_j' lose one dimension
+    because they sum to zero on the support).  Imposing sum_q w_q N_k(x_q) = int B_i' N_k
+    for those k therefore gives the same set of admissible weights, with one condition
+    per dimension instead of a redundant one."""
+    p = line.p
+    t = line.knot_coord(tk)
+    sa, sb = support(tk, p, i)
+    if a == 0:
+        J = [j for j in range(len(tk) - p - 1)
+             if max(sa, support(tk, p, j)[0]) < min(sb, support(tk, p, j)[1])]
+        A = np.array([bspline(t, p, j, xq) for j in J])
+        b = np.array([exact_gram(line, tk, i, j, 0) for j in J])
+        return A, b
+    K = [k for k in range(len(tk) - p) if tk[k] < tk[k + p] and max(sa, tk[k]) < min(sb, tk[k + p])]
+    A = np.array([bspline(t, p - 1, k, xq) for k in K])
+    b = np.zeros(len(K))
+    g = np.arange(p + 1)
+    for c, k in enumerate(K):
+        for e in range(max(sa, int(tk[k])), min(sb, int(tk[k + p]))):
+            x = line.gauss_coord(e, g)
+            b[c] += float(np.sum(line.gauss_weight(g) * bspline(t, p, i, x, 1) * bspline(t, p - 1, k, x)))
+    return A, b
+
+
 def wq_rule(line: Line, tk: np.ndarray, pts, full_gauss: set, i: int, a: int):
     """Weighted-quadrature rule of test function i (knots tk) for derivative order a.
 
@@ -176,47 +208,26 @@ def wq_rule(line: Line, tk: np.ndarray, pts, full_gauss: set, i: int, a: int):
     overlaps supp B_i in a set of positive measure.  If every element of supp B_i
     keeps all Gauss points, the Gauss weights times B_i^(a) are used directly
     (Section 2.2, last paragraph).  Otherwise the rule is the minimum-Euclidean-norm
-    solution of the (consistent, possibly underdetermined) system, computed by SVD.
+    solution of the (consistent, underdetermined) system after scaling each condition
+    to unit norm (the solution does not depend on that scaling; it only removes the
+    spread of the rows' magnitudes from the conditioning): with the QR factorization
+    A^T = Q R (full row rank), w = Q R^-T b is the solution in the row space of A.  For
+    a = 1 the conditions are posed on the derivative space's own B-splines
+    (`exactness_system`), which fixes the same weights without the redundant condition.
     """
     p = line.p
     t = line.knot_coord(tk)
-    nfun = len(tk) - p - 1
     sa, sb = support(tk, p, i)
     Q = [(e, g) for (e, g) in pts if sa <= e < sb]
     xq = line.coord(Q)
     if all(e in full_gauss for e in range(sa, sb)):
         wg = np.array([line.gauss_weight(g) for (_, g) in Q])
         return Q, wg * bspline(t, p, i, xq, a)
-    J = [j for j in range(nfun)
-         if max(sa, support(tk, p, j)[0]) < min(sb, support(tk, p, j)[1])]
-    A = np.array([bspline(t, p, j, xq, a) for j in J])
-    b = np.array([exact_gram(line, tk, i, j, a) for j in J])
-    w = np.linalg.lstsq(A, b, rcond=1e-11)[0]
+    A, b = exactness_system(line, tk, i, a, xq)
+    s = 1.0 / np.linalg.norm(A, axis=1)
+    Qf, Rf = np.linalg.qr((A * s[:, None]).T)
+    w = Qf @ np.linalg.solve(Rf.T, b * s)
     return Q, w
-
-
-def wq_condition(line: Line, a: int) -> float:
-    """Largest 2-norm condition number, over the nonzero singular values that the solve in
-    `wq_rule` keeps, of the min-norm systems of the standard rules of one direction (0 when
-    every rule takes the Gauss shortcut).  The individual weights of a min-norm rule are
-    fixed by floating point only to about this many units of roundoff; sums that the
-    exactness conditions constrain (a matrix entry with a smooth coefficient) are not
-    affected, a single weight is.  Used to set tolerances, not part of the method."""
-    p = line.p
-    tk = line.tk
-    t = line.knot_coord(tk)
-    nfun = len(tk) - p - 1
-    worst = 0.0
-    for i in range(nfun):
-        sa, sb = support(tk, p, i)
-        if all(e in line.full_gauss_elems for e in range(sa, sb)):
-            continue
-        xq = line.coord([(e, g) for (e, g) in line.X if sa <= e < sb])
-        J = [j for j in range(nfun) if max(sa, support(tk, p, j)[0]) < min(sb, support(tk, p, j)[1])]
-        s = np.linalg.svd(np.array([bspline(t, p, j, xq, a) for j in J]), compute_uv=False)
-        s = s[s > 1e-11 * s[0]]
-        worst = max(worst, float(s[0] / s[-1]))
-    return worst
 
 
 class Rules1D:

@@ -252,3 +252,24 @@ def test_dwq_one_sided_exactness(p):
                     tot[j] = tot.get(j, 0.0) + got
             for j in range(line.n):
                 assert abs(tot[j] - fine_gram(line, line.tk, i, j, a)) <= 1e-12 * abs(fine_gram(line, line.tk, i, i, a))
+
+
+# smallest positive Gauss-Legendre node of order p+1 (tabulated values, 6 digits)
+ZETA = {2: 0.774597, 3: 0.339981, 4: 0.538469, 5: 0.238619, 6: 0.405845}
+
+
+@pytest.mark.parametrize("p", range(2, 7))
+def test_kept_pair_is_nearest_midpoint_pair(p):
+    """Reading of the point layout (Section 2.2, layout paragraph): an element that is
+    neither the first nor the last of its direction keeps the Gauss pair +-zeta_p around
+    its midpoint, zeta_p the smallest positive node of the (p+1)-point rule; the boundary
+    elements keep all p+1 points."""
+    line = Line(6, p)
+    for e in range(1, line.nel - 1):
+        xi = np.array([line.gxi[g] for g in line.kept[e]])
+        assert np.allclose(xi, [-ZETA[p], ZETA[p]], rtol=0, atol=1e-6)
+        x = line.coord([(e, g) for g in line.kept[e]])
+        mid = line.lo + (e + 0.5) * line.h
+        assert np.allclose(x, [mid - ZETA[p] * line.h / 2, mid + ZETA[p] * line.h / 2], rtol=0, atol=1e-6 * line.h)
+    for e in (0, line.nel - 1):
+        assert line.kept[e] == list(range(p + 1))

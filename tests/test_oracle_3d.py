@@ -252,6 +252,38 @@ def test_split_is_valid_and_maximal():
     assert n_box > 0
 
 
+def test_split_tie_break():
+    """Reading of the split search (Section 2.2 step 2 and the 3D paragraph after Fig. 3):
+    among valid boxes with the most elements the first in the order d ascending, s
+    ascending, high side before low wins.  Two hand-built element patterns inside the
+    3 x 3 x 3 support of a p = 2 function produce ties."""
+    P = Problem(W.custom(6, 2))
+    dom = P.dom
+    I = (3, 3, 3)
+    rng = [dom.support_range(I, d) for d in range(3)]
+    assert rng == [(1, 3)] * 3
+
+    def run(cut_elems):
+        dom.ecls[...] = IN
+        for e in cut_elems:
+            dom.ecls[e] = CUT
+        dom._split = {}
+        return dom.split(I)
+
+    # an edge column (first two offsets 0) is cut: d = 0 and d = 1 (s = 2, high side)
+    # both keep 18 elements; d = 0 comes first
+    sp = run([(1, 1, c) for c in range(1, 4)])
+    assert sp[:3] == (0, 2, True) and sp[3] == ((2, 3), (1, 3), (1, 3))
+    # the middle slab in direction 0 is cut: (s = 2, low) and (s = 3, high) both keep 9
+    # elements; s = 2 comes first
+    sp = run([(2, b, c) for b in range(1, 4) for c in range(1, 4)])
+    assert sp[:3] == (0, 2, False) and sp[3] == ((1, 1), (1, 3), (1, 3))
+    # the far corner slab in direction 1 is cut: (d = 1, s = 2, low) keeps 9 elements,
+    # (d = 1, s = 3, low) keeps 18 and wins over the smaller valid boxes
+    sp = run([(a, 3, c) for a in range(1, 4) for c in range(1, 4)])
+    assert sp[:3] == (1, 3, False) and sp[3] == ((1, 3), (1, 2), (1, 3))
+
+
 # ------------------------------------------------------------------------------------------
 def test_octree_plane_volume_converges():
     """Octree weights of a cut element -> exact volume of the element below the plane."""
