@@ -322,17 +322,22 @@ class Problem:
                 out.setdefault(e, set()).add(I)
         return out
 
-    def assemble_full_wq(self, kappa_fn):
+    def assemble_full_wq(self, kappa_fn, share=(0, 1)):
         """Whole WQ/DWQ matrices (CSR values over row_ptr / csr_cols).
 
         Regular parts row by row; remainder-element and cut-element parts are the same
-        sums grouped by element (each element's points serve all rows that use them)."""
+        sums grouped by element (each element's points serve all rows that use them).
+        share = (k, n): only every n-th row and element starting at the k-th; the n
+        shares sum to the whole matrices (lets a caller spread the loops over processes)."""
+        k0, ns = share
         dom = self.dom
         row_ptr = self.row_ptr()
         cols = self.csr_cols()
         M = np.zeros(row_ptr[-1])
         K = np.zeros(row_ptr[-1])
         for r, k in enumerate(dom.active_lex):
+            if r % ns != k0:
+                continue
             I = dom.unlex(k)
             reg = self.regular_part(I)
             if reg is None:
@@ -340,11 +345,15 @@ class Problem:
             _, m, kk = self.assemble_row(I, kappa_fn, parts=[reg])
             M[row_ptr[r]:row_ptr[r + 1]] += m
             K[row_ptr[r]:row_ptr[r + 1]] += kk
-        for e, rows in self.remainder_rows_by_element().items():
+        for c, (e, rows) in enumerate(self.remainder_rows_by_element().items()):
+            if c % ns != k0:
+                continue
             x, w = self._element_gauss_points(e)
             self._add_element_local(e, x, w, kappa_fn, row_ptr, cols, M, K, rows_filter=rows)
         sl = self.slots(with_octree=False)
-        for e in dom.cut_elements():
+        for c, e in enumerate(dom.cut_elements()):
+            if c % ns != k0:
+                continue
             x, w = sl.octree(e)
             self._add_element_local(e, x, w, kappa_fn, row_ptr, cols, M, K)
         return M, K
@@ -388,28 +397,36 @@ class Problem:
         contrib += sum(np.sum(dPhi[c] * (gk @ dPhi[c]), axis=0) for c in range(3))
         np.add.at(dk, slot, w * contrib)
 
-    def adjoint(self, GM, GK):
+    def adjoint(self, GM, GK, share=(0, 1)):
         """dL/dkappa over all slots for cotangents GM, GK given as CSR value arrays (or None).
 
-        Regular parts row by row; element parts grouped by element as in assemble_full_wq."""
+        Regular parts row by row; element parts grouped by element as in assemble_full_wq
+        (share as there: the n shares sum to the whole gradient)."""
+        k0, ns = share
         dom = self.dom
         sl = self.slots(with_octree=True)
         row_ptr = self.row_ptr()
         cols = self.csr_cols()
         dk = np.zeros(sl.n_slots)
         for r, k in enumerate(dom.active_lex):
+            if r % ns != k0:
+                continue
             I = dom.unlex(k)
             part = self.regular_part(I, slots=sl)
             if part is None:
                 continue
             self._adjoint_rowpart(I, part, GM, GK, row_ptr[r], row_ptr[r + 1], dk)
         p1 = self.p + 1
-        for e, rows in self.remainder_rows_by_element().items():
+        for ce, (e, rows) in enumerate(self.remainder_rows_by_element().items()):
+            if ce % ns != k0:
+                continue
             x, w = self._element_gauss_points(e)
             slot = np.array([sl.gauss_slot(((e[0], a), (e[1], b), (e[2], c)))
                              for a, b, c in itertools.product(range(p1), repeat=3)])
             self._adjoint_element(e, x, w, slot, GM, GK, row_ptr, cols, dk, rows_filter=rows)
-        for e in dom.cut_elements():
+        for c, e in enumerate(dom.cut_elements()):
+            if c % ns != k0:
+                continue
             x, w = sl.octree(e)
             slot = sl.oct_base[e] + np.arange(len(w))
             self._adjoint_element(e, x, w, slot, GM, GK, row_ptr, cols, dk)

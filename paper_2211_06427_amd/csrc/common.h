@@ -14,7 +14,7 @@
 
 // Device view of a rules handle; passed by value to kernels.
 struct DevRules {
-    int p, m, nw, ndq;                  // degree, 2p+1, 3p+1, p(p+1)
+    int p, m, nw, ndq;                  // degree, 2p+1, 4p (weight-table stride), p(p+1)
     int nel[3], nfun[3], nx[3], ny[3];
     double lo[3], h[3];
     int levels;
@@ -43,6 +43,8 @@ struct DevRules {
     // interior line blocks: (i1 start, i2, i3, count)
     const int4* lblocks;
     int64_t n_lblocks;
+    const int4* fblocks;                // the same runs cut into blocks of at most 8 rows (FP32 rows, p <= 4)
+    int64_t n_fblocks;
     // cut rows
     const int32_t* cut_rows;            // active index
     const int4* split;                  // d, s, high, dwq rule (-1: none)

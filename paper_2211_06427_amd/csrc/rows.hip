@@ -353,6 +353,244 @@ k_rows_interior(DevRules R, const T* __restrict__ kappa, T* __restrict__ vm, T* 
 }
 
 // ----------------------------------------------------------------------------------------
+// interior rows, FP32, p <= 4: one workgroup per block of up to RB rows along direction 1
+// ----------------------------------------------------------------------------------------
+// A window of function i along a direction is regular when supp B_i holds p+1 elements that
+// each keep two points and every trial function of the row window exists (i in
+// [p+1, nel-2]): point q then lies in window element q/2 and W[jj][q] can be nonzero only for
+// jj in [q/2, q/2+p], so every contraction over such a window runs over a compile-time band.
+// Other windows (near the boundary) run over their points with the zero-padded tables.
+// Every direction must have at least p+2 elements (windows of at most 3p+1 points).
+template <int P, int RB>
+struct BlkCfg {
+    static constexpr int M = 2 * P + 1, MM = M * M, NT = 256;
+    static constexpr int NWT = 4 * P;                  // row stride of the weight tables
+    static constexpr int NWB = 3 * P + 1;              // largest window
+    static constexpr int NR = 2 * P + 2;               // points of a regular window
+    static constexpr int NQB = 2 * RB + 4 * P - 2;     // direction-1 points of a block
+    static constexpr int T1N = 2 * NQB * NWB * M;      // stage-1 sums; the slab reuses the space
+};
+
+__device__ inline bool regular_window(int i, int p, int nel) { return i >= p + 1 && i <= nel - 2; }
+
+// Stages, for the block's rows i1s..i1s+nrows-1 at fixed (i2, i3) and the union of their
+// direction-1 windows (planes q1 of the kappa grid):
+//   1. T1_v[q1][q2][j3] = sum_q3 W3_v[j3][q3] kappa[q1][q2][q3], v = 00 / 11 rules
+//      (one thread per (q1, q2), kappa read straight from the grid);
+//   2. T2[q1][j2 j3] = sum_q2 W2_00[j2][q2] T1_00, Ts = sum_q2 W2_11 T1_00 + W2_00 T1_11
+//      (one thread per (q1, j3));
+//   3. row r, column c = (j2, j3): M[j1][c] = sum_q W1_00[j1][q] T2[off_r + q][c],
+//      K = sum_q W1_11 T2 + W1_00 Ts (one thread per (row, column); all of a block's rows
+//      share the slab), stored at the row's CSR offsets (contiguous per j1).
+template <int P, int WHICH, int RB>
+__global__ void __launch_bounds__(256, 3)
+k_rows_block(DevRules R, const float* __restrict__ kappa, float* __restrict__ vm, float* __restrict__ vk) {
+    using C = BlkCfg<P, RB>;
+    constexpr int M = C::M, MM = C::MM, NT = C::NT, NWT = C::NWT, NWB = C::NWB, NR = C::NR, NQB = C::NQB;
+    constexpr bool MASS = (WHICH & 1) != 0, STIFF = (WHICH & 2) != 0;
+    __shared__ float s_buf[C::T1N];
+    __shared__ float s_w1[RB * 2 * M * NWT];
+    __shared__ float s_w2[2 * M * NWT], s_w3[2 * M * NWT];
+    __shared__ int64_t s_base[RB];
+    __shared__ int s_off[RB], s_nw[RB], s_lo[RB], s_hi[RB], s_reg[RB];
+
+    const int4 blk = R.fblocks[xcd_logical(blockIdx.x, gridDim.x)];
+    const int i1s = blk.x, i2 = blk.y, i3 = blk.z, nrows = blk.w;
+    const int t = threadIdx.x;
+    const int n1 = R.nfun[0], n2 = R.nfun[1], n3 = R.nfun[2];
+    {
+        const float* W1 = R.Wt32[0] + (int64_t)i1s * 2 * M * NWT;
+        for (int k = t; k < nrows * 2 * M * NWT; k += NT) s_w1[k] = W1[k];
+        const float* W2 = R.Wt32[1] + (int64_t)i2 * 2 * M * NWT;
+        const float* W3 = R.Wt32[2] + (int64_t)i3 * 2 * M * NWT;
+        for (int k = t; k < 2 * M * NWT; k += NT) {
+            s_w2[k] = W2[k];
+            s_w3[k] = W3[k];
+        }
+    }
+    const int qbase = R.xs[0][i1s];
+    if (t < nrows) {
+        const int i1 = i1s + t;
+        const int ra = R.lex2act[((int64_t)i1 * n2 + i2) * n3 + i3];
+        s_base[t] = R.row_ptr[ra];
+        s_off[t] = R.xs[0][i1] - qbase;
+        s_nw[t] = R.nwin[0][i1];
+        s_lo[t] = i1 - P < 0 ? P - i1 : 0;
+        s_hi[t] = i1 + P > n1 - 1 ? n1 - 1 - i1 + P : 2 * P;
+        s_reg[t] = regular_window(i1, P, R.nel[0]);
+    }
+    const int i1e = i1s + nrows - 1;
+    const int nq1 = R.xs[0][i1e] + R.nwin[0][i1e] - qbase;
+    const int xs2 = R.xs[1][i2], nw2 = R.nwin[1][i2];
+    const int xs3 = R.xs[2][i3], nw3 = R.nwin[2][i3];
+    const bool reg2 = regular_window(i2, P, R.nel[1]);
+    const bool reg3 = regular_window(i3, P, R.nel[2]);
+    const int nx2 = R.nx[1], nx3 = R.nx[2];
+    __syncthreads();
+
+    // ---- stage 1: items (q1, q2).  Layouts in s_buf, plane by plane: stage-1 sums
+    // [q1][v][q2][j3] (2 NWB M values per plane), slab [q1][v][j2 j3] (2 MM per plane) ----
+    constexpr int P1S = 2 * NWB * M, PSL = 2 * MM;
+    for (int it = t; it < nq1 * nw2; it += NT) {
+        const int q1 = it / nw2, q2 = it - q1 * nw2;
+        const float* kr = kappa + ((int64_t)(qbase + q1) * nx2 + xs2 + q2) * nx3 + xs3;
+        float a0[M], a1[M];
+#pragma unroll
+        for (int j = 0; j < M; ++j) { a0[j] = 0.f; a1[j] = 0.f; }
+        if (reg3) {
+            float kv[NR];
+#pragma unroll
+            for (int q = 0; q < NR; ++q) kv[q] = kr[q];
+#pragma unroll
+            for (int q = 0; q < NR; ++q)
+#pragma unroll
+                for (int j = q / 2; j <= q / 2 + P; ++j) {
+                    a0[j] += s_w3[j * NWT + q] * kv[q];
+                    if (STIFF) a1[j] += s_w3[(M + j) * NWT + q] * kv[q];
+                }
+        } else {
+#pragma unroll 1
+            for (int q = 0; q < nw3; ++q) {
+                const float kv = kr[q];
+#pragma unroll
+                for (int j = 0; j < M; ++j) {
+                    a0[j] += s_w3[j * NWT + q] * kv;
+                    if (STIFF) a1[j] += s_w3[(M + j) * NWT + q] * kv;
+                }
+            }
+        }
+        float* o0 = s_buf + q1 * P1S + q2 * M;
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            o0[j] = a0[j];
+            if (STIFF) o0[NWB * M + j] = a1[j];
+        }
+    }
+    __syncthreads();
+
+    // ---- stage 2: items (q1, j3), in rounds of NT items ordered by q1.  A round keeps its
+    // results in registers until all its threads have read their stage-1 sums, then writes
+    // them over the slab planes of its q1; slab plane q1 ends below stage-1 plane q1 + 1
+    // (2 MM < 2 NWB M), so a round never overwrites sums that a later round reads ----
+    static_assert(PSL < P1S && (NT / M) * (P1S - PSL) >= PSL,
+                  "a round's slab planes end below the stage-1 planes of later rounds");
+    for (int base = 0; base < nq1 * M; base += NT) {
+        const int it = base + t;
+        const int q1 = it / M, j3 = it - q1 * M;
+        float r0[M], rs[M];
+#pragma unroll
+        for (int j = 0; j < M; ++j) { r0[j] = 0.f; rs[j] = 0.f; }
+        const bool on = it < nq1 * M;
+        if (on) {
+            const float* t0 = s_buf + q1 * P1S + j3;
+            const float* t1 = t0 + NWB * M;
+            if (reg2) {
+#pragma unroll
+                for (int q = 0; q < NR; ++q) {
+                    const float x0 = t0[q * M];
+                    const float x1 = STIFF ? t1[q * M] : 0.f;
+#pragma unroll
+                    for (int j = q / 2; j <= q / 2 + P; ++j) {
+                        const float w0 = s_w2[j * NWT + q];
+                        r0[j] += w0 * x0;
+                        if (STIFF) rs[j] += s_w2[(M + j) * NWT + q] * x0 + w0 * x1;
+                    }
+                }
+            } else {
+#pragma unroll 1
+                for (int q = 0; q < nw2; ++q) {
+                    const float x0 = t0[q * M];
+                    const float x1 = STIFF ? t1[q * M] : 0.f;
+#pragma unroll
+                    for (int j = 0; j < M; ++j) {
+                        const float w0 = s_w2[j * NWT + q];
+                        r0[j] += w0 * x0;
+                        if (STIFF) rs[j] += s_w2[(M + j) * NWT + q] * x0 + w0 * x1;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        if (on) {
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                s_buf[q1 * PSL + j * M + j3] = r0[j];
+                if (STIFF) s_buf[q1 * PSL + MM + j * M + j3] = rs[j];
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- stage 3: items (row, column) ----
+    const int lo2 = i2 - P < 0 ? P - i2 : 0, hi2 = i2 + P > n2 - 1 ? n2 - 1 - i2 + P : 2 * P;
+    const int lo3 = i3 - P < 0 ? P - i3 : 0, hi3 = i3 + P > n3 - 1 ? n3 - 1 - i3 + P : 2 * P;
+    const int m2 = hi2 - lo2 + 1, m3 = hi3 - lo3 + 1;
+    for (int it = t; it < nrows * MM; it += NT) {
+        const int r = it / MM, c = it - r * MM;
+        const int jj2 = c / M, jj3 = c - jj2 * M;
+        const bool live = jj2 >= lo2 && jj2 <= hi2 && jj3 >= lo3 && jj3 <= hi3;
+        const int lo1 = s_lo[r], hi1 = s_hi[r];
+        const int64_t ob = s_base[r] + (int64_t)(jj2 - lo2) * m3 + (jj3 - lo3);
+        const int step = m2 * m3;
+        const float* w10 = s_w1 + r * 2 * M * NWT;
+        const float* w11 = w10 + M * NWT;
+        const float* x0 = s_buf + s_off[r] * PSL + c;
+        const float* xs = x0 + MM;
+        if (s_reg[r]) {
+            float t0[NR], ts[NR];
+#pragma unroll
+            for (int q = 0; q < NR; ++q) {
+                t0[q] = x0[q * PSL];
+                ts[q] = STIFF ? xs[q * PSL] : 0.f;
+            }
+#pragma unroll
+            for (int jj1 = 0; jj1 < M; ++jj1) {
+                const int qa = 2 * (jj1 - P > 0 ? jj1 - P : 0);
+                const int qb = 2 * ((jj1 < P ? jj1 : P) + 1);
+                float am = 0.f, ak = 0.f;
+#pragma unroll
+                for (int q = 0; q < NR; ++q) {
+                    if (q >= qa && q < qb) {
+                        const float a = w10[jj1 * NWT + q];
+                        if (MASS) am += a * t0[q];
+                        if (STIFF) ak += w11[jj1 * NWT + q] * t0[q] + a * ts[q];
+                    }
+                }
+                if (live) {
+                    const int64_t o = ob + (int64_t)jj1 * step;
+                    if (MASS) vm[o] = am;
+                    if (STIFF) vk[o] = ak;
+                }
+            }
+        } else {
+            const int nw1 = s_nw[r];
+            float am[M], ak[M];
+#pragma unroll
+            for (int jj1 = 0; jj1 < M; ++jj1) { am[jj1] = 0.f; ak[jj1] = 0.f; }
+#pragma unroll 1
+            for (int q = 0; q < nw1; ++q) {
+                const float v0 = x0[q * PSL];
+                const float vs = STIFF ? xs[q * PSL] : 0.f;
+#pragma unroll
+                for (int jj1 = 0; jj1 < M; ++jj1) {
+                    const float a = w10[jj1 * NWT + q];
+                    if (MASS) am[jj1] += a * v0;
+                    if (STIFF) ak[jj1] += w11[jj1 * NWT + q] * v0 + a * vs;
+                }
+            }
+#pragma unroll
+            for (int jj1 = 0; jj1 < M; ++jj1) {
+                if (live && jj1 >= lo1 && jj1 <= hi1) {
+                    const int64_t o = ob + (int64_t)(jj1 - lo1) * step;
+                    if (MASS) vm[o] = am[jj1];
+                    if (STIFF) vk[o] = ak[jj1];
+                }
+            }
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------------------
 // cut rows (general kernel): contraction order A (split direction first), B, C
 // ----------------------------------------------------------------------------------------
 template <typename T, int P, int WHICH>
@@ -366,17 +604,39 @@ struct CutCfg {
 };
 
 // Cut rows without a DWQ box: one wave per row writes zeros over the row (their values come
-// from cut_assemble alone).
+// from cut_assemble alone), 16-byte stores over the aligned middle of the row.
 template <typename T, int WHICH>
 __global__ void __launch_bounds__(256)
 k_rows_zero(DevRules R, T* __restrict__ vm, T* __restrict__ vk) {
     const int64_t cr = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (cr >= R.n_cut || R.split[cr].x >= 0) return;
+    const int lane = threadIdx.x & 63;
     const int ra = R.cut_rows[cr];
     const int64_t rb = R.row_ptr[ra], re = R.row_ptr[ra + 1];
-    for (int64_t k = rb + (threadIdx.x & 63); k < re; k += 64) {
-        if (WHICH & 1) vm[k] = 0;
-        if (WHICH & 2) vk[k] = 0;
+    constexpr int V = 16 / sizeof(T);           // values per 16-byte store
+    if (((uintptr_t)vm | (uintptr_t)vk) % 16 != 0) {   // arrays not 16-byte aligned: plain stores
+        for (int64_t k = rb + lane; k < re; k += 64) {
+            if (WHICH & 1) vm[k] = 0;
+            if (WHICH & 2) vk[k] = 0;
+        }
+        return;
+    }
+    // head up to the first 16-byte boundary, then whole vectors, then the tail
+    int64_t a = (rb + V - 1) / V * V;
+    if (a > re) a = re;
+    const int64_t b = a + (re - a) / V * V;
+    if (rb + lane < a) {
+        if (WHICH & 1) vm[rb + lane] = 0;
+        if (WHICH & 2) vk[rb + lane] = 0;
+    }
+    if (b + lane < re) {
+        if (WHICH & 1) vm[b + lane] = 0;
+        if (WHICH & 2) vk[b + lane] = 0;
+    }
+    const int4 z = make_int4(0, 0, 0, 0);
+    for (int64_t k = a / V + lane; k < b / V; k += 64) {
+        if (WHICH & 1) reinterpret_cast<int4*>(vm)[k] = z;
+        if (WHICH & 2) reinterpret_cast<int4*>(vk)[k] = z;
     }
 }
 
@@ -531,11 +791,274 @@ k_rows_cut(DevRules R, const T* __restrict__ kappa, T* __restrict__ vm, T* __res
 }
 
 // ----------------------------------------------------------------------------------------
+// cut rows with a DWQ box, p <= 4: the whole box at once
+// ----------------------------------------------------------------------------------------
+// One workgroup per box row.  The row's points are the one-sided DWQ rule's points in the
+// split direction A and the standard windows in B and C (directions ascending).  kappa of
+// every point of the box is gathered into LDS first (one batch of independent loads; the
+// slot of a point follows from per-direction tables: a grid point when its A point is a WQ
+// point, else the Gauss block of its element), then three contractions:
+//   A: T1_v[qC][qB][jA] = sum_qA W_A^v[jA][qA] kappa[qC][qB][qA];
+//   B: T2_00[qC][jB jA] = sum_qB W_B^00 T1_00, T2_s = sum_qB W_B^11 T1_00 + W_B^00 T1_11;
+//   C: M[jC jB jA] = sum_qC W_C^00 T2_00, K = sum_qC W_C^11 T2_00 + W_C^00 T2_s,
+// each thread holding one output index j of the contracted direction and a few values of
+// the others, so a weight read from LDS serves several products.  Values go to the row
+// through its position map.  Needs windows of at most 3p+1 points (p+2 elements per direction).
+template <typename T, int P>
+struct BoxCfg {
+    static constexpr int M = 2 * P + 1, MM = M * M, NT = 256;
+    static constexpr int NDQ = P * (P + 1), NWT = 4 * P, NWB = 3 * P + 1;
+    static constexpr int KS = NDQ + 1;                      // odd stride of a kappa row
+    static constexpr int NK = NWB * NWB * KS;                // kappa of the box [qC qB][qA]
+    static constexpr int NT2 = 2 * NWB * MM;                 // stage-B sums (reuse the kappa space)
+    static constexpr int NKB = NK > NT2 ? NK : NT2;
+    static constexpr int NT1 = 2 * NWB * NWB * M;            // stage-A sums [v][qC qB][jA]
+    static constexpr int NG = (NDQ * NWB * NWB + NT - 1) / NT;   // kappa gathers per thread
+    static constexpr int GA = 4, GB = 4, GC = 3;             // outputs per thread and weight read
+};
+
+template <typename T, int P, int WHICH>
+__global__ void __launch_bounds__(256)
+k_rows_box(DevRules R, const T* __restrict__ kappa, T* __restrict__ vm, T* __restrict__ vk) {
+    using C = BoxCfg<T, P>;
+    constexpr int M = C::M, MM = C::MM, NT = C::NT, NDQ = C::NDQ, NWT = C::NWT, NWB = C::NWB, KS = C::KS;
+    constexpr int P1 = P + 1, P13 = P1 * P1 * P1;
+    constexpr bool MASS = (WHICH & 1) != 0, STIFF = (WHICH & 2) != 0;
+    __shared__ T s_kb[C::NKB];                   // kappa, then the stage-B sums
+    __shared__ T s_t1[C::NT1];
+    __shared__ T s_wa[2 * M * NDQ], s_wb[2 * M * NWT], s_wc[2 * M * NWT];
+    __shared__ int s_g[3][NDQ], s_e[3][NDQ], s_l[3][NDQ];   // per direction slot: grid part, element part, point part
+    __shared__ int s_n[3];
+
+    const int64_t cr = R.box_rows[blockIdx.x];
+    const int ra = R.cut_rows[cr];
+    const int4 sp = R.split[cr];
+    const int64_t rb = R.row_ptr[ra];
+    const int t = threadIdx.x;
+    const int lex = R.act2lex[ra];
+    int I[3];
+    I[2] = lex % R.nfun[2]; I[1] = (lex / R.nfun[2]) % R.nfun[1]; I[0] = lex / (R.nfun[1] * R.nfun[2]);
+    const int dA = sp.x, dB = dA == 0 ? 1 : 0, dC = dA == 2 ? 1 : 2;
+    // strides of the grid and of the element / point indices of a Gauss block along
+    // direction d (selects, not indexed arrays, so nothing goes to scratch)
+    auto gstr = [&](int d) { return d == 0 ? R.nx[1] * R.nx[2] : (d == 1 ? R.nx[2] : 1); };
+    auto estr = [&](int d) { return d == 0 ? R.nel[1] * R.nel[2] : (d == 1 ? R.nel[2] : 1); };
+    auto lstr = [&](int d) { return d == 0 ? P1 * P1 : (d == 1 ? P1 : 1); };
+    // rules and per-point slot parts
+    {
+        const int r = sp.w;
+        const int np = R.dwq_np[r];
+        const T* W = dwq_table<T>(R) + (int64_t)r * 2 * M * NDQ;
+        for (int k = t; k < 2 * M * NDQ; k += NT) s_wa[k] = W[k];
+        const int IB = dB == 0 ? I[0] : I[1], IC = dC == 1 ? I[1] : I[2];
+        const T* WB = wt_table<T>(R, dB) + (int64_t)IB * 2 * M * NWT;
+        const T* WC = wt_table<T>(R, dC) + (int64_t)IC * 2 * M * NWT;
+        for (int k = t; k < 2 * M * NWT; k += NT) {
+            s_wb[k] = WB[k];
+            s_wc[k] = WC[k];
+        }
+        if (t < NDQ) {
+            if (t < np) {
+                const int y = R.dwq_y[(int64_t)r * NDQ + t];
+                const int x = R.y2x[dA][y];
+                s_g[0][t] = x >= 0 ? x * gstr(dA) : -1;
+                s_e[0][t] = (y / P1) * estr(dA);
+                s_l[0][t] = (y % P1) * lstr(dA);
+            }
+        }
+#pragma unroll
+        for (int s = 1; s < 3; ++s) {
+            const int d = s == 1 ? dB : dC;
+            const int Id = d == 0 ? I[0] : (d == 1 ? I[1] : I[2]);
+            const int xs = R.xs[d][Id], nw = R.nwin[d][Id];
+            if (t < nw) {
+                const int x = xs + t;
+                const int y = R.x2y[d][x];
+                s_g[s][t] = x * gstr(d);
+                s_e[s][t] = (y / P1) * estr(d);
+                s_l[s][t] = (y % P1) * lstr(d);
+            }
+            if (t == 0) s_n[s] = nw;
+        }
+        if (t == 0) s_n[0] = np;
+    }
+    // position map entries of this thread's outputs in stage C
+    const int32_t* pos = R.pos_map + cr * (int64_t)M * MM;
+    __syncthreads();
+    const int nA = s_n[0], nB = s_n[1], nC = s_n[2];
+    const int npts = nA * nB * nC;
+    // ---- kappa of the box: [qC qB][qA] ----
+    {
+        T kv[C::NG];
+#pragma unroll
+        for (int i = 0; i < C::NG; ++i) {
+            const int k = t + i * NT;
+            kv[i] = (T)0;
+            if (k < npts) {
+                const int qA = k % nA, pr = k / nA, qB = pr % nB, qC = pr / nB;
+                const int ga = s_g[0][qA];
+                int64_t slot;
+                if (ga >= 0) {
+                    slot = (int64_t)ga + s_g[1][qB] + s_g[2][qC];
+                } else {
+                    const int b = R.elem_block[s_e[0][qA] + s_e[1][qB] + s_e[2][qC]];
+                    slot = R.n_grid + (int64_t)b * P13 + s_l[0][qA] + s_l[1][qB] + s_l[2][qC];
+                }
+                kv[i] = kappa[slot];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < C::NG; ++i) {
+            const int k = t + i * NT;
+            if (k < npts) {
+                const int qA = k % nA, pr = k / nA;
+                s_kb[pr * KS + qA] = kv[i];
+            }
+        }
+    }
+    __syncthreads();
+    // ---- stage A: thread (jA, group), pairs pr = group + k * ngroups ----
+    {
+        constexpr int G = C::GA;
+        const int npair = nB * nC, ngrp = (npair + G - 1) / G;
+        for (int it = t; it < M * ngrp; it += NT) {
+            const int jA = it / ngrp, grp = it - jA * ngrp;
+            T a0[G], a1[G];
+            int prk[G];
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+                a0[k] = 0; a1[k] = 0;
+                const int pr = grp + k * ngrp;
+                prk[k] = pr < npair ? pr : npair - 1;
+            }
+            const T* w0p = s_wa + jA * NDQ;
+            const T* w1p = s_wa + (M + jA) * NDQ;
+#pragma unroll 2
+            for (int qA = 0; qA < nA; ++qA) {
+                const T w0 = w0p[qA];
+                const T w1 = STIFF ? w1p[qA] : (T)0;
+#pragma unroll
+                for (int k = 0; k < G; ++k) {
+                    const T kk = s_kb[prk[k] * KS + qA];
+                    a0[k] += w0 * kk;
+                    if (STIFF) a1[k] += w1 * kk;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+                const int pr = grp + k * ngrp;
+                if (pr < npair) {
+                    s_t1[pr * M + jA] = a0[k];
+                    if (STIFF) s_t1[NWB * NWB * M + pr * M + jA] = a1[k];
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // ---- stage B: thread (jB, group), pairs (qC, jA) ----
+    {
+        constexpr int G = C::GB;
+        const int npair = nC * M, ngrp = (npair + G - 1) / G;
+        for (int it = t; it < M * ngrp; it += NT) {
+            const int jB = it / ngrp, grp = it - jB * ngrp;
+            T m0[G], ms[G];
+            int base[G];
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+                m0[k] = 0; ms[k] = 0;
+                int pr = grp + k * ngrp;
+                pr = pr < npair ? pr : npair - 1;
+                const int qC = pr / M, jA = pr - qC * M;
+                base[k] = qC * nB * M + jA;
+            }
+            const T* w0p = s_wb + jB * NWT;
+            const T* w1p = s_wb + (M + jB) * NWT;
+#pragma unroll 2
+            for (int qB = 0; qB < nB; ++qB) {
+                const T w0 = w0p[qB];
+                const T w1 = STIFF ? w1p[qB] : (T)0;
+#pragma unroll
+                for (int k = 0; k < G; ++k) {
+                    const T t0 = s_t1[base[k] + qB * M];
+                    m0[k] += w0 * t0;
+                    if (STIFF) ms[k] += w1 * t0 + w0 * s_t1[NWB * NWB * M + base[k] + qB * M];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+                const int pr = grp + k * ngrp;
+                if (pr < npair) {
+                    const int qC = pr / M, jA = pr - qC * M;
+                    s_kb[qC * MM + jB * M + jA] = m0[k];
+                    if (STIFF) s_kb[NWB * MM + qC * MM + jB * M + jA] = ms[k];
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // ---- stage C: thread (jC, group), pairs c = (jB, jA); stores through the position map ----
+    {
+        constexpr int G = C::GC;
+        constexpr int ngrp = (MM + G - 1) / G;
+        for (int it = t; it < M * ngrp; it += NT) {
+            const int jC = it / ngrp, grp = it - jC * ngrp;
+            T am[G], ak[G];
+            int ck[G];
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+                am[k] = 0; ak[k] = 0;
+                const int c = grp + k * ngrp;
+                ck[k] = c < MM ? c : MM - 1;
+            }
+            const T* w0p = s_wc + jC * NWT;
+            const T* w1p = s_wc + (M + jC) * NWT;
+#pragma unroll 2
+            for (int qC = 0; qC < nC; ++qC) {
+                const T w0 = w0p[qC];
+                const T w1 = STIFF ? w1p[qC] : (T)0;
+#pragma unroll
+                for (int k = 0; k < G; ++k) {
+                    const T t0 = s_kb[qC * MM + ck[k]];
+                    if (MASS) am[k] += w0 * t0;
+                    if (STIFF) ak[k] += w1 * t0 + w0 * s_kb[NWB * MM + qC * MM + ck[k]];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+                const int c = grp + k * ngrp;
+                if (c < MM) {
+                    const int jB = c / M, jA = c - jB * M;
+                    const int o = pos[(pick3(0, dA, dB, jA, jB, jC) * M + pick3(1, dA, dB, jA, jB, jC)) * M +
+                                      pick3(2, dA, dB, jA, jB, jC)];
+                    if (o >= 0) {
+                        if (MASS) vm[rb + o] = am[k];
+                        if (STIFF) vk[rb + o] = ak[k];
+                    }
+                }
+            }
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------------------
 // host launchers
 // ----------------------------------------------------------------------------------------
+// windows of at most 3p+1 points: p + 2 elements in every direction
+static bool windows_fit(const DevRules& R) {
+    return R.nel[0] >= R.p + 2 && R.nel[1] >= R.p + 2 && R.nel[2] >= R.p + 2;
+}
+static bool block_kernel_fits(const DevRules& R) { return R.p <= 4 && R.n_fblocks > 0 && windows_fit(R); }
+
 template <typename T, int P, int WHICH>
 static void launch_rows_p(const wq_rules* H, const T* kappa, T* vm, T* vk, hipStream_t s) {
     const DevRules& R = H->R;
+    if constexpr (sizeof(T) == 4 && P <= 4) {
+        if (block_kernel_fits(R)) {
+            hipLaunchKernelGGL((k_rows_block<P, WHICH, 8>), dim3((unsigned)R.n_fblocks), dim3(256), 0, s, R,
+                               (const float*)kappa, (float*)vm, (float*)vk);
+            goto cut_rows;
+        }
+    }
     if (R.n_lblocks > 0) {
         // line blocks hold up to 16 rows for p <= 4 and 8 above; FP64 at p <= 4 takes half a
         // block per workgroup to bound its LDS slab
@@ -553,8 +1076,18 @@ static void launch_rows_p(const wq_rules* H, const T* kappa, T* vm, T* vk, hipSt
                                vm, vk);
         }
     }
-    if (R.n_box > 0)
-        hipLaunchKernelGGL((k_rows_cut<T, P, WHICH>), dim3((unsigned)R.n_box), dim3(256), 0, s, R, kappa, vm, vk);
+cut_rows:
+    if (R.n_box > 0) {
+        bool done = false;
+        if constexpr (P <= 4) {
+            if (windows_fit(R)) {
+                hipLaunchKernelGGL((k_rows_box<T, P, WHICH>), dim3((unsigned)R.n_box), dim3(256), 0, s, R, kappa, vm, vk);
+                done = true;
+            }
+        }
+        if (!done)
+            hipLaunchKernelGGL((k_rows_cut<T, P, WHICH>), dim3((unsigned)R.n_box), dim3(256), 0, s, R, kappa, vm, vk);
+    }
     if (R.n_cut > R.n_box)
         hipLaunchKernelGGL((k_rows_zero<T, WHICH>), dim3((unsigned)((R.n_cut + 3) / 4)), dim3(256), 0, s, R, vm, vk);
 }
@@ -575,8 +1108,19 @@ static void launch_rows_bf3_p(const wq_rules* H, const float* kappa, float* vm, 
                                s, R, kappa, vm, vk);
         }
     }
-    if (R.n_box > 0)
-        hipLaunchKernelGGL((k_rows_cut<float, P, WHICH>), dim3((unsigned)R.n_box), dim3(256), 0, s, R, kappa, vm, vk);
+    if (R.n_box > 0) {
+        bool done = false;
+        if constexpr (P <= 4) {
+            if (windows_fit(R)) {
+                hipLaunchKernelGGL((k_rows_box<float, P, WHICH>), dim3((unsigned)R.n_box), dim3(256), 0, s, R, kappa, vm,
+                                   vk);
+                done = true;
+            }
+        }
+        if (!done)
+            hipLaunchKernelGGL((k_rows_cut<float, P, WHICH>), dim3((unsigned)R.n_box), dim3(256), 0, s, R, kappa, vm,
+                               vk);
+    }
     if (R.n_cut > R.n_box)
         hipLaunchKernelGGL((k_rows_zero<float, WHICH>), dim3((unsigned)((R.n_cut + 3) / 4)), dim3(256), 0, s, R, vm, vk);
 }

@@ -178,9 +178,12 @@ __global__ void k_dir_tables(DevRules R, int d, const double* gxi, double* ycoor
 // shortcut: use w_q = gq * B_l^(a)(x_q) (every element of the support keeps all its Gauss
 // points).  Otherwise the minimum-norm solution of the exactness conditions
 //   sum_q w_q B_j^(a)(x_q) = int B_l^(a) B_j^(a),  j overlapping l,
-// by Householder QR of the transposed system; for a = 1 the last condition is implied by
-// the others (sum_j B_j' = 0 on the support) and is dropped, which leaves the solution
-// set unchanged.  Returns 0, or WQ_ESINGULAR when a pivot vanishes.
+// by Householder QR of the transposed system with every condition scaled to unit norm
+// (the solution does not depend on that scaling).  For a = 1 the conditions are posed on
+// the degree p-1 B-splines N_k over the same knots that are nonzero on supp B_l: the B_j'
+// are combinations of them and span the same space there (less one dimension, since they
+// sum to zero), so sum_q w_q N_k(x_q) = int B_l' N_k fixes the same weights without a
+// redundant condition.  Returns 0, or WQ_ESINGULAR when a pivot vanishes.
 __device__ int wq_local_rule(const double* T, int nT, int p, int l, int a, const double* xq, const double* gq,
                              int nq, bool shortcut, const double* gxi, const double* gw, double* w) {
     double N[WQ_PMAX + 1], dN[WQ_PMAX + 1];
@@ -194,24 +197,28 @@ __device__ int wq_local_rule(const double* T, int nT, int p, int l, int a, const
         }
         return 0;
     }
-    int nf = nT - p - 1;
+    // condition functions: degree pc = p - a over T, indices clo..chi (nonzero and
+    // overlapping supp B_l)
+    const int pc = p - a;
+    const int nfc = nT - pc - 1;
     double tl = T[l], tr = T[l + p + 1];
-    int jlo = -1, jhi = -1;
-    for (int j = 0; j < nf; ++j) {
-        if (T[j] == T[j + p + 1]) continue;
-        double a0 = fmax(tl, T[j]), b0 = fmin(tr, T[j + p + 1]);
-        if (a0 < b0) { if (jlo < 0) jlo = j; jhi = j; }
+    int clo = -1, chi = -1;
+    for (int j = 0; j < nfc; ++j) {
+        if (T[j] == T[j + pc + 1]) continue;
+        double a0 = fmax(tl, T[j]), b0 = fmin(tr, T[j + pc + 1]);
+        if (a0 < b0) { if (clo < 0) clo = j; chi = j; }
     }
-    int mc = jhi - jlo + 1 - (a == 1 ? 1 : 0);
-    if (mc <= 0 || mc > WQ_MMAX || nq < mc) return WQ_ESINGULAR;
+    int mc = chi - clo + 1;
+    if (clo < 0 || mc > WQ_MMAX || nq < mc) return WQ_ESINGULAR;
     double At[WQ_NQREF][WQ_MMAX];
     double b[WQ_MMAX], beta[WQ_MMAX], diag[WQ_MMAX];
+    double Nc[WQ_PMAX + 1], dNc[WQ_PMAX + 1];
     for (int q = 0; q < nq; ++q) {
         int s = find_span(T, nT, p, xq[q]);
-        basis_funs(T, p, s, xq[q], N, dN);
+        basis_funs(T, pc, s, xq[q], Nc, dNc);     // Nc[r] = N_{s-pc+r}
         for (int c = 0; c < mc; ++c) {
-            int r = jlo + c - (s - p);
-            At[q][c] = (r >= 0 && r <= p) ? (a ? dN[r] : N[r]) : 0.0;
+            int r = clo + c - (s - pc);
+            At[q][c] = (r >= 0 && r <= pc) ? Nc[r] : 0.0;
         }
     }
     for (int c = 0; c < mc; ++c) b[c] = 0.0;
@@ -223,11 +230,21 @@ __device__ int wq_local_rule(const double* T, int nT, int p, int l, int a, const
             double wg = gw[g] * (t1 - t0) / 2.0;
             basis_funs(T, p, k, x, N, dN);
             double bl = a ? dN[l - (k - p)] : N[l - (k - p)];
+            basis_funs(T, pc, k, x, Nc, dNc);
             for (int c = 0; c < mc; ++c) {
-                int r = jlo + c - (k - p);
-                if (r >= 0 && r <= p) b[c] += wg * bl * (a ? dN[r] : N[r]);
+                int r = clo + c - (k - pc);
+                if (r >= 0 && r <= pc) b[c] += wg * bl * Nc[r];
             }
         }
+    }
+    // unit-norm conditions
+    for (int c = 0; c < mc; ++c) {
+        double nrm = 0.0;
+        for (int q = 0; q < nq; ++q) nrm += At[q][c] * At[q][c];
+        if (!(nrm > 0.0)) return WQ_ESINGULAR;
+        const double sc = 1.0 / sqrt(nrm);
+        for (int q = 0; q < nq; ++q) At[q][c] *= sc;
+        b[c] *= sc;
     }
     // Householder QR of At (nq x mc)
     double dmax = 0.0;
@@ -1231,6 +1248,17 @@ int build_rules(const wq_mesh* mesh, const wq_levelset* ls, const wq_options* op
         if (!blocks) return B.fail();
         R.lblocks = blocks; R.n_lblocks = nb;
         hipLaunchKernelGGL(k_line_fill, grid_for(nl), dim3(256), 0, stream, R, fcls, rb, loff, blocks);
+        // blocks of at most 8 rows for the FP32 row kernel (p <= 4)
+        R.fblocks = nullptr; R.n_fblocks = 0;
+        if (p <= 4) {
+            hipLaunchKernelGGL(k_line_count, grid_for(nl), dim3(256), 0, stream, R, fcls, 8, lc);
+            int64_t nf = 0;
+            if (scan_exclusive(B, lc, loff, nl, &nf)) return B.fail();
+            int4* fb = B.keep<int4>(nf > 0 ? nf : 1);
+            if (!fb) return B.fail();
+            R.fblocks = fb; R.n_fblocks = nf;
+            hipLaunchKernelGGL(k_line_fill, grid_for(nl), dim3(256), 0, stream, R, fcls, 8, loff, fb);
+        }
     }
 
     // element Gauss blocks
