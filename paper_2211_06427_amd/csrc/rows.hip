@@ -808,6 +808,7 @@ template <typename T, int P>
 struct BoxCfg {
     static constexpr int M = 2 * P + 1, MM = M * M, NT = 256;
     static constexpr int NDQ = P * (P + 1), NWT = 4 * P, NWB = 3 * P + 1;
+    static constexpr int NQM = NDQ > NWB ? NDQ : NWB;       // points of the longest of the three rules
     static constexpr int KS = NDQ + 1;                      // odd stride of a kappa row
     static constexpr int NK = NWB * NWB * KS;                // kappa of the box [qC qB][qA]
     static constexpr int NT2 = 2 * NWB * MM;                 // stage-B sums (reuse the kappa space)
@@ -827,7 +828,7 @@ k_rows_box(DevRules R, const T* __restrict__ kappa, T* __restrict__ vm, T* __res
     __shared__ T s_kb[C::NKB];                   // kappa, then the stage-B sums
     __shared__ T s_t1[C::NT1];
     __shared__ T s_wa[2 * M * NDQ], s_wb[2 * M * NWT], s_wc[2 * M * NWT];
-    __shared__ int s_g[3][NDQ], s_e[3][NDQ], s_l[3][NDQ];   // per direction slot: grid part, element part, point part
+    __shared__ int s_g[3][C::NQM], s_e[3][C::NQM], s_l[3][C::NQM];   // per direction and point: slot parts
     __shared__ int s_n[3];
 
     const int64_t cr = R.box_rows[blockIdx.x];
