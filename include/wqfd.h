@@ -151,6 +151,19 @@ int wq_assemble_rows(const wq_rules* rules, int dtype, uint32_t which, const voi
 int cut_assemble(const wq_rules* rules, int dtype, uint32_t which, const void* kappa,
                  void* vals_mass, void* vals_stiff, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): cut_assemble with the same arguments,
+ * results and error behaviour, whose scratch (the moments and local rows of the cut
+ * elements) lives in a fixed 64 MiB device array inside the library instead of a
+ * stream-ordered pool.  The cut elements are processed in batches that fit the array; a
+ * case where one cut element alone needs more returns WQ_EINVAL.  No hipMalloc, hipFree or
+ * allocating library routine is called.  Every call on one device shares that device's
+ * array: calls that overlap in time on one device (different streams or host threads)
+ * race and give wrong results; calls ordered on one stream are safe.  The array is held
+ * on every device the library runs on until the process ends. */
+int cut_assemble_noalloc(const wq_rules* rules, int dtype, uint32_t which, const void* kappa,
+                         void* vals_mass, void* vals_stiff, void* stream);
+
 /* Adjoint of rows + cut parts: for L = sum_IJ (G_mass_IJ M_IJ + G_stiff_IJ K_IJ),
  * dkappa[slot] = dL/dkappa(slot), summed over every use of the slot.  dkappa (n_kappa) is
  * OVERWRITTEN.  G_mass / G_stiff: (nnz) cotangents on the pattern; each may be NULL iff

@@ -3,6 +3,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 
 #include "rows.h"
 
@@ -33,6 +34,37 @@ static int check_values(const wq_rules* r, int dtype, uint32_t which, const void
     if (!kappa) return wq_set_error(WQ_EINVAL, "%s: kappa is NULL", what);
     if ((which & WQ_MASS) && !a) return wq_set_error(WQ_EINVAL, "%s: mass output requested but pointer is NULL", what);
     if ((which & WQ_STIFF) && !b) return wq_set_error(WQ_EINVAL, "%s: stiffness output requested but pointer is NULL", what);
+    return WQ_OK;
+}
+
+// Device scratch of the allocation-free cut assembly: a fixed array, one copy on every device
+// the library runs on (held until the process ends).  Host code never uses the array's name
+// as an address: the device address comes from hipGetSymbolAddress, once per device, with
+// that device current.
+static constexpr size_t WQ_NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+static constexpr int WQ_MAX_DEVICES = 64;
+static __device__ __align__(256) unsigned char scratch[WQ_NOALLOC_SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[WQ_MAX_DEVICES] = {};
+
+static int scratch_address(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return wq_set_error(WQ_EHIP, "cut_assemble_noalloc: hipGetDevice failed: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= WQ_MAX_DEVICES)
+        return wq_set_error(WQ_EUNSUPPORTED, "cut_assemble_noalloc: device %d beyond the supported %d", dev,
+                            WQ_MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return wq_set_error(WQ_EHIP, "cut_assemble_noalloc: device address of the scratch array: %s",
+                                hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
     return WQ_OK;
 }
 
@@ -130,6 +162,26 @@ int cut_assemble(const wq_rules* r, int dtype, uint32_t which, const void* kappa
         st = launch_cut<float>(r, which & 3u, parts, (const float*)kappa, (float*)vm, (float*)vk, (hipStream_t)stream);
     if (st) return st;
     return check_launch("cut_assemble");
+}
+
+int cut_assemble_noalloc(const wq_rules* r, int dtype, uint32_t which, const void* kappa, void* vm, void* vk,
+                         void* stream) {
+    int st = check_values(r, dtype, which, kappa, vm, vk, "cut_assemble_noalloc", WQ_CUT_REMAINDER | WQ_CUT_OCTREE);
+    if (st) return st;
+    if (r->nnz == 0) return WQ_OK;
+    void* buf = nullptr;
+    st = scratch_address(&buf);
+    if (st) return st;
+    uint32_t parts = which & (WQ_CUT_REMAINDER | WQ_CUT_OCTREE);
+    if (parts == 0) parts = WQ_CUT_REMAINDER | WQ_CUT_OCTREE;
+    if (dtype == WQ_F64)
+        st = launch_cut<double>(r, which & 3u, parts, (const double*)kappa, (double*)vm, (double*)vk, (hipStream_t)stream,
+                                buf, WQ_NOALLOC_SCRATCH_BYTES);
+    else
+        st = launch_cut<float>(r, which & 3u, parts, (const float*)kappa, (float*)vm, (float*)vk, (hipStream_t)stream,
+                               buf, WQ_NOALLOC_SCRATCH_BYTES);
+    if (st) return st;
+    return check_launch("cut_assemble_noalloc");
 }
 
 int wq_assemble_adjoint(const wq_rules* r, int dtype, uint32_t which, const void* gm, const void* gk, void* dk,

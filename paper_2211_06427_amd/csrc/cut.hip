@@ -7,10 +7,15 @@
 //     Gauss grid and adds into a row accumulator in LDS, which is then added into the row
 //     (a row is owned by one workgroup, so no global atomics).
 // (ii) Cut elements: octree leaves with (p+1)^3 Gauss points each (weight 0 outside the
-//     domain at cut leaves).  One workgroup per (cut element, a2, group of a1), with (a1,
-//     a2, a3) the local index of the test function on the element; per leaf the local
-//     matrix is contracted direction 3, then 2, then 1 and accumulated in registers over
-//     all leaves; the local rows are added into the CSR values with atomics at the end.
+//     domain at cut leaves).  For octrees of depth <= 3 (the default) in moment form:
+//     k_cut_moments forms each cut element's Bernstein moments of w kappa over its leaves,
+//     k_cut_local (k_cut_local_a2 at p = 5, 6) contracts them with the Bernstein tables of
+//     the basis products into the element's local rows, and k_cut_gather adds every cut
+//     row's local rows in a fixed order (one workgroup per row, no atomics).  Deeper
+//     octrees take k_cut_octree: one workgroup per (cut element, a3, group of a1), the
+//     local matrix contracted leaf by leaf and added into the CSR values with atomics.
+#include <algorithm>
+
 #include "rows.h"
 #include "moments.h"
 
@@ -398,7 +403,7 @@ k_cut_octree(DevRules R, const int32_t* __restrict__ act2cut, const T* __restric
 // leaf, direction 2 per column, direction 1 per x-group) and writes it to a scratch buffer.
 template <typename T, int P>
 __global__ void __launch_bounds__(256)
-k_cut_moments(DevRules R, const T* __restrict__ kappa, T* __restrict__ mom) {
+k_cut_moments(DevRules R, const T* __restrict__ kappa, T* __restrict__ mom, int ce0) {
     using C = MomCfg<P>;
     constexpr int P1 = C::P1, P2 = C::P2, NP = C::NP, NK = C::NK, NK2 = C::NK2, NK3 = C::NK3, NT = C::NT;
     constexpr int NB = C::NB, KW = C::KW, MAXC = C::MAXC;
@@ -409,7 +414,7 @@ k_cut_moments(DevRules R, const T* __restrict__ kappa, T* __restrict__ mom) {
     __shared__ T s_mz[2 * NZ];                      // column sums, double buffered
     __shared__ T s_my[NY];                          // x-group sums
 
-    const int ce = blockIdx.x;
+    const int ce = ce0 + blockIdx.x;                // mom holds the elements from ce0 on
     const int t = threadIdx.x;
     const int ni = (2 << R.levels) - 1;
     for (int i = t; i < ni * NK * P1; i += NT) s_bi[i] = bern_i<T>(R)[i];
@@ -537,7 +542,7 @@ k_cut_moments(DevRules R, const T* __restrict__ kappa, T* __restrict__ mom) {
 #pragma unroll
     for (int r = 0; r < RX; ++r) {
         const int i = t + r * NT;
-        if (i < NK3) mom[(int64_t)ce * NK3 + i] = accX[r];
+        if (i < NK3) mom[(int64_t)blockIdx.x * NK3 + i] = accX[r];
     }
 }
 
@@ -551,7 +556,7 @@ k_cut_moments(DevRules R, const T* __restrict__ kappa, T* __restrict__ mom) {
 template <typename T, int P, int WHICH, bool SCATTER = false>
 __global__ void __launch_bounds__(256)
 k_cut_local(DevRules R, const int32_t* __restrict__ elems, const T* __restrict__ mom, T* __restrict__ loc,
-            const int32_t* __restrict__ act2cut, T* __restrict__ vm, T* __restrict__ vk) {
+            const int32_t* __restrict__ act2cut, T* __restrict__ vm, T* __restrict__ vk, int ce0) {
     using C = MomCfg<P>;
     using MF = MfmaOp<T>;
     using v4 = typename MF::v4;
@@ -570,8 +575,8 @@ k_cut_local(DevRules R, const int32_t* __restrict__ elems, const T* __restrict__
 
     __shared__ int64_t s_rb[SCATTER ? P2 : 1];
     __shared__ int32_t s_cr[SCATTER ? P2 : 1];
-    const int ce = blockIdx.x / P1, a3 = blockIdx.x % P1;
-    const int64_t eid = elems[ce];
+    const int ce = blockIdx.x / P1, a3 = blockIdx.x % P1;    // ce counts from element ce0 of elems
+    const int64_t eid = elems[ce0 + ce];
     int e[3];
     unlex3i(eid, R.nel, e);
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
@@ -720,7 +725,7 @@ k_cut_local(DevRules R, const int32_t* __restrict__ elems, const T* __restrict__
 // a2 only, direction 1 on matrix cores with rows (a1 b1) and columns (b2 b3).
 template <typename T, int P, int WHICH>
 __global__ void __launch_bounds__(256)
-k_cut_local_a2(DevRules R, const int32_t* __restrict__ elems, const T* __restrict__ mom, T* __restrict__ loc) {
+k_cut_local_a2(DevRules R, const int32_t* __restrict__ elems, const T* __restrict__ mom, T* __restrict__ loc, int ce0) {
     using C = MomCfg<P>;
     using MF = MfmaOp<T>;
     using v4 = typename MF::v4;
@@ -739,8 +744,8 @@ k_cut_local_a2(DevRules R, const int32_t* __restrict__ elems, const T* __restric
     T* s_s2 = s_u + 2 * NS1;                        // [2][NS2]
     T* s_blk = s_u;                                 // [a1][b] after the contractions
 
-    const int ce = blockIdx.x / P2, a3 = (blockIdx.x / P1) % P1, a2 = blockIdx.x % P1;
-    const int64_t eid = elems[ce];
+    const int ce = blockIdx.x / P2, a3 = (blockIdx.x / P1) % P1, a2 = blockIdx.x % P1;   // from element ce0
+    const int64_t eid = elems[ce0 + ce];
     int e[3];
     unlex3i(eid, R.nel, e);
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
@@ -862,25 +867,50 @@ k_cut_local_a2(DevRules R, const int32_t* __restrict__ elems, const T* __restric
 // k_cut_gather: one workgroup per cut row adds the local rows of its cut elements (a fixed
 // order, no atomics): NSLOT elements in flight, one lane per column b of the element,
 // per-slot LDS accumulators over the row's (2p+1)^3 window, then one pass over the row.
+// Only the cut elements ce0 <= ce < ce1 are added (loc holds their local rows from ce0 on);
+// the workgroups cover the cut rows from cr0 on.
 template <typename T, int P, int WHICH>
 __global__ void __launch_bounds__(RemCfg<P>::NT)
-k_cut_gather(DevRules R, const T* __restrict__ loc, T* __restrict__ vm, T* __restrict__ vk) {
+k_cut_gather(DevRules R, const T* __restrict__ loc, T* __restrict__ vm, T* __restrict__ vk, int ce0, int ce1,
+             int64_t cr0) {
     using C = RemCfg<P>;
     constexpr int P1 = C::P1, NP = C::NP, P2 = C::P2, M = 2 * P + 1, M3 = M * M * M, NT = C::NT, SLOT = C::SLOT;
     constexpr int NSLOT = C::NSLOT, NBLK = P2 * NP;
     constexpr bool MASS = (WHICH & 1) != 0, STIFF = (WHICH & 2) != 0;
     __shared__ T s_accm[NSLOT][MASS ? M3 : 1], s_acck[NSLOT][STIFF ? M3 : 1];
     __shared__ int2 s_list[NP];
-    const int64_t cr = blockIdx.x;
+    __shared__ int s_n;
+    const int64_t cr = cr0 + blockIdx.x;
     const int t = threadIdx.x;
-    const int l0 = R.rcut_ptr[cr], n = R.rcut_ptr[cr + 1] - l0;
-    if (n == 0) return;
+    const int l0 = R.rcut_ptr[cr], nall = R.rcut_ptr[cr + 1] - l0;
+    if (nall == 0) return;
+    // this row's cut elements inside [ce0, ce1), in list order (one wave compacts them)
+    if (t < 64) {
+        int base = 0;
+        for (int k0 = 0; k0 < nall; k0 += 64) {
+            const int k = k0 + t;
+            int2 en = make_int2(0, 0);
+            bool in = false;
+            if (k < nall) {
+                en = R.rcut_list[l0 + k];
+                in = en.x >= ce0 && en.x < ce1;
+            }
+            const uint64_t mask = __ballot(in);
+            if (in) {
+                en.x -= ce0;
+                s_list[base + __popcll(mask & ((1ull << t) - 1))] = en;
+            }
+            base += __popcll(mask);
+        }
+        if (t == 0) s_n = base;
+    }
     for (int k = t; k < NSLOT * M3; k += NT) {
         if (MASS) s_accm[k / M3][k % M3] = 0;
         if (STIFF) s_acck[k / M3][k % M3] = 0;
     }
-    for (int k = t; k < n; k += NT) s_list[k] = R.rcut_list[l0 + k];
     __syncthreads();
+    const int n = s_n;
+    if (n == 0) return;
     const int sl = t / SLOT, u = t % SLOT;
     const bool act_u = u < NP;
     const int b1 = u / P2, b2 = (u / P1) % P1, b3 = u % P1;
@@ -999,13 +1029,13 @@ static int launch_gauss_p(const wq_rules* H, const T* kg, const T* kappa, T* vm,
     if (ni > 0) {
         hipLaunchKernelGGL((k_gauss_moments<T, P>), dim3((unsigned)ni), dim3(256), 0, s, R, kg, (const double*)H->gw, mom);
         hipLaunchKernelGGL((k_cut_local<T, P, WHICH, true>), dim3((unsigned)(ni * (P + 1))), dim3(256), 0, s, R, H->int_elems,
-                           (const T*)mom, (T*)nullptr, H->act2cut, vm, vk);
+                           (const T*)mom, (T*)nullptr, H->act2cut, vm, vk, 0);
     }
     if (nc > 0) {
         T* mc = mom + (size_t)ni * C::NK3;
-        hipLaunchKernelGGL((k_cut_moments<T, P>), dim3((unsigned)nc), dim3(256), 0, s, R, kappa, mc);
+        hipLaunchKernelGGL((k_cut_moments<T, P>), dim3((unsigned)nc), dim3(256), 0, s, R, kappa, mc, 0);
         hipLaunchKernelGGL((k_cut_local<T, P, WHICH, true>), dim3((unsigned)(nc * (P + 1))), dim3(256), 0, s, R, R.cut_elems,
-                           (const T*)mc, (T*)nullptr, H->act2cut, vm, vk);
+                           (const T*)mc, (T*)nullptr, H->act2cut, vm, vk, 0);
     }
     err = hipFreeAsync(mom, s);
     if (err != hipSuccess) return wq_set_error(WQ_EHIP, "gauss_assemble: scratch release failed: %s", hipGetErrorString(err));
@@ -1060,40 +1090,75 @@ template int launch_gauss<float>(const wq_rules*, uint32_t, const float*, const 
 // ----------------------------------------------------------------------------------------
 // host launchers
 // ----------------------------------------------------------------------------------------
+// Cut elements in moment form, in batches of at most nb elements whose moments and local
+// rows fit in buf; the gather of a batch covers the cut rows whose support can reach it
+// (cut elements and cut rows are in lexicographic order, so a batch's first direction-1
+// element index bounds them).
 template <typename T, int P, int WHICH>
-static int launch_cut_p(const wq_rules* H, uint32_t parts, const T* kappa, T* vm, T* vk, hipStream_t s) {
+static void launch_moment_form(const wq_rules* H, const T* kappa, T* vm, T* vk, T* buf, int64_t nb, hipStream_t s) {
+    const DevRules& R = H->R;
+    using C = MomCfg<P>;
+    const int64_t nce = R.n_cut_elems;
+    for (int64_t c0 = 0; c0 < nce; c0 += nb) {
+        const int64_t c1 = c0 + nb < nce ? c0 + nb : nce, n = c1 - c0;
+        T* mom = buf;
+        T* loc = buf + n * C::NK3;
+        hipLaunchKernelGGL((k_cut_moments<T, P>), dim3((unsigned)n), dim3(256), 0, s, R, kappa, mom, (int)c0);
+        if constexpr (P <= 4)
+            hipLaunchKernelGGL((k_cut_local<T, P, WHICH>), dim3((unsigned)(n * (P + 1))), dim3(256), 0, s, R, R.cut_elems,
+                               (const T*)mom, loc, nullptr, nullptr, nullptr, (int)c0);
+        else
+            hipLaunchKernelGGL((k_cut_local_a2<T, P, WHICH>), dim3((unsigned)(n * (P + 1) * (P + 1))), dim3(256), 0, s, R,
+                               R.cut_elems, (const T*)mom, loc, (int)c0);
+        int64_t r0 = 0, r1 = R.n_cut;
+        if (c0 > 0 || c1 < nce) {
+            const int e1lo = H->h_cut_elem_e1[c0], e1hi = H->h_cut_elem_e1[c1 - 1];
+            const auto& ri = H->h_cut_row_i1;
+            r0 = std::lower_bound(ri.begin(), ri.end(), e1lo) - ri.begin();
+            r1 = std::upper_bound(ri.begin(), ri.end(), e1hi + P) - ri.begin();
+        }
+        if (r1 > r0)
+            hipLaunchKernelGGL((k_cut_gather<T, P, WHICH>), dim3((unsigned)(r1 - r0)), dim3(RemCfg<P>::NT), 0, s, R,
+                               (const T*)loc, vm, vk, (int)c0, (int)c1, r0);
+    }
+}
+
+// scratch values per cut element of the moment form: moments and local rows
+template <int P>
+static constexpr int64_t moment_form_per_elem() {
+    using C = MomCfg<P>;
+    return (int64_t)C::NK3 + (int64_t)C::P1 * 2 * C::P2 * C::NP;
+}
+
+// buf == nullptr: scratch from the handle's stream-ordered pool; else the caller's buffer of
+// cap bytes, filled batch by batch (allocation-free variant)
+template <typename T, int P, int WHICH>
+static int launch_cut_p(const wq_rules* H, uint32_t parts, const T* kappa, T* vm, T* vk, hipStream_t s, void* buf,
+                        size_t cap) {
     const DevRules& R = H->R;
     if ((parts & WQ_CUT_REMAINDER) && R.n_cut > 0)
         hipLaunchKernelGGL((k_cut_remainder<T, P, WHICH>), dim3((unsigned)R.n_cut), dim3(RemCfg<P>::NT), 0, s, R, kappa, vm,
                            vk);
     if ((parts & WQ_CUT_OCTREE) && R.n_cut_elems > 0) {
-        {
-            if (R.levels <= 3) {
-                // moments scratch, stream ordered
-                // scratch (stream ordered): moments and local rows of every cut element
-                using C = MomCfg<P>;
-                const size_t nmom = (size_t)R.n_cut_elems * C::NK3;
-                const size_t nloc = (size_t)R.n_cut_elems * C::P1 * 2 * C::P2 * C::NP;
-                T* mom = nullptr;
-                hipError_t err = H->scratch_alloc((void**)&mom, sizeof(T) * (nmom + nloc), s);
-                if (err != hipSuccess)
-                    return wq_set_error(WQ_ENOMEM, "cut_assemble: scratch allocation failed: %s", hipGetErrorString(err));
-                T* loc = mom + nmom;
-                hipLaunchKernelGGL((k_cut_moments<T, P>), dim3((unsigned)R.n_cut_elems), dim3(256), 0, s, R, kappa, mom);
-                if constexpr (P <= 4)
-                    hipLaunchKernelGGL((k_cut_local<T, P, WHICH>), dim3((unsigned)(R.n_cut_elems * (P + 1))), dim3(256), 0, s,
-                                       R, R.cut_elems, (const T*)mom, loc, nullptr, nullptr, nullptr);
-                else
-                    hipLaunchKernelGGL((k_cut_local_a2<T, P, WHICH>), dim3((unsigned)(R.n_cut_elems * (P + 1) * (P + 1))),
-                                       dim3(256), 0, s, R, R.cut_elems, (const T*)mom, loc);
-                if (R.n_cut > 0)
-                    hipLaunchKernelGGL((k_cut_gather<T, P, WHICH>), dim3((unsigned)R.n_cut), dim3(RemCfg<P>::NT), 0, s, R,
-                                       (const T*)loc, vm, vk);
-                err = hipFreeAsync(mom, s);
-                if (err != hipSuccess)
-                    return wq_set_error(WQ_EHIP, "cut_assemble: scratch release failed: %s", hipGetErrorString(err));
+        if (R.levels <= 3) {
+            const int64_t per = moment_form_per_elem<P>();
+            if (buf) {
+                const int64_t nb = (int64_t)(cap / sizeof(T)) / per;
+                if (nb < 1)
+                    return wq_set_error(WQ_EINVAL, "cut_assemble_noalloc: one cut element needs %lld bytes of scratch, "
+                                                   "more than the fixed %zu", (long long)(per * sizeof(T)), cap);
+                launch_moment_form<T, P, WHICH>(H, kappa, vm, vk, (T*)buf, nb, s);
                 return WQ_OK;
             }
+            T* mom = nullptr;
+            hipError_t err = H->scratch_alloc((void**)&mom, sizeof(T) * (size_t)(per * R.n_cut_elems), s);
+            if (err != hipSuccess)
+                return wq_set_error(WQ_ENOMEM, "cut_assemble: scratch allocation failed: %s", hipGetErrorString(err));
+            launch_moment_form<T, P, WHICH>(H, kappa, vm, vk, mom, R.n_cut_elems, s);
+            err = hipFreeAsync(mom, s);
+            if (err != hipSuccess)
+                return wq_set_error(WQ_EHIP, "cut_assemble: scratch release failed: %s", hipGetErrorString(err));
+            return WQ_OK;
         }
         using C = OctCfg<P>;
         hipLaunchKernelGGL((k_cut_octree<T, P, WHICH>), dim3((unsigned)(R.n_cut_elems * C::P1 * C::NAG)), dim3(C::NT), 0, s, R,
@@ -1103,28 +1168,32 @@ static int launch_cut_p(const wq_rules* H, uint32_t parts, const T* kappa, T* vm
 }
 
 template <typename T, int P>
-static int launch_cut_w(const wq_rules* H, uint32_t which, uint32_t parts, const T* kappa, T* vm, T* vk, hipStream_t s) {
-    if (which == 1) return launch_cut_p<T, P, 1>(H, parts, kappa, vm, vk, s);
-    if (which == 2) return launch_cut_p<T, P, 2>(H, parts, kappa, vm, vk, s);
-    return launch_cut_p<T, P, 3>(H, parts, kappa, vm, vk, s);
+static int launch_cut_w(const wq_rules* H, uint32_t which, uint32_t parts, const T* kappa, T* vm, T* vk, hipStream_t s,
+                        void* buf, size_t cap) {
+    if (which == 1) return launch_cut_p<T, P, 1>(H, parts, kappa, vm, vk, s, buf, cap);
+    if (which == 2) return launch_cut_p<T, P, 2>(H, parts, kappa, vm, vk, s, buf, cap);
+    return launch_cut_p<T, P, 3>(H, parts, kappa, vm, vk, s, buf, cap);
 }
 
 template <typename T>
-int launch_cut(const wq_rules* H, uint32_t which, uint32_t parts, const T* kappa, T* vm, T* vk, hipStream_t s) {
+int launch_cut(const wq_rules* H, uint32_t which, uint32_t parts, const T* kappa, T* vm, T* vk, hipStream_t s, void* buf,
+               size_t cap) {
     switch (H->R.p) {
-        case 1: return launch_cut_w<T, 1>(H, which, parts, kappa, vm, vk, s);
-        case 2: return launch_cut_w<T, 2>(H, which, parts, kappa, vm, vk, s);
-        case 3: return launch_cut_w<T, 3>(H, which, parts, kappa, vm, vk, s);
-        case 4: return launch_cut_w<T, 4>(H, which, parts, kappa, vm, vk, s);
-        case 5: return launch_cut_w<T, 5>(H, which, parts, kappa, vm, vk, s);
-        case 6: return launch_cut_w<T, 6>(H, which, parts, kappa, vm, vk, s);
+        case 1: return launch_cut_w<T, 1>(H, which, parts, kappa, vm, vk, s, buf, cap);
+        case 2: return launch_cut_w<T, 2>(H, which, parts, kappa, vm, vk, s, buf, cap);
+        case 3: return launch_cut_w<T, 3>(H, which, parts, kappa, vm, vk, s, buf, cap);
+        case 4: return launch_cut_w<T, 4>(H, which, parts, kappa, vm, vk, s, buf, cap);
+        case 5: return launch_cut_w<T, 5>(H, which, parts, kappa, vm, vk, s, buf, cap);
+        case 6: return launch_cut_w<T, 6>(H, which, parts, kappa, vm, vk, s, buf, cap);
     }
     return WQ_OK;
 }
 
 #ifndef WQ_ONLY_F32
-template int launch_cut<double>(const wq_rules*, uint32_t, uint32_t, const double*, double*, double*, hipStream_t);
+template int launch_cut<double>(const wq_rules*, uint32_t, uint32_t, const double*, double*, double*, hipStream_t, void*,
+                                size_t);
 #endif
 #ifndef WQ_ONLY_F64
-template int launch_cut<float>(const wq_rules*, uint32_t, uint32_t, const float*, float*, float*, hipStream_t);
+template int launch_cut<float>(const wq_rules*, uint32_t, uint32_t, const float*, float*, float*, hipStream_t, void*,
+                               size_t);
 #endif

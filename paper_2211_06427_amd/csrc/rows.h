@@ -6,8 +6,10 @@
 template <typename T>
 void launch_rows(const wq_rules* H, uint32_t which, const T* kappa, T* vm, T* vk, hipStream_t s);
 void launch_rows_bf16x3(const wq_rules* H, uint32_t which, const float* kappa, float* vm, float* vk, hipStream_t s);
+// buf == nullptr: scratch from the handle's pool; else the caller's device buffer of cap bytes
 template <typename T>
-int launch_cut(const wq_rules* H, uint32_t which, uint32_t parts, const T* kappa, T* vm, T* vk, hipStream_t s);
+int launch_cut(const wq_rules* H, uint32_t which, uint32_t parts, const T* kappa, T* vm, T* vk, hipStream_t s,
+               void* buf = nullptr, size_t cap = 0);
 template <typename T>
 int launch_adjoint(const wq_rules* H, uint32_t which, const T* gm, const T* gk, T* dk, hipStream_t s);
 template <typename T>

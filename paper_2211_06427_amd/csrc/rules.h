@@ -29,6 +29,9 @@ struct wq_rules {
     int32_t* cell_elem = nullptr;       // octree leaf -> cut element
     double* kappa_xyz = nullptr;
     int64_t n_split = 0;
+    // host copies for batching the cut elements: direction-1 element index of every cut
+    // element and direction-1 function index of every cut row (both non-decreasing)
+    std::vector<int32_t> h_cut_elem_e1, h_cut_row_i1;
     hipMemPool_t pool = nullptr;        // stream-ordered scratch of the assembly calls (may be null)
     ~wq_rules() {
         for (void* p : allocs) (void)hipFree(p);

@@ -1456,6 +1456,20 @@ int build_rules(const wq_mesh* mesh, const wq_levelset* ls, const wq_options* op
     if (B.check(hipMemcpyAsync(&herr, d_err, sizeof(int), hipMemcpyDeviceToHost, stream))) return B.fail();
     if (B.check(hipStreamSynchronize(stream))) return B.fail();
     if (herr) return B.fail_msg(herr, "a weighted-quadrature exactness system is rank deficient");
+    {   // host copies that bound the batches of the allocation-free cut assembly
+        std::vector<int32_t> ce((size_t)R.n_cut_elems), cr((size_t)R.n_cut), a2l((size_t)H->n_active);
+        if (R.n_cut_elems > 0 &&
+            B.check(hipMemcpy(ce.data(), R.cut_elems, sizeof(int32_t) * ce.size(), hipMemcpyDeviceToHost)))
+            return B.fail();
+        if (R.n_cut > 0 && (B.check(hipMemcpy(cr.data(), R.cut_rows, sizeof(int32_t) * cr.size(), hipMemcpyDeviceToHost)) ||
+                            B.check(hipMemcpy(a2l.data(), R.act2lex, sizeof(int32_t) * a2l.size(), hipMemcpyDeviceToHost))))
+            return B.fail();
+        const int64_t ep = (int64_t)R.nel[1] * R.nel[2], fp = (int64_t)R.nfun[1] * R.nfun[2];
+        H->h_cut_elem_e1.resize(ce.size());
+        for (size_t i = 0; i < ce.size(); ++i) H->h_cut_elem_e1[i] = (int32_t)(ce[i] / ep);
+        H->h_cut_row_i1.resize(cr.size());
+        for (size_t i = 0; i < cr.size(); ++i) H->h_cut_row_i1[i] = (int32_t)(a2l[cr[i]] / fp);
+    }
     B.release_tmp();
     {   // scratch pool of the assembly calls; memory is kept between calls
         int dev = 0;
