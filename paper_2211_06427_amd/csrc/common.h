@@ -99,6 +99,10 @@ __device__ __host__ inline int xcd_logical(int b, int n) {
     return x * q + (x < r ? x : r) + b / NX;
 }
 
+// a * b + c with one rounding, for float and double
+__device__ inline float fmat(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ inline double fmat(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 __device__ __host__ inline int find_span(const double* t, int nt, int p, double x) {
     int lo = p, hi = nt - p - 2;
     if (x >= t[hi + 1]) {

@@ -120,7 +120,7 @@ k_cut_remainder(DevRules R, const T* __restrict__ kappa, T* __restrict__ vm, T* 
                 const T t0 = s_t1[sl][0][(d1 * P1 + g2) * P1 + d3];
                 const T w0 = W2[d2 * P1 + g2];
                 m0 += w0 * t0;
-                if (STIFF) ms += W2[P2 + d2 * P1 + g2] * t0 + w0 * s_t1[sl][1][(d1 * P1 + g2) * P1 + d3];
+                if (STIFF) ms = fmat(w0, s_t1[sl][1][(d1 * P1 + g2) * P1 + d3], fmat(W2[P2 + d2 * P1 + g2], t0, ms));
             }
             s_t2[sl][0][u] = m0;
             if (STIFF) s_t2[sl][1][u] = ms;
@@ -133,7 +133,7 @@ k_cut_remainder(DevRules R, const T* __restrict__ kappa, T* __restrict__ vm, T* 
                 const T t0 = s_t2[sl][0][g1 * P2 + d2 * P1 + d3];
                 const T w0 = W1[d1 * P1 + g1];
                 am += w0 * t0;
-                if (STIFF) ak += W1[P2 + d1 * P1 + g1] * t0 + w0 * s_t2[sl][1][g1 * P2 + d2 * P1 + d3];
+                if (STIFF) ak = fmat(w0, s_t2[sl][1][g1 * P2 + d2 * P1 + d3], fmat(W1[P2 + d1 * P1 + g1], t0, ak));
             }
             // trial J = e + (d1, d2, d3) = I + (d - kI): local index d - kI + P
             const int jj = ((d1 - kI0 + P) * M + (d2 - kI1 + P)) * M + (d3 - kI2 + P);
@@ -317,7 +317,7 @@ k_cut_octree(DevRules R, const int32_t* __restrict__ act2cut, const T* __restric
                         for (int g2 = 0; g2 < P1; ++g2) {
                             const T w0 = s_py[(a2B * P1 + bb2) * P1 + g2];
                             s0 += w0 * u0[g2];
-                            if (STIFF) ss += s_py[P2 * P1 + (a2B * P1 + bb2) * P1 + g2] * u0[g2] + w0 * u1[g2];
+                            if (STIFF) ss = fmat(w0, u1[g2], fmat(s_py[P2 * P1 + (a2B * P1 + bb2) * P1 + g2], u0[g2], ss));
                         }
                         accB[0][bb2] += s0;
                         accB[1][bb2] += ss;
@@ -352,7 +352,7 @@ k_cut_octree(DevRules R, const int32_t* __restrict__ act2cut, const T* __restric
                                 for (int g1 = 0; g1 < P1; ++g1) {
                                     const T w0 = s_px[(a1 * P1 + b1) * P1 + g1];
                                     sm += w0 * v0[g1];
-                                    if (STIFF) sk += s_px[P2 * P1 + (a1 * P1 + b1) * P1 + g1] * v0[g1] + w0 * vs[g1];
+                                    if (STIFF) sk = fmat(w0, vs[g1], fmat(s_px[P2 * P1 + (a1 * P1 + b1) * P1 + g1], v0[g1], sk));
                                 }
                                 accm[i][b1] += sm;
                                 acck[i][b1] += sk;
@@ -623,7 +623,7 @@ k_cut_local(DevRules R, const int32_t* __restrict__ elems, const T* __restrict__
         for (int k2 = 0; k2 < NK; ++k2) {
             const T u0 = s_s1[(k1 * NK + k2) * P1 + b3];
             m0 += y0[k2] * u0;
-            if (STIFF) ms += y1[k2] * u0 + y0[k2] * s_s1[NS1 + (k1 * NK + k2) * P1 + b3];
+            if (STIFF) ms = fmat(y0[k2], s_s1[NS1 + (k1 * NK + k2) * P1 + b3], fmat(y1[k2], u0, ms));
         }
         s_s2[i] = m0;
         if (STIFF) s_s2[NS2 + i] = ms;
@@ -785,7 +785,7 @@ k_cut_local_a2(DevRules R, const int32_t* __restrict__ elems, const T* __restric
         for (int k2 = 0; k2 < NK; ++k2) {
             const T u0 = s_s1[(k1 * NK + k2) * P1 + b3];
             m0 += y0[k2] * u0;
-            if (STIFF) ms += y1[k2] * u0 + y0[k2] * s_s1[NS1 + (k1 * NK + k2) * P1 + b3];
+            if (STIFF) ms = fmat(y0[k2], s_s1[NS1 + (k1 * NK + k2) * P1 + b3], fmat(y1[k2], u0, ms));
         }
         s_s2[i] = m0;
         if (STIFF) s_s2[NS2 + i] = ms;

@@ -10,6 +10,8 @@
 // Cut rows: one workgroup per cut row.  Rows with a DWQ box use the one-sided rule in the
 // split direction and the standard rules in the others (kappa gathered through the slot
 // map); rows without a box are zeroed (their support is handled by cut_assemble).
+#include <type_traits>
+
 #include "rows.h"
 
 template <typename T> __device__ inline const T* wt_table(const DevRules& R, int d);
@@ -233,7 +235,7 @@ k_rows_interior(DevRules R, const T* __restrict__ kappa, T* __restrict__ vm, T* 
             for (int j2 = 0; j2 < M; ++j2) {
                 const T w0 = s_w2[j2 * NWP + q2];
                 m0[j2] += w0 * a0;
-                if (C::STIFF) ms[j2] += s_w2[(M + j2) * NWP + q2] * a0 + w0 * a1;
+                if (C::STIFF) ms[j2] = fmat(w0, a1, fmat(s_w2[(M + j2) * NWP + q2], a0, ms[j2]));
             }
         }
 #pragma unroll
@@ -304,7 +306,7 @@ k_rows_interior(DevRules R, const T* __restrict__ kappa, T* __restrict__ vm, T* 
                         if (q >= qa && q < qb) {
                             const T a = w10[jj1 * NW + q];
                             if (C::MASS) am += a * t00[q];
-                            if (C::STIFF) ak += w11[jj1 * NW + q] * t00[q] + a * ts[q];
+                            if (C::STIFF) ak = fmat(a, ts[q], fmat(w11[jj1 * NW + q], t00[q], ak));
                         }
                     }
                     if (live) {
@@ -321,7 +323,7 @@ k_rows_interior(DevRules R, const T* __restrict__ kappa, T* __restrict__ vm, T* 
                     for (int q = 0; q < NW; ++q) {
                         const T a = w10[jj1 * NW + q];
                         if (C::MASS) am += a * t00[q];
-                        if (C::STIFF) ak += w11[jj1 * NW + q] * t00[q] + a * ts[q];
+                        if (C::STIFF) ak = fmat(a, ts[q], fmat(w11[jj1 * NW + q], t00[q], ak));
                     }
                     if (live) {
                         const int64_t o = base + ((int64_t)(jj1 - lo1) * m2 + (jj2 - lo2)) * m3 + (jj3 - lo3);
@@ -366,41 +368,107 @@ struct BlkCfg {
     static constexpr int M = 2 * P + 1, MM = M * M, NT = 256;
     static constexpr int NWT = 4 * P;                  // row stride of the weight tables
     static constexpr int NWB = 3 * P + 1;              // largest window
-    static constexpr int NR = 2 * P + 2;               // points of a regular window
     static constexpr int NQB = 2 * RB + 4 * P - 2;     // direction-1 points of a block
-    static constexpr int T1N = 2 * NQB * NWB * M;      // stage-1 sums; the slab reuses the space
+    // LDS strides chosen so that threads with consecutive (plane, j) indices hit consecutive
+    // banks: a stage-1 plane [v][q2][j3] and a slab plane [v][j2 j3] both start M banks
+    // after the previous plane (32 banks)
+    static constexpr int pad_to(int n) { return n + (((M - n) % 32) + 32) % 32; }
+    static constexpr int P1S = pad_to(2 * NWB * M);    // stage-1 plane stride
+    static constexpr int PSL = pad_to(2 * MM);         // slab plane stride
+    static constexpr int BUFN = NQB * (P1S > PSL ? P1S : PSL);
+    static constexpr int W1S = 2 * M * NWT + 4;        // row stride of the staged direction-1 weights
+    static constexpr int IPL1 = (NQB * NWB + NT - 1) / NT;   // stage-1 items per thread
 };
 
-__device__ inline bool regular_window(int i, int p, int nel) { return i >= p + 1 && i <= nel - 2; }
+// Window classes of the 1D rule of function i along a direction with at least p+2 elements:
+//   0        regular, i in [p+1, nel-2]: elements i-p..i, two points each (2p+2 points);
+//   1+k      low end, i = k in [0, p]: elements 0..k, element 0 with all p+1 points;
+//   p+1+m    high end, i = nel+p-m, m in [1, p+1]: the last m elements, the last one with all
+//            p+1 points.
+// For each class the window element of every point and the trial range are known at compile
+// time, hence the band of trial functions jj that are nonzero at a point (B_j vanishes off
+// its p+1 elements).
+template <int P, int CLS>
+struct Win {
+    static constexpr bool LOW = CLS >= 1 && CLS <= P + 1, HIGH = CLS >= P + 2;
+    static constexpr int K = LOW ? CLS - 1 : 0, MEL = HIGH ? CLS - P - 1 : 0;
+    static constexpr int NW = LOW ? P + 1 + 2 * K : (HIGH ? 2 * (MEL - 1) + P + 1 : 2 * P + 2);
+    static constexpr int JLO = LOW ? P - K : 0, JHI = HIGH ? MEL - 1 + P : 2 * P;
+    static constexpr int el(int q) {
+        return LOW ? (q < P + 1 ? 0 : 1 + (q - P - 1) / 2) : (HIGH ? (q < 2 * (MEL - 1) ? q / 2 : MEL - 1) : q / 2);
+    }
+    static constexpr int jlo(int q) { return (LOW ? el(q) + P - K : el(q)) > JLO ? (LOW ? el(q) + P - K : el(q)) : JLO; }
+    static constexpr int jhi(int q) { return (LOW ? el(q) + 2 * P - K : el(q) + P) < JHI ? (LOW ? el(q) + 2 * P - K : el(q) + P) : JHI; }
+};
+
+__device__ inline int window_class(int i, int p, int nel) {
+    if (i <= p) return 1 + i;
+    if (i >= nel - 1) return p + 1 + (nel + p - i);
+    return 0;
+}
+
+// calls f(std::integral_constant<int, CLS>) for the runtime class cls
+template <int P, int C = 0, typename F>
+__device__ inline void with_window(int cls, F&& f) {
+    if constexpr (C < 2 * P + 3) {
+        if (cls == C) f(std::integral_constant<int, C>{});
+        else with_window<P, C + 1>(cls, f);
+    }
+}
 
 // Stages, for the block's rows i1s..i1s+nrows-1 at fixed (i2, i3) and the union of their
 // direction-1 windows (planes q1 of the kappa grid):
 //   1. T1_v[q1][q2][j3] = sum_q3 W3_v[j3][q3] kappa[q1][q2][q3], v = 00 / 11 rules
-//      (one thread per (q1, q2), kappa read straight from the grid);
+//      (one thread per (q1, q2); its kappa row is loaded before the first barrier);
 //   2. T2[q1][j2 j3] = sum_q2 W2_00[j2][q2] T1_00, Ts = sum_q2 W2_11 T1_00 + W2_00 T1_11
 //      (one thread per (q1, j3));
 //   3. row r, column c = (j2, j3): M[j1][c] = sum_q W1_00[j1][q] T2[off_r + q][c],
 //      K = sum_q W1_11 T2 + W1_00 Ts (one thread per (row, column); all of a block's rows
 //      share the slab), stored at the row's CSR offsets (contiguous per j1).
+// Every contraction runs over the compile-time band of its window class; stiffness sums are
+// accumulated one product per fused multiply-add.
 template <int P, int WHICH, int RB>
 __global__ void __launch_bounds__(256, 3)
 k_rows_block(DevRules R, const float* __restrict__ kappa, float* __restrict__ vm, float* __restrict__ vk) {
     using C = BlkCfg<P, RB>;
-    constexpr int M = C::M, MM = C::MM, NT = C::NT, NWT = C::NWT, NWB = C::NWB, NR = C::NR, NQB = C::NQB;
+    constexpr int M = C::M, MM = C::MM, NT = C::NT, NWT = C::NWT, NWB = C::NWB, NQB = C::NQB;
+    constexpr int P1S = C::P1S, PSL = C::PSL, W1S = C::W1S, IPL1 = C::IPL1;
     constexpr bool MASS = (WHICH & 1) != 0, STIFF = (WHICH & 2) != 0;
-    __shared__ float s_buf[C::T1N];
-    __shared__ float s_w1[RB * 2 * M * NWT];
+    __shared__ float s_buf[C::BUFN];
+    __shared__ float s_w1[RB * W1S];
     __shared__ float s_w2[2 * M * NWT], s_w3[2 * M * NWT];
     __shared__ int64_t s_base[RB];
-    __shared__ int s_off[RB], s_nw[RB], s_lo[RB], s_hi[RB], s_reg[RB];
+    __shared__ int s_off[RB], s_cls[RB];
 
     const int4 blk = R.fblocks[xcd_logical(blockIdx.x, gridDim.x)];
     const int i1s = blk.x, i2 = blk.y, i3 = blk.z, nrows = blk.w;
     const int t = threadIdx.x;
-    const int n1 = R.nfun[0], n2 = R.nfun[1], n3 = R.nfun[2];
+    const int n2 = R.nfun[1], n3 = R.nfun[2];
+    const int qbase = R.xs[0][i1s];
+    const int i1e = i1s + nrows - 1;
+    const int nq1 = R.xs[0][i1e] + R.nwin[0][i1e] - qbase;
+    const int xs2 = R.xs[1][i2], nw2 = R.nwin[1][i2];
+    const int xs3 = R.xs[2][i3], nw3 = R.nwin[2][i3];
+    const int cls2 = window_class(i2, P, R.nel[1]);
+    const int cls3 = window_class(i3, P, R.nel[2]);
+    const int nx2 = R.nx[1], nx3 = R.nx[2];
+    // kappa row of this thread's first stage-1 item, issued together with the table loads
+    // below (a block with more than NT items loads the rest in stage 1)
+    auto kappa_row = [&](int it, float* kv) {
+        const int q1 = it / nw2, q2 = it - q1 * nw2;
+        const bool on = it < nq1 * nw2;
+        const float* kr = kappa + ((int64_t)(qbase + (on ? q1 : 0)) * nx2 + xs2 + (on ? q2 : 0)) * nx3 + xs3;
+#pragma unroll
+        for (int q = 0; q < NWB; ++q) kv[q] = (on && q < nw3) ? kr[q] : 0.f;
+    };
+    float kv[NWB];
+    kappa_row(t, kv);
     {
         const float* W1 = R.Wt32[0] + (int64_t)i1s * 2 * M * NWT;
-        for (int k = t; k < nrows * 2 * M * NWT; k += NT) s_w1[k] = W1[k];
+        for (int k = t; k < nrows * 2 * M * NWT; k += NT) {
+            const int r = k / (2 * M * NWT);
+            s_w1[r * W1S + (k - r * 2 * M * NWT)] = W1[k];
+        }
         const float* W2 = R.Wt32[1] + (int64_t)i2 * 2 * M * NWT;
         const float* W3 = R.Wt32[2] + (int64_t)i3 * 2 * M * NWT;
         for (int k = t; k < 2 * M * NWT; k += NT) {
@@ -408,114 +476,95 @@ k_rows_block(DevRules R, const float* __restrict__ kappa, float* __restrict__ vm
             s_w3[k] = W3[k];
         }
     }
-    const int qbase = R.xs[0][i1s];
     if (t < nrows) {
         const int i1 = i1s + t;
         const int ra = R.lex2act[((int64_t)i1 * n2 + i2) * n3 + i3];
         s_base[t] = R.row_ptr[ra];
         s_off[t] = R.xs[0][i1] - qbase;
-        s_nw[t] = R.nwin[0][i1];
-        s_lo[t] = i1 - P < 0 ? P - i1 : 0;
-        s_hi[t] = i1 + P > n1 - 1 ? n1 - 1 - i1 + P : 2 * P;
-        s_reg[t] = regular_window(i1, P, R.nel[0]);
+        s_cls[t] = window_class(i1, P, R.nel[0]);
     }
-    const int i1e = i1s + nrows - 1;
-    const int nq1 = R.xs[0][i1e] + R.nwin[0][i1e] - qbase;
-    const int xs2 = R.xs[1][i2], nw2 = R.nwin[1][i2];
-    const int xs3 = R.xs[2][i3], nw3 = R.nwin[2][i3];
-    const bool reg2 = regular_window(i2, P, R.nel[1]);
-    const bool reg3 = regular_window(i3, P, R.nel[2]);
-    const int nx2 = R.nx[1], nx3 = R.nx[2];
     __syncthreads();
 
     // ---- stage 1: items (q1, q2).  Layouts in s_buf, plane by plane: stage-1 sums
-    // [q1][v][q2][j3] (2 NWB M values per plane), slab [q1][v][j2 j3] (2 MM per plane) ----
-    constexpr int P1S = 2 * NWB * M, PSL = 2 * MM;
-    for (int it = t; it < nq1 * nw2; it += NT) {
-        const int q1 = it / nw2, q2 = it - q1 * nw2;
-        const float* kr = kappa + ((int64_t)(qbase + q1) * nx2 + xs2 + q2) * nx3 + xs3;
-        float a0[M], a1[M];
-#pragma unroll
-        for (int j = 0; j < M; ++j) { a0[j] = 0.f; a1[j] = 0.f; }
-        if (reg3) {
-            float kv[NR];
-#pragma unroll
-            for (int q = 0; q < NR; ++q) kv[q] = kr[q];
-#pragma unroll
-            for (int q = 0; q < NR; ++q)
-#pragma unroll
-                for (int j = q / 2; j <= q / 2 + P; ++j) {
-                    a0[j] += s_w3[j * NWT + q] * kv[q];
-                    if (STIFF) a1[j] += s_w3[(M + j) * NWT + q] * kv[q];
-                }
-        } else {
+    // [q1][v][q2][j3] (stride P1S), slab [q1][v][j2 j3] (stride PSL) ----
+    with_window<P>(cls3, [&](auto cc) {
+        using Wn = Win<P, decltype(cc)::value>;
 #pragma unroll 1
-            for (int q = 0; q < nw3; ++q) {
-                const float kv = kr[q];
+        for (int k = 0; k < IPL1; ++k) {
+            const int it = t + k * NT;
+            if (it >= nq1 * nw2) break;
+            if (k > 0) kappa_row(it, kv);
+            // keep the weight loads inside the loop: hoisted, the uniform weights of a
+            // class take over a hundred registers for at most two items
+            asm volatile("" ::: "memory");
+            const int q1 = it / nw2, q2 = it - q1 * nw2;
+            float a0[M], a1[M];
 #pragma unroll
-                for (int j = 0; j < M; ++j) {
-                    a0[j] += s_w3[j * NWT + q] * kv;
-                    if (STIFF) a1[j] += s_w3[(M + j) * NWT + q] * kv;
+            for (int j = 0; j < M; ++j) { a0[j] = 0.f; a1[j] = 0.f; }
+#pragma unroll
+            for (int q = 0; q < Wn::NW; ++q)
+#pragma unroll
+                for (int j = Wn::jlo(q); j <= Wn::jhi(q); ++j) {
+                    a0[j] = __builtin_fmaf(s_w3[j * NWT + q], kv[q], a0[j]);
+                    if (STIFF) a1[j] = __builtin_fmaf(s_w3[(M + j) * NWT + q], kv[q], a1[j]);
                 }
+            float* o0 = s_buf + q1 * P1S + q2 * M;
+#pragma unroll
+            for (int j = Wn::JLO; j <= Wn::JHI; ++j) {
+                o0[j] = a0[j];
+                if (STIFF) o0[NWB * M + j] = a1[j];
             }
         }
-        float* o0 = s_buf + q1 * P1S + q2 * M;
-#pragma unroll
-        for (int j = 0; j < M; ++j) {
-            o0[j] = a0[j];
-            if (STIFF) o0[NWB * M + j] = a1[j];
-        }
-    }
+    });
     __syncthreads();
 
     // ---- stage 2: items (q1, j3), in rounds of NT items ordered by q1.  A round keeps its
     // results in registers until all its threads have read their stage-1 sums, then writes
-    // them over the slab planes of its q1; slab plane q1 ends below stage-1 plane q1 + 1
-    // (2 MM < 2 NWB M), so a round never overwrites sums that a later round reads ----
-    static_assert(PSL < P1S && (NT / M) * (P1S - PSL) >= PSL,
+    // them over the slab planes of its q1; when a block needs several rounds, slab plane q1
+    // ends below stage-1 plane q1 + 1 (PSL < P1S), so a round never overwrites sums that a
+    // later round reads.  Entries of trial indices outside the windows' ranges are never
+    // written and never read ----
+    static_assert(NQB * M <= NT || (PSL < P1S && (NT / M) * (P1S - PSL) >= PSL),
                   "a round's slab planes end below the stage-1 planes of later rounds");
     for (int base = 0; base < nq1 * M; base += NT) {
+        asm volatile("" ::: "memory");             // weight loads stay inside the round
         const int it = base + t;
         const int q1 = it / M, j3 = it - q1 * M;
         float r0[M], rs[M];
 #pragma unroll
         for (int j = 0; j < M; ++j) { r0[j] = 0.f; rs[j] = 0.f; }
         const bool on = it < nq1 * M;
-        if (on) {
-            const float* t0 = s_buf + q1 * P1S + j3;
-            const float* t1 = t0 + NWB * M;
-            if (reg2) {
+        int jlo2 = 0, jhi2 = -1;
+        with_window<P>(cls2, [&](auto cc) {
+            using Wn = Win<P, decltype(cc)::value>;
+            jlo2 = Wn::JLO; jhi2 = Wn::JHI;
+            if (on) {
+                const float* t0 = s_buf + q1 * P1S + j3;
+                const float* t1 = t0 + NWB * M;
 #pragma unroll
-                for (int q = 0; q < NR; ++q) {
+                for (int q = 0; q < Wn::NW; ++q) {
                     const float x0 = t0[q * M];
                     const float x1 = STIFF ? t1[q * M] : 0.f;
 #pragma unroll
-                    for (int j = q / 2; j <= q / 2 + P; ++j) {
+                    for (int j = Wn::jlo(q); j <= Wn::jhi(q); ++j) {
                         const float w0 = s_w2[j * NWT + q];
-                        r0[j] += w0 * x0;
-                        if (STIFF) rs[j] += s_w2[(M + j) * NWT + q] * x0 + w0 * x1;
-                    }
-                }
-            } else {
-#pragma unroll 1
-                for (int q = 0; q < nw2; ++q) {
-                    const float x0 = t0[q * M];
-                    const float x1 = STIFF ? t1[q * M] : 0.f;
-#pragma unroll
-                    for (int j = 0; j < M; ++j) {
-                        const float w0 = s_w2[j * NWT + q];
-                        r0[j] += w0 * x0;
-                        if (STIFF) rs[j] += s_w2[(M + j) * NWT + q] * x0 + w0 * x1;
+                        r0[j] = __builtin_fmaf(w0, x0, r0[j]);
+                        if (STIFF) {
+                            rs[j] = __builtin_fmaf(s_w2[(M + j) * NWT + q], x0, rs[j]);
+                            rs[j] = __builtin_fmaf(w0, x1, rs[j]);
+                        }
                     }
                 }
             }
-        }
+        });
         __syncthreads();
         if (on) {
 #pragma unroll
             for (int j = 0; j < M; ++j) {
-                s_buf[q1 * PSL + j * M + j3] = r0[j];
-                if (STIFF) s_buf[q1 * PSL + MM + j * M + j3] = rs[j];
+                if (j >= jlo2 && j <= jhi2) {
+                    s_buf[q1 * PSL + j * M + j3] = r0[j];
+                    if (STIFF) s_buf[q1 * PSL + MM + j * M + j3] = rs[j];
+                }
             }
         }
         __syncthreads();
@@ -529,64 +578,41 @@ k_rows_block(DevRules R, const float* __restrict__ kappa, float* __restrict__ vm
         const int r = it / MM, c = it - r * MM;
         const int jj2 = c / M, jj3 = c - jj2 * M;
         const bool live = jj2 >= lo2 && jj2 <= hi2 && jj3 >= lo3 && jj3 <= hi3;
-        const int lo1 = s_lo[r], hi1 = s_hi[r];
         const int64_t ob = s_base[r] + (int64_t)(jj2 - lo2) * m3 + (jj3 - lo3);
         const int step = m2 * m3;
-        const float* w10 = s_w1 + r * 2 * M * NWT;
+        const float* w10 = s_w1 + r * W1S;
         const float* w11 = w10 + M * NWT;
         const float* x0 = s_buf + s_off[r] * PSL + c;
         const float* xs = x0 + MM;
-        if (s_reg[r]) {
-            float t0[NR], ts[NR];
+        with_window<P>(s_cls[r], [&](auto cc) {
+            using Wn = Win<P, decltype(cc)::value>;
+            float t0[Wn::NW], ts[Wn::NW];
 #pragma unroll
-            for (int q = 0; q < NR; ++q) {
-                t0[q] = x0[q * PSL];
-                ts[q] = STIFF ? xs[q * PSL] : 0.f;
+            for (int q = 0; q < Wn::NW; ++q) {
+                t0[q] = live ? x0[q * PSL] : 0.f;
+                ts[q] = (STIFF && live) ? xs[q * PSL] : 0.f;
             }
 #pragma unroll
-            for (int jj1 = 0; jj1 < M; ++jj1) {
-                const int qa = 2 * (jj1 - P > 0 ? jj1 - P : 0);
-                const int qb = 2 * ((jj1 < P ? jj1 : P) + 1);
+            for (int jj1 = Wn::JLO; jj1 <= Wn::JHI; ++jj1) {
                 float am = 0.f, ak = 0.f;
 #pragma unroll
-                for (int q = 0; q < NR; ++q) {
-                    if (q >= qa && q < qb) {
+                for (int q = 0; q < Wn::NW; ++q) {
+                    if (jj1 >= Wn::jlo(q) && jj1 <= Wn::jhi(q)) {
                         const float a = w10[jj1 * NWT + q];
-                        if (MASS) am += a * t0[q];
-                        if (STIFF) ak += w11[jj1 * NWT + q] * t0[q] + a * ts[q];
+                        if (MASS) am = __builtin_fmaf(a, t0[q], am);
+                        if (STIFF) {
+                            ak = __builtin_fmaf(w11[jj1 * NWT + q], t0[q], ak);
+                            ak = __builtin_fmaf(a, ts[q], ak);
+                        }
                     }
                 }
                 if (live) {
-                    const int64_t o = ob + (int64_t)jj1 * step;
+                    const int64_t o = ob + (int64_t)(jj1 - Wn::JLO) * step;
                     if (MASS) vm[o] = am;
                     if (STIFF) vk[o] = ak;
                 }
             }
-        } else {
-            const int nw1 = s_nw[r];
-            float am[M], ak[M];
-#pragma unroll
-            for (int jj1 = 0; jj1 < M; ++jj1) { am[jj1] = 0.f; ak[jj1] = 0.f; }
-#pragma unroll 1
-            for (int q = 0; q < nw1; ++q) {
-                const float v0 = x0[q * PSL];
-                const float vs = STIFF ? xs[q * PSL] : 0.f;
-#pragma unroll
-                for (int jj1 = 0; jj1 < M; ++jj1) {
-                    const float a = w10[jj1 * NWT + q];
-                    if (MASS) am[jj1] += a * v0;
-                    if (STIFF) ak[jj1] += w11[jj1 * NWT + q] * v0 + a * vs;
-                }
-            }
-#pragma unroll
-            for (int jj1 = 0; jj1 < M; ++jj1) {
-                if (live && jj1 >= lo1 && jj1 <= hi1) {
-                    const int64_t o = ob + (int64_t)(jj1 - lo1) * step;
-                    if (MASS) vm[o] = am[jj1];
-                    if (STIFF) vk[o] = ak[jj1];
-                }
-            }
-        }
+        });
     }
 }
 
@@ -762,7 +788,7 @@ k_rows_cut(DevRules R, const T* __restrict__ kappa, T* __restrict__ vm, T* __res
                 const T t0 = s_t1[((0 * QCH + qCl) * NW + qB) * M + jA];
                 const T w0 = s_w[1][jB * NA + qB];
                 m0 += w0 * t0;
-                if (C::STIFF) ms += s_w[1][(M + jB) * NA + qB] * t0 + w0 * s_t1[((1 * QCH + qCl) * NW + qB) * M + jA];
+                if (C::STIFF) ms = fmat(w0, s_t1[((1 * QCH + qCl) * NW + qB) * M + jA], fmat(s_w[1][(M + jB) * NA + qB], t0, ms));
             }
             s_t2[(0 * NW + qC) * MM + jB * M + jA] = m0;
             if (C::STIFF) s_t2[(1 * NW + qC) * MM + jB * M + jA] = ms;
@@ -780,7 +806,7 @@ k_rows_cut(DevRules R, const T* __restrict__ kappa, T* __restrict__ vm, T* __res
             const T t0 = s_t2[(0 * NW + qC) * MM + cc];
             const T a = s_w[2][jC * NA + qC];
             if (C::MASS) am += a * t0;
-            if (C::STIFF) ak += s_w[2][(M + jC) * NA + qC] * t0 + a * s_t2[(1 * NW + qC) * MM + cc];
+            if (C::STIFF) ak = fmat(a, s_t2[(1 * NW + qC) * MM + cc], fmat(s_w[2][(M + jC) * NA + qC], t0, ak));
         }
         const int k = pq[i];
         if (k >= 0) {
@@ -830,6 +856,7 @@ k_rows_box(DevRules R, const T* __restrict__ kappa, T* __restrict__ vm, T* __res
     __shared__ T s_wa[2 * M * NDQ], s_wb[2 * M * NWT], s_wc[2 * M * NWT];
     __shared__ int s_g[3][C::NQM], s_e[3][C::NQM], s_l[3][C::NQM];   // per direction and point: slot parts
     __shared__ int s_n[3];
+    __shared__ int s_qa[2][M];                   // nonzero point range [s_qa[0][j], s_qa[1][j]) of W_A[.][j][.]
 
     const int64_t cr = R.box_rows[blockIdx.x];
     const int ra = R.cut_rows[cr];
@@ -887,6 +914,23 @@ k_rows_box(DevRules R, const T* __restrict__ kappa, T* __restrict__ vm, T* __res
     const int32_t* pos = R.pos_map + cr * (int64_t)M * MM;
     __syncthreads();
     const int nA = s_n[0], nB = s_n[1], nC = s_n[2];
+    // W_A[v][jA][qA] vanishes unless point qA lies in the support of trial function jA: the
+    // nonzero points of each jA form one range (the points are ordered)
+    if (t < M) {
+        int lo = nA, hi = 0;
+        for (int q = 0; q < nA; ++q)
+            if (s_wa[t * NDQ + q] != (T)0 || s_wa[(M + t) * NDQ + q] != (T)0) {
+                lo = q < lo ? q : lo;
+                hi = q + 1;
+            }
+        s_qa[0][t] = lo < hi ? lo : 0;
+        s_qa[1][t] = lo < hi ? hi : 0;
+    }
+    // regular standard windows (2p+2 points, two per element): W[j][q] != 0 only for
+    // q in [2 max(0, j-p), 2 (min(j, p) + 1))
+    const int IBr = dB == 0 ? I[0] : I[1], ICr = dC == 1 ? I[1] : I[2];
+    const bool regB = IBr >= P + 1 && IBr <= R.nel[dB] - 2;
+    const bool regC = ICr >= P + 1 && ICr <= R.nel[dC] - 2;
     const int npts = nA * nB * nC;
     // ---- kappa of the box: [qC qB][qA] ----
     {
@@ -934,8 +978,9 @@ k_rows_box(DevRules R, const T* __restrict__ kappa, T* __restrict__ vm, T* __res
             }
             const T* w0p = s_wa + jA * NDQ;
             const T* w1p = s_wa + (M + jA) * NDQ;
+            const int qlo = s_qa[0][jA], qhi = s_qa[1][jA];
 #pragma unroll 2
-            for (int qA = 0; qA < nA; ++qA) {
+            for (int qA = qlo; qA < qhi; ++qA) {
                 const T w0 = w0p[qA];
                 const T w1 = STIFF ? w1p[qA] : (T)0;
 #pragma unroll
@@ -974,15 +1019,17 @@ k_rows_box(DevRules R, const T* __restrict__ kappa, T* __restrict__ vm, T* __res
             }
             const T* w0p = s_wb + jB * NWT;
             const T* w1p = s_wb + (M + jB) * NWT;
+            const int qlo = regB ? 2 * (jB - P > 0 ? jB - P : 0) : 0;
+            const int qhi = regB ? 2 * ((jB < P ? jB : P) + 1) : nB;
 #pragma unroll 2
-            for (int qB = 0; qB < nB; ++qB) {
+            for (int qB = qlo; qB < qhi; ++qB) {
                 const T w0 = w0p[qB];
                 const T w1 = STIFF ? w1p[qB] : (T)0;
 #pragma unroll
                 for (int k = 0; k < G; ++k) {
                     const T t0 = s_t1[base[k] + qB * M];
                     m0[k] += w0 * t0;
-                    if (STIFF) ms[k] += w1 * t0 + w0 * s_t1[NWB * NWB * M + base[k] + qB * M];
+                    if (STIFF) ms[k] = fmat(w0, s_t1[NWB * NWB * M + base[k] + qB * M], fmat(w1, t0, ms[k]));
                 }
             }
 #pragma unroll
@@ -1013,15 +1060,17 @@ k_rows_box(DevRules R, const T* __restrict__ kappa, T* __restrict__ vm, T* __res
             }
             const T* w0p = s_wc + jC * NWT;
             const T* w1p = s_wc + (M + jC) * NWT;
+            const int qlo = regC ? 2 * (jC - P > 0 ? jC - P : 0) : 0;
+            const int qhi = regC ? 2 * ((jC < P ? jC : P) + 1) : nC;
 #pragma unroll 2
-            for (int qC = 0; qC < nC; ++qC) {
+            for (int qC = qlo; qC < qhi; ++qC) {
                 const T w0 = w0p[qC];
                 const T w1 = STIFF ? w1p[qC] : (T)0;
 #pragma unroll
                 for (int k = 0; k < G; ++k) {
                     const T t0 = s_kb[qC * MM + ck[k]];
                     if (MASS) am[k] += w0 * t0;
-                    if (STIFF) ak[k] += w1 * t0 + w0 * s_kb[NWB * MM + qC * MM + ck[k]];
+                    if (STIFF) ak[k] = fmat(w0, s_kb[NWB * MM + qC * MM + ck[k]], fmat(w1, t0, ak[k]));
                 }
             }
 #pragma unroll
@@ -1051,13 +1100,13 @@ static bool windows_fit(const DevRules& R) {
 static bool block_kernel_fits(const DevRules& R) { return R.p <= 4 && R.n_fblocks > 0 && windows_fit(R); }
 
 template <typename T, int P, int WHICH>
-static void launch_rows_p(const wq_rules* H, const T* kappa, T* vm, T* vk, hipStream_t s) {
+static void launch_interior_rows(const wq_rules* H, const T* kappa, T* vm, T* vk, hipStream_t s) {
     const DevRules& R = H->R;
     if constexpr (sizeof(T) == 4 && P <= 4) {
         if (block_kernel_fits(R)) {
             hipLaunchKernelGGL((k_rows_block<P, WHICH, 8>), dim3((unsigned)R.n_fblocks), dim3(256), 0, s, R,
                                (const float*)kappa, (float*)vm, (float*)vk);
-            goto cut_rows;
+            return;
         }
     }
     if (R.n_lblocks > 0) {
@@ -1077,7 +1126,11 @@ static void launch_rows_p(const wq_rules* H, const T* kappa, T* vm, T* vk, hipSt
                                vm, vk);
         }
     }
-cut_rows:
+}
+
+template <typename T, int P, int WHICH>
+static void launch_cut_rows(const wq_rules* H, const T* kappa, T* vm, T* vk, hipStream_t s) {
+    const DevRules& R = H->R;
     if (R.n_box > 0) {
         bool done = false;
         if constexpr (P <= 4) {
@@ -1091,6 +1144,32 @@ cut_rows:
     }
     if (R.n_cut > R.n_box)
         hipLaunchKernelGGL((k_rows_zero<T, WHICH>), dim3((unsigned)((R.n_cut + 3) / 4)), dim3(256), 0, s, R, vm, vk);
+}
+
+// The cut rows run on the handle's side stream beside the interior rows on the caller's
+// stream (they write disjoint rows): forked after the caller's earlier work, joined back
+// before anything the caller enqueues later.
+template <typename T, int P, int WHICH>
+static void launch_rows_p(const wq_rules* H, const T* kappa, T* vm, T* vk, hipStream_t s) {
+    const DevRules& R = H->R;
+    if (!(H->side && R.n_cut > 0)) {
+        launch_cut_rows<T, P, WHICH>(H, kappa, vm, vk, s);
+        launch_interior_rows<T, P, WHICH>(H, kappa, vm, vk, s);
+        return;
+    }
+    std::lock_guard<std::mutex> lock(*H->side_mu);
+    if (hipEventRecord(H->ev_fork, s) != hipSuccess || hipStreamWaitEvent(H->side, H->ev_fork, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        launch_cut_rows<T, P, WHICH>(H, kappa, vm, vk, s);
+        launch_interior_rows<T, P, WHICH>(H, kappa, vm, vk, s);
+        return;
+    }
+    launch_cut_rows<T, P, WHICH>(H, kappa, vm, vk, H->side);
+    launch_interior_rows<T, P, WHICH>(H, kappa, vm, vk, s);
+    if (hipEventRecord(H->ev_join, H->side) != hipSuccess || hipStreamWaitEvent(s, H->ev_join, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipStreamSynchronize(H->side);    // the join failed: finish the side stream's work here
+    }
 }
 
 #ifndef WQ_ONLY_F64

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <cstdarg>
+#include <mutex>
 #include <vector>
 
 #include "common.h"
@@ -33,7 +34,17 @@ struct wq_rules {
     // element and direction-1 function index of every cut row (both non-decreasing)
     std::vector<int32_t> h_cut_elem_e1, h_cut_row_i1;
     hipMemPool_t pool = nullptr;        // stream-ordered scratch of the assembly calls (may be null)
+    // second stream of the row assembly: the cut rows run on it beside the interior rows
+    // (forked from and joined back into the caller's stream with the two events); the
+    // mutex keeps one call's record / wait sequence from interleaving with another's
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    std::mutex* side_mu = nullptr;
     ~wq_rules() {
+        if (side) (void)hipStreamDestroy(side);
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_join) (void)hipEventDestroy(ev_join);
+        delete side_mu;
         for (void* p : allocs) (void)hipFree(p);
         if (pool) (void)hipMemPoolDestroy(pool);
     }

@@ -1489,6 +1489,19 @@ int build_rules(const wq_mesh* mesh, const wq_levelset* ls, const wq_options* op
             }
         }
     }
+    // side stream (default priority) and fork / join events of the row assembly; without
+    // them the rows run on the caller's stream alone
+    if (hipStreamCreateWithFlags(&H->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&H->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&H->ev_join, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        if (H->side) (void)hipStreamDestroy(H->side);
+        if (H->ev_fork) (void)hipEventDestroy(H->ev_fork);
+        if (H->ev_join) (void)hipEventDestroy(H->ev_join);
+        H->side = nullptr; H->ev_fork = H->ev_join = nullptr;
+    } else {
+        H->side_mu = new std::mutex;
+    }
     *out = H;
     return WQ_OK;
 }
