@@ -369,11 +369,11 @@ struct BlkCfg {
     static constexpr int NWT = 4 * P;                  // row stride of the weight tables
     static constexpr int NWB = 3 * P + 1;              // largest window
     static constexpr int NQB = 2 * RB + 4 * P - 2;     // direction-1 points of a block
-    // LDS strides chosen so that threads with consecutive (plane, j) indices hit consecutive
-    // banks: a stage-1 plane [v][q2][j3] and a slab plane [v][j2 j3] both start M banks
-    // after the previous plane (32 banks)
+    // the slab plane stride is padded so that threads with consecutive (plane, j) indices hit
+    // consecutive banks (a plane starts M banks after the previous one, 32 banks); the
+    // stage-1 planes are not, to keep the workgroup's LDS within a quarter of the CU's
     static constexpr int pad_to(int n) { return n + (((M - n) % 32) + 32) % 32; }
-    static constexpr int P1S = pad_to(2 * NWB * M);    // stage-1 plane stride
+    static constexpr int P1S = 2 * NWB * M;            // stage-1 plane stride
     static constexpr int PSL = pad_to(2 * MM);         // slab plane stride
     static constexpr int BUFN = NQB * (P1S > PSL ? P1S : PSL);
     static constexpr int W1S = 2 * M * NWT + 4;        // row stride of the staged direction-1 weights
@@ -428,7 +428,7 @@ __device__ inline void with_window(int cls, F&& f) {
 // Every contraction runs over the compile-time band of its window class; stiffness sums are
 // accumulated one product per fused multiply-add.
 template <int P, int WHICH, int RB>
-__global__ void __launch_bounds__(256, 3)
+__global__ void __launch_bounds__(256, 4)
 k_rows_block(DevRules R, const float* __restrict__ kappa, float* __restrict__ vm, float* __restrict__ vk) {
     using C = BlkCfg<P, RB>;
     constexpr int M = C::M, MM = C::MM, NT = C::NT, NWT = C::NWT, NWB = C::NWB, NQB = C::NQB;
