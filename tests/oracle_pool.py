@@ -92,3 +92,24 @@ def rows(wl, rows_active, hybrid=False):
         for j, res in enumerate(part):
             out[k + j * n] = res
     return out
+
+
+def _load_share(args):
+    wl, f_name, k, n = args
+    from oracle.assemble import Problem
+    from oracle.projection import Projection
+    import workloads
+    return Projection(Problem(wl)).load_vector(workloads.FUNCTIONS[f_name], share=(k, n))
+
+
+def load_vector(wl, f_name, n_active=None):
+    """The oracle's load vector b for workload wl and the named function of
+    workloads.FUNCTIONS, computed over worker processes."""
+    key = ("load", wl, f_name)
+    if key not in _CACHE:
+        n = _workers(max(1, (n_active or 64) // 32))
+        if n == 1:
+            _CACHE[key] = _load_share((wl, f_name, 0, 1))
+        else:
+            _CACHE[key] = np.sum(_map(_load_share, [(wl, f_name, k, n) for k in range(n)]), axis=0)
+    return _CACHE[key]

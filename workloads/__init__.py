@@ -164,3 +164,41 @@ def sample_indices(seed: int, n: int, k: int) -> np.ndarray:
     """k distinct sorted indices out of range(n)."""
     k = min(k, n)
     return np.sort(np.random.default_rng(seed).choice(n, size=k, replace=False))
+
+
+# ----------------------------------------------------------------------------------------
+# the paper's accuracy experiment (Section 3.1, Fig. 4)
+# ----------------------------------------------------------------------------------------
+PAPER_PLANE_POINT = (0.1, 0.2, 0.3)
+PAPER_PLANE_NORMAL = (0.5, -0.2, 0.9)
+
+
+def paper_plane(h: int, degree: int, octree_levels: int = 3) -> Workload:
+    """Background [-1,1]^3 with h elements per direction; Omega is the part of it below the
+    plane through PAPER_PLANE_POINT with normal PAPER_PLANE_NORMAL; mass matrix only
+    (kappa = 1)."""
+    r0 = sum(a * b for a, b in zip(PAPER_PLANE_NORMAL, PAPER_PLANE_POINT))
+    return Workload(f"paper_plane{h}_p{degree}", (h, h, h), degree,
+                    LevelSet(LS_PLANE, n=PAPER_PLANE_NORMAL, r0=r0), "one", which=MASS,
+                    lo=(-1.0, -1.0, -1.0), hi=(1.0, 1.0, 1.0), octree_levels=octree_levels)
+
+
+def target_f(xyz):
+    """The projected function f = sin(2xz) cos(3yz) at points xyz ((N,3) array or tensor)."""
+    if isinstance(xyz, torch.Tensor):
+        x, y, z = xyz[:, 0], xyz[:, 1], xyz[:, 2]
+        return torch.sin(2.0 * x * z) * torch.cos(3.0 * y * z)
+    xyz = np.asarray(xyz, dtype=np.float64)
+    x, y, z = xyz[:, 0], xyz[:, 1], xyz[:, 2]
+    return np.sin(2.0 * x * z) * np.cos(3.0 * y * z)
+
+
+def poly2_f(xyz):
+    """A polynomial of degree at most 2 in each variable (test input): it lies in every
+    spline space of degree p >= 2."""
+    xyz = np.asarray(xyz, dtype=np.float64)
+    x, y, z = xyz[:, 0], xyz[:, 1], xyz[:, 2]
+    return 0.5 + x * x * y - 3.0 * z * y * y + 0.25 * x * z
+
+
+FUNCTIONS = {"target_f": target_f, "poly2_f": poly2_f}
