@@ -12,14 +12,19 @@ well conditioned; the relative L2 error of the projection measures accuracy (Sec
     row, with f in place of the coefficient and no trial function.
   * Inner functions: active functions whose support contains at least one interior
     element; the other active functions are outer.
-  * Extension (after Hoellig's weighted extended B-splines): for an outer index j the array
-    l + {0..p}^3 of inner indices whose centre l + p/2 is closest to j in the Euclidean
-    norm, the first such l in lexicographic order on ties; the outer function enters the
-    basis through the inner functions of its array with the coefficients
-    e_{i,j} = prod_d L_{i_d - l_d}(j_d - l_d), L_a the Lagrange polynomials on the nodes
-    0..p (they reproduce polynomials of degree p in the index).  The extended basis is
-    B_i + sum_j e_{i,j} B_j over the outer j that use inner i; E (active x inner) maps
-    its coefficients to the active coefficients.
+  * Extension (extended B-splines after Hoellig, in the form for open knot vectors): the
+    root element of an outer function j is the interior element l nearest to it, measured
+    between the element's centre l + 1/2 and the centre j - p/2 + 1/2 of the support of B_j
+    in element units (so |l + p/2 - j|, Euclidean over the three directions), the first in
+    lexicographic order on ties.  The functions supported on l, l + {0..p}^3, are all inner;
+    they are B_j's array.  B_j enters the basis through them with the coefficients
+    e_{i,j} = lambda_j(P_i), P_i the polynomial piece of B_i on the root element and lambda_j
+    the dual functional of B_j (the B-spline coefficient of a polynomial w.r.t. B_j).  These
+    reproduce every polynomial of degree p in each variable: a polynomial's coefficients on
+    outer functions follow from those on inner ones.  On uniform knots they are Lagrange
+    extrapolation weights in the index, prod_d L_{i_d - l_d}(j_d - l_d).  The extended basis is
+    B_i + sum_j e_{i,j} B_j over the outer j that use inner i; E (active x inner) maps its
+    coefficients to the active coefficients.
   * System: E^T M E c = E^T b with M the mass matrix (kappa = 1); u = E c.
   * Error: ||u_h - f||^2 and ||f||^2 over Omega with the (p+1)^3 Gauss rule on interior
     elements and the octree points on cut elements (the points of the conventional
@@ -28,6 +33,8 @@ well conditioned; the relative L2 error of the projection measures accuracy (Sec
 from __future__ import annotations
 
 import itertools
+from fractions import Fraction
+from functools import lru_cache
 
 import numpy as np
 
@@ -35,14 +42,75 @@ from .domain import CUT, IN, OUT
 from .spline import bspline
 
 
-def lagrange_weights(p: int, x: float) -> np.ndarray:
-    """L_a(x), a = 0..p, Lagrange polynomials on the integer nodes 0..p."""
-    out = np.ones(p + 1)
-    for a in range(p + 1):
-        for m in range(p + 1):
-            if m != a:
-                out[a] *= (x - m) / (a - m)
-    return out
+def _knots(nel: int, p: int):
+    """Open uniform knots in element units (integers)."""
+    return [min(max(k - p, 0), nel) for k in range(nel + 2 * p + 1)]
+
+
+@lru_cache(maxsize=None)
+def _piece(nel: int, p: int, i: int, s: int):
+    """Coefficients (ascending powers of x, exact fractions) of the polynomial that equals
+    B_i on the knot span [t_s, t_{s+1}], element units: the Cox-de Boor recursion carried out
+    on polynomials, 0/0 terms dropped."""
+    t = _knots(nel, p)
+
+    def rec(i, k):
+        if k == 0:
+            return [Fraction(1 if i == s else 0)]
+        out = [Fraction(0)] * (k + 1)
+        d1 = t[i + k] - t[i]
+        if d1 != 0:                                   # (x - t_i) / d1 * B_{i,k-1}
+            for n, c in enumerate(rec(i, k - 1)):
+                out[n + 1] += c / d1
+                out[n] -= c * t[i] / d1
+        d2 = t[i + k + 1] - t[i + 1]
+        if d2 != 0:                                   # (t_{i+k+1} - x) / d2 * B_{i+1,k-1}
+            for n, c in enumerate(rec(i + 1, k - 1)):
+                out[n] += c * t[i + k + 1] / d2
+                out[n + 1] -= c / d2
+        return out
+
+    return tuple(rec(i, p))
+
+
+def _poly_at(c, x):
+    v = Fraction(0)
+    for a in reversed(c):
+        v = v * x + a
+    return v
+
+
+def _solve_exact(A, b):
+    """Gaussian elimination over fractions (A regular)."""
+    n = len(b)
+    M = [list(A[r]) + [b[r]] for r in range(n)]
+    for col in range(n):
+        piv = next(r for r in range(col, n) if M[r][col] != 0)
+        M[col], M[piv] = M[piv], M[col]
+        for r in range(n):
+            if r != col and M[r][col] != 0:
+                f = M[r][col] / M[col][col]
+                M[r] = [a - f * c for a, c in zip(M[r], M[col])]
+    return [M[r][n] / M[r][r] for r in range(n)]
+
+
+@lru_cache(maxsize=None)
+def _dual(nel: int, p: int, l: int, m: int, j: int) -> float:
+    P = _piece(nel, p, m, l + p)                      # element l is the span [t_{l+p}, t_{l+p+1}]
+    e = max(j - p, 0)                                 # an element in the support of B_j
+    xs = [e + Fraction(r + 1, p + 2) for r in range(p + 1)]
+    A = [[_poly_at(_piece(nel, p, e + k, e + p), x) for k in range(p + 1)] for x in xs]
+    sol = _solve_exact(A, [_poly_at(P, x) for x in xs])
+    return float(sol[j - e])
+
+
+def dual_coefficient(line, l: int, m: int, j: int) -> float:
+    """lambda_j(P): the coefficient of B_j in the B-spline expansion of P, the polynomial that
+    equals B_m on element l.  On an element e in the support of B_j only B_e..B_{e+p} are
+    nonzero, so the coefficient follows from interpolating P at p+1 points of e; everything is
+    exact rational arithmetic in element units (B-spline coefficients do not change under an
+    affine change of the parameter)."""
+    return _dual(line.nel, line.p, int(l), int(m), int(j))
 
 
 class Projection:
@@ -54,14 +122,16 @@ class Projection:
         self.p = problem.p
 
     # --- load vector ----------------------------------------------------------------------
-    def load_vector(self, f_fn, share=(0, 1)) -> np.ndarray:
-        """b (n_active); share = (k, n): only every n-th row from the k-th (the rest zero)."""
+    def load_vector(self, f_fn, share=(0, 1), rows=None) -> np.ndarray:
+        """b (n_active); share = (k, n): only every n-th row from the k-th; rows: only these
+        active rows (the other entries stay zero)."""
         dom = self.dom
         b = np.zeros(dom.n_active)
-        for r, k in enumerate(dom.active_lex):
-            if r % share[1] != share[0]:
+        todo = range(dom.n_active) if rows is None else sorted(set(int(r) for r in rows))
+        for c, r in enumerate(todo):
+            if c % share[1] != share[0]:
                 continue
-            I = dom.unlex(k)
+            I = dom.unlex(dom.active_lex[r])
             for part in self.P.row_parts(I):
                 if part["xyz"].shape[0]:
                     b[r] += float(np.sum(part["wM"] * f_fn(part["xyz"])))
@@ -78,26 +148,12 @@ class Projection:
         return out
 
     def arrays(self):
-        """{outer active index: base l (3-tuple)} of the extension arrays."""
+        """{outer active index: root element l (3-tuple)}."""
         dom, p = self.dom, self.p
-        nf = dom.nfun
         inner = self.inner_mask()
-        ind = np.zeros(nf, dtype=np.int64)
-        for r, k in enumerate(dom.active_lex):
-            if inner[r]:
-                ind[dom.unlex(k)] = 1
-        # blocks l + {0..p}^3 that are all inner: box sums of the indicator
-        S = np.zeros(tuple(n + 1 for n in nf), dtype=np.int64)
-        S[1:, 1:, 1:] = ind.cumsum(0).cumsum(1).cumsum(2)
-        L = [np.arange(n - p) for n in nf]
-        l0, l1, l2 = np.meshgrid(*L, indexing="ij")
-        tot = np.zeros(l0.shape, dtype=np.int64)
-        for bits in itertools.product((0, 1), repeat=3):
-            idx = tuple((l + (p + 1) * bt) for l, bt in zip((l0, l1, l2), bits))
-            tot += (-1) ** (3 - sum(bits)) * S[idx]
-        cand = np.argwhere(tot == (p + 1) ** 3)           # lexicographic order
-        if len(cand) == 0:
-            raise ValueError("no array of inner functions: the mesh is too coarse for the extension")
+        cand = np.argwhere(dom.ecls == IN)                  # lexicographic order
+        if len(cand) == 0 and not inner.all():
+            raise ValueError("no interior element: the mesh is too coarse for the extension")
         out = {}
         for r, k in enumerate(dom.active_lex):
             if inner[r]:
@@ -116,9 +172,10 @@ class Projection:
         lex2act = dom.lex_to_active
         E = np.zeros((dom.n_active, int(inner.sum())))
         E[np.nonzero(inner)[0], inner_idx[inner]] = 1.0
+        lines = self.P.lines
         for r, l in self.arrays().items():
             j = dom.unlex(dom.active_lex[r])
-            lam = [lagrange_weights(p, j[d] - l[d]) for d in range(3)]
+            lam = [[dual_coefficient(lines[d], l[d], l[d] + a, j[d]) for a in range(p + 1)] for d in range(3)]
             for a in itertools.product(range(p + 1), repeat=3):
                 i = tuple(l[d] + a[d] for d in range(3))
                 ri = lex2act[dom.lex(i)]

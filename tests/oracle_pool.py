@@ -95,21 +95,23 @@ def rows(wl, rows_active, hybrid=False):
 
 
 def _load_share(args):
-    wl, f_name, k, n = args
+    wl, f_name, k, n, rows = args
     from oracle.assemble import Problem
     from oracle.projection import Projection
     import workloads
-    return Projection(Problem(wl)).load_vector(workloads.FUNCTIONS[f_name], share=(k, n))
+    return Projection(Problem(wl)).load_vector(workloads.FUNCTIONS[f_name], share=(k, n), rows=rows)
 
 
-def load_vector(wl, f_name, n_active=None):
+def load_vector(wl, f_name, n_active=None, rows=None):
     """The oracle's load vector b for workload wl and the named function of
-    workloads.FUNCTIONS, computed over worker processes."""
-    key = ("load", wl, f_name)
+    workloads.FUNCTIONS, computed over worker processes (rows: only these active rows, the
+    other entries zero)."""
+    key = ("load", wl, f_name, None if rows is None else tuple(int(r) for r in rows))
     if key not in _CACHE:
-        n = _workers(max(1, (n_active or 64) // 32))
+        n_items = len(rows) if rows is not None else (n_active or 64)
+        n = _workers(max(1, n_items // 32))
         if n == 1:
-            _CACHE[key] = _load_share((wl, f_name, 0, 1))
+            _CACHE[key] = _load_share((wl, f_name, 0, 1, rows))
         else:
-            _CACHE[key] = np.sum(_map(_load_share, [(wl, f_name, k, n) for k in range(n)]), axis=0)
+            _CACHE[key] = np.sum(_map(_load_share, [(wl, f_name, k, n, rows) for k in range(n)]), axis=0)
     return _CACHE[key]

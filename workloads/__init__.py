@@ -196,7 +196,8 @@ def target_f(xyz):
 def poly2_f(xyz):
     """A polynomial of degree at most 2 in each variable (test input): it lies in every
     spline space of degree p >= 2."""
-    xyz = np.asarray(xyz, dtype=np.float64)
+    if not isinstance(xyz, torch.Tensor):
+        xyz = np.asarray(xyz, dtype=np.float64)
     x, y, z = xyz[:, 0], xyz[:, 1], xyz[:, 2]
     return 0.5 + x * x * y - 3.0 * z * y * y + 0.25 * x * z
 
