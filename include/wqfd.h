@@ -185,6 +185,67 @@ int gauss_assemble(const wq_rules* rules, int dtype, uint32_t which, const void*
  * in lexicographic Gauss order (first direction slowest). */
 int wq_gauss_coords(const wq_rules* rules, double* xyz, void* stream);
 
+/* ---------------------------------------------------------------------------------------
+ * L2 projection with extended B-splines (Section 3.1 test setting: mass matrix, projection
+ * of a target function f, extended B-splines for a well-conditioned system; Section 3.2:
+ * relative L2 error).  FP64 only.  The paper refers to other works for the extension; the
+ * library reads it as follows.  Inner functions: active functions with an interior element in
+ * their support; the others are outer.  The array of an outer function j is the block
+ * l + {0..p}^3 of inner functions whose centre l + p/2 is nearest to j (Euclidean; the
+ * lexicographically first l on ties); j enters the basis through its array with the
+ * coefficients prod_d L_{i_d - l_d}(j_d - l_d), L_a the Lagrange polynomials on the nodes
+ * 0..p.  E (n_active x n_inner) maps the coefficients of the extended basis to those of the
+ * active functions; the projection solves E^T M E c = E^T b and returns u = E c.
+ * --------------------------------------------------------------------------------------- */
+typedef struct wq_extension wq_extension;   /* opaque; owns its device buffers */
+
+/* Read-only views of an extension (device pointers owned by it, valid until
+ * wq_extension_free). */
+typedef struct {
+    int64_t n_inner;               /* inner functions (columns of E) */
+    int64_t n_outer;               /* outer functions */
+    int64_t nnz_e;                 /* entries of E */
+    const int32_t* inner_of_active;  /* (n_active) inner index of each active function, -1 if outer */
+    const int32_t* outer_rows;       /* (n_outer) active index of each outer function, ascending */
+    const int32_t* outer_base;       /* (n_outer, 3) base l of its array */
+    const int64_t* e_ptr;            /* (n_active+1) CSR row pointer of E */
+    const int32_t* e_col;            /* (nnz_e) inner indices, ascending per row */
+    const double* e_val;             /* (nnz_e) values */
+} wq_extension_info;
+
+/* Load vector of the projection: b_I = sum over the quadrature points x_q of row I (the WQ or
+ * DWQ box points, the element Gauss remainder, the octree points of cut elements) of the mass
+ * row's test weight W_I(q) times f(x_q).  Computed as the row sums of the mass matrix
+ * assembled with kappa = f, which is the same sum: the active functions of a row add up to one
+ * at each of its points.  f: (n_kappa) values at the slots (device); b: (n_active) output,
+ * OVERWRITTEN (device).  Uses nnz doubles of stream-ordered scratch.  Asynchronous. */
+int wq_load_vector(const wq_rules* rules, const double* f, double* b, void* stream);
+
+/* Builds the extension operator of a rules handle.  Synchronous.  Returns WQ_EINVAL when an
+ * outer function exists but no (p+1)^3 block of inner functions does (mesh too coarse). */
+int wq_extension_build(const wq_rules* rules, void* stream, wq_extension** out);
+int wq_extension_info_get(const wq_extension* ext, wq_extension_info* out);
+void wq_extension_free(wq_extension* ext);
+
+/* u = E c with E^T M E c = E^T b by conjugate gradients with the Jacobi preconditioner
+ * (diagonal of E^T M E), from c = 0, stopping when ||r|| <= tol ||E^T b|| (checked every 8
+ * iterations) or after max_iter iterations.  vals_mass: (nnz) mass values (FP64, kappa = 1 for
+ * the paper's projection), b: (n_active), u: (n_active) output; all device.  *iters and
+ * *relres (host, may be NULL) receive the iteration count and the final relative residual.
+ * ext must come from the same rules handle.  Synchronous (the host reads the residual);
+ * WQ_ESINGULAR on a non-positive diagonal entry or a breakdown.  Reductions use a fixed
+ * order: the result is the same on every run. */
+int wq_project(const wq_rules* rules, const wq_extension* ext, const double* vals_mass, const double* b,
+               double* u, double tol, int32_t max_iter, int32_t* iters, double* relres, void* stream);
+
+/* out[0] = sum w (u_h - f)^2 and out[1] = sum w f^2 over Omega: (p+1)^3 Gauss points on every
+ * interior element and the octree points on every cut element (the relative L2 error is
+ * sqrt(out[0] / out[1])).  u: (n_active) coefficients; f_gauss: f at the points of
+ * wq_gauss_coords (may be NULL iff n_gauss_elems = 0); f: (n_kappa) slot values of f (the
+ * octree slots are read); out: 2 doubles; all device.  Asynchronous. */
+int wq_l2_error(const wq_rules* rules, const double* u, const double* f_gauss, const double* f, double* out,
+                void* stream);
+
 void wq_rules_free(wq_rules* rules);
 const char* wq_last_error(void);
 

@@ -14,7 +14,9 @@ WQ_CUT_REMAINDER, WQ_CUT_OCTREE = 4, 8
 STATUS = {0: "WQ_OK", -1: "WQ_EINVAL", -2: "WQ_ENOMEM", -3: "WQ_EHIP", -4: "WQ_ESINGULAR", -5: "WQ_EUNSUPPORTED"}
 
 EXPORTS = ["wq_build_rules", "wq_rules_info_get", "wq_assemble_rows", "cut_assemble", "wq_assemble_adjoint",
-           "wq_rules_free", "wq_last_error", "gauss_assemble", "wq_gauss_coords", "cut_assemble_noalloc"]
+           "wq_rules_free", "wq_last_error", "gauss_assemble", "wq_gauss_coords", "cut_assemble_noalloc",
+           "wq_load_vector", "wq_extension_build", "wq_extension_info_get", "wq_extension_free", "wq_project",
+           "wq_l2_error"]
 
 
 class WqMesh(C.Structure):
@@ -39,6 +41,12 @@ class WqRulesInfo(C.Structure):
         ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p), ("active_to_lex", C.c_void_p),
         ("kappa_xyz", C.c_void_p), ("octree_w", C.c_void_p), ("block_elems", C.c_void_p),
         ("fun_class", C.c_void_p), ("elem_class", C.c_void_p), ("split", C.c_void_p), ("cut_rows", C.c_void_p)]
+
+
+class WqExtensionInfo(C.Structure):
+    _fields_ = [("n_inner", C.c_int64), ("n_outer", C.c_int64), ("nnz_e", C.c_int64),
+                ("inner_of_active", C.c_void_p), ("outer_rows", C.c_void_p), ("outer_base", C.c_void_p),
+                ("e_ptr", C.c_void_p), ("e_col", C.c_void_p), ("e_val", C.c_void_p)]
 
 
 class WqError(RuntimeError):
@@ -66,11 +74,20 @@ def load(path: str = LIB_PATH):
     lib.wq_assemble_adjoint.argtypes = [vp, i32, u32, vp, vp, vp, vp]
     lib.gauss_assemble.argtypes = [vp, i32, u32, vp, vp, vp, vp, vp]
     lib.wq_gauss_coords.argtypes = [vp, vp, vp]
+    lib.wq_load_vector.argtypes = [vp, vp, vp, vp]
+    lib.wq_extension_build.argtypes = [vp, vp, C.POINTER(vp)]
+    lib.wq_extension_info_get.argtypes = [vp, C.POINTER(WqExtensionInfo)]
+    lib.wq_extension_free.argtypes = [vp]
+    lib.wq_extension_free.restype = None
+    lib.wq_project.argtypes = [vp, vp, vp, vp, vp, C.c_double, C.c_int32, C.POINTER(C.c_int32),
+                               C.POINTER(C.c_double), vp]
+    lib.wq_l2_error.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.wq_rules_free.argtypes = [vp]
     lib.wq_rules_free.restype = None
     lib.wq_last_error.restype = C.c_char_p
     for name in ("wq_build_rules", "wq_rules_info_get", "wq_assemble_rows", "cut_assemble", "wq_assemble_adjoint",
-                 "cut_assemble_noalloc", "gauss_assemble", "wq_gauss_coords"):
+                 "cut_assemble_noalloc", "gauss_assemble", "wq_gauss_coords", "wq_load_vector", "wq_extension_build",
+                 "wq_extension_info_get", "wq_project", "wq_l2_error"):
         getattr(lib, name).restype = i32
     _lib = lib
     return lib

@@ -81,9 +81,9 @@ class Rules:
             self._h = None
 
     # --- read-only views (copied into torch tensors) ---------------------------------
-    def _view(self, field, n, dtype, shape=None):
+    def _view(self, field, n, dtype, shape=None, info=None):
         out = torch.empty(n, dtype=dtype, device=self.device)
-        ptr = getattr(self._info, field)
+        ptr = getattr(self._info if info is None else info, field)
         if n > 0:
             hip = L.hip_runtime()
             with torch.cuda.device(self.device):
@@ -196,6 +196,86 @@ class Rules:
         L.check(L.load().wq_assemble_adjoint(self._h, _DT[ref.dtype], which, _ptr(g_mass), _ptr(g_stiff), _ptr(dk),
                                              C.c_void_p(_stream_handle(self.device))))
         return dk
+
+
+    # --- L2 projection (FP64) --------------------------------------------------------------
+    def load_vector(self, f):
+        """b_I = sum_q W_I(q) f(x_q) over the mass row's points; f: (n_kappa) float64 slot values."""
+        _need(f, self.n_kappa, torch.float64, self.device, "f")
+        b = torch.empty(self.n_active, dtype=torch.float64, device=self.device)
+        L.check(L.load().wq_load_vector(self._h, _ptr(f), _ptr(b), C.c_void_p(_stream_handle(self.device))))
+        return b
+
+    def extension(self):
+        """The extended B-spline operator of this mesh and domain."""
+        return Extension(self)
+
+    def project(self, ext, vals_mass, b, tol=1e-12, max_iter=5000):
+        """u = E c with E^T M E c = E^T b (Jacobi PCG). Returns (u, iterations, relative residual)."""
+        _need(vals_mass, self.nnz, torch.float64, self.device, "vals_mass")
+        _need(b, self.n_active, torch.float64, self.device, "b")
+        u = torch.empty(self.n_active, dtype=torch.float64, device=self.device)
+        it, rel = C.c_int32(0), C.c_double(0.0)
+        L.check(L.load().wq_project(self._h, ext._h, _ptr(vals_mass), _ptr(b), _ptr(u), float(tol), int(max_iter),
+                                    C.byref(it), C.byref(rel), C.c_void_p(_stream_handle(self.device))))
+        return u, int(it.value), float(rel.value)
+
+    def l2_error(self, u, f_gauss, f):
+        """(sum w (u_h - f)^2, sum w f^2) over Omega: Gauss points of interior elements (f_gauss at
+        gauss_coords()) and octree points of cut elements (f: slot values)."""
+        _need(u, self.n_active, torch.float64, self.device, "u")
+        _need(f, self.n_kappa, torch.float64, self.device, "f")
+        if self.n_gauss_elems > 0:
+            _need(f_gauss, self.n_gauss_elems * (self.degree + 1) ** 3, torch.float64, self.device, "f_gauss")
+        out = torch.empty(2, dtype=torch.float64, device=self.device)
+        L.check(L.load().wq_l2_error(self._h, _ptr(u), _ptr(f_gauss), _ptr(f), _ptr(out),
+                                     C.c_void_p(_stream_handle(self.device))))
+        return float(out[0]), float(out[1])
+
+
+class Extension:
+    """Extended B-spline operator E of a Rules handle (device buffers owned by the library)."""
+
+    def __init__(self, rules: Rules):
+        lib = L.load()
+        h = C.c_void_p()
+        with torch.cuda.device(rules.device):
+            L.check(lib.wq_extension_build(rules._h, C.c_void_p(_stream_handle(rules.device)), C.byref(h)))
+        self._h = h
+        self.rules = rules          # keeps the rules handle alive
+        info = L.WqExtensionInfo()
+        L.check(lib.wq_extension_info_get(h, C.byref(info)))
+        self._info = info
+        self.n_inner, self.n_outer, self.nnz_e = int(info.n_inner), int(info.n_outer), int(info.nnz_e)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if sys.is_finalizing():
+            return
+        if h is not None and h.value:
+            L.load().wq_extension_free(h)
+            self._h = None
+
+    def _view(self, field, n, dtype, shape=None):
+        return Rules._view(self.rules, field, n, dtype, shape, info=self._info)
+
+    def inner_of_active(self):
+        return self._view("inner_of_active", self.rules.n_active, torch.int32)
+
+    def outer_rows(self):
+        return self._view("outer_rows", self.n_outer, torch.int32)
+
+    def outer_base(self):
+        return self._view("outer_base", 3 * self.n_outer, torch.int32, (self.n_outer, 3))
+
+    def e_ptr(self):
+        return self._view("e_ptr", self.rules.n_active + 1, torch.int64)
+
+    def e_col(self):
+        return self._view("e_col", self.nnz_e, torch.int32)
+
+    def e_val(self):
+        return self._view("e_val", self.nnz_e, torch.float64)
 
 
 class WQAssemble(torch.autograd.Function):

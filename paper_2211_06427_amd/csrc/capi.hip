@@ -222,6 +222,46 @@ int gauss_assemble(const wq_rules* r, int dtype, uint32_t which, const void* kap
     return check_launch("gauss_assemble");
 }
 
+int wq_load_vector(const wq_rules* r, const double* f, double* b, void* stream) {
+    if (!r || !f || !b) return wq_set_error(WQ_EINVAL, "wq_load_vector: NULL argument");
+    int st = projection_load_vector(r, f, b, (hipStream_t)stream);
+    if (st) return st;
+    return check_launch("wq_load_vector");
+}
+
+int wq_extension_build(const wq_rules* r, void* stream, wq_extension** out) {
+    if (!r || !out) return wq_set_error(WQ_EINVAL, "wq_extension_build: NULL argument");
+    *out = nullptr;
+    return projection_build_extension(r, (hipStream_t)stream, out);
+}
+
+int wq_extension_info_get(const wq_extension* x, wq_extension_info* out) {
+    if (!x || !out) return wq_set_error(WQ_EINVAL, "wq_extension_info_get: NULL argument");
+    return projection_info(x, out);
+}
+
+void wq_extension_free(wq_extension* x) {
+    if (!x) return;
+    (void)hipDeviceSynchronize();
+    projection_free(x);
+}
+
+int wq_project(const wq_rules* r, const wq_extension* x, const double* vm, const double* b, double* u, double tol,
+               int32_t max_iter, int32_t* iters, double* relres, void* stream) {
+    if (!r || !x || !vm || !b || !u) return wq_set_error(WQ_EINVAL, "wq_project: NULL argument");
+    if (projection_owner(x) != r) return wq_set_error(WQ_EINVAL, "wq_project: the extension belongs to another rules handle");
+    if (!(tol > 0.0) || max_iter < 1) return wq_set_error(WQ_EINVAL, "wq_project: need tol > 0 and max_iter >= 1");
+    return projection_solve(r, x, vm, b, u, tol, max_iter, iters, relres, (hipStream_t)stream);
+}
+
+int wq_l2_error(const wq_rules* r, const double* u, const double* fg, const double* f, double* out, void* stream) {
+    if (!r || !u || !f || !out) return wq_set_error(WQ_EINVAL, "wq_l2_error: NULL argument");
+    if (!fg && r->n_int_elems > 0) return wq_set_error(WQ_EINVAL, "wq_l2_error: f_gauss is NULL");
+    int st = projection_error(r, u, fg, f, out, (hipStream_t)stream);
+    if (st) return st;
+    return check_launch("wq_l2_error");
+}
+
 void wq_rules_free(wq_rules* r) {
     if (!r) return;
     (void)hipDeviceSynchronize();

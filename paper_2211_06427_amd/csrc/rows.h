@@ -15,3 +15,14 @@ int launch_adjoint(const wq_rules* H, uint32_t which, const T* gm, const T* gk, 
 template <typename T>
 int launch_gauss(const wq_rules* H, uint32_t which, const T* kg, const T* kappa, T* vm, T* vk, hipStream_t s);
 int launch_gauss_coords(const wq_rules* H, double* xyz, hipStream_t s);
+
+// L2 projection (projection.hip)
+int projection_load_vector(const wq_rules* H, const double* f, double* b, hipStream_t s);
+int projection_build_extension(const wq_rules* H, hipStream_t s, wq_extension** out);
+int projection_info(const wq_extension* X, wq_extension_info* out);
+void projection_free(wq_extension* X);
+const wq_rules* projection_owner(const wq_extension* X);
+int projection_solve(const wq_rules* H, const wq_extension* X, const double* M, const double* b, double* u,
+                     double tol, int32_t max_iter, int32_t* iters, double* relres, hipStream_t s);
+int projection_error(const wq_rules* H, const double* u, const double* fg, const double* f, double* out,
+                     hipStream_t s);
