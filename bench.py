@@ -53,6 +53,12 @@ def parse():
     ap.add_argument("--cpu-rows", type=int, default=128, help="rows in the oracle's timed sample")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device copy (calibrates the HBM byte counters)")
+    ap.add_argument("--paper-sweep", action="store_true",
+                    help="the paper's accuracy and timing experiment instead of the benchmark: L2 projection of "
+                         "sin(2xz)cos(3yz) on [-1,1]^3 below the inclined plane, schemes Ref / Hybrid / DWQ, one JSON "
+                         "line per (h, p)")
+    ap.add_argument("--sweep-h", default="4,8,16,32,64")
+    ap.add_argument("--sweep-p", default="2,3,4,5,6")
     return ap.parse_args()
 
 
@@ -186,10 +192,99 @@ def cpu_baseline(wl, nrows):
                       f"(one core: {serial:.1f} s); rule setup excluded"}
 
 
+def paper_sweep(args):
+    """Section 3.1 / 3.2: mass matrix of the cut cube [-1,1]^3 (kappa = 1, FP64), L2 projection of
+    f = sin(2xz) cos(3yz) with extended B-splines, relative L2 error, for the three schemes:
+    Ref (element-by-element Gauss), Hybrid Gauss and DWQ.  Times are HIP-event means over
+    repeated calls; the Ref load vector is the row sums of its mass matrix with kappa = f."""
+    import torch
+
+    import workloads as W
+    from paper_2211_06427_amd import Rules
+    from paper_2211_06427_amd._lib import WQ_CUT_OCTREE, WQ_CUT_REMAINDER, WQ_MASS
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    f64 = torch.float64
+    for p in [int(v) for v in args.sweep_p.split(",")]:
+        for h in [int(v) for v in args.sweep_h.split(",")]:
+            wl = W.paper_plane(h, p)
+            rec = {"h": h, "p": p}
+            nrep = 5 if h <= 32 else 2
+            ref_rules = None
+            for scheme, hyb in (("dwq", False), ("hybrid", True)):
+                t0 = time.perf_counter()
+                R = Rules.from_workload(wl, hybrid_gauss=hyb)
+                torch.cuda.synchronize()
+                build_ms = (time.perf_counter() - t0) * 1e3
+                one = torch.ones(R.n_kappa, dtype=f64, device=dev)
+                f = W.target_f(R.kappa_xyz())
+                vm = torch.empty(R.nnz, dtype=f64, device=dev)
+                one32, vm32 = one.float(), torch.empty(R.nnz, dtype=torch.float32, device=dev)
+
+                def mass(o=one, v=vm):
+                    R.assemble_rows(o, v, None, which=WQ_MASS)
+                    R.cut_assemble(o, v, None, which=WQ_MASS)
+
+                mass()
+                r = {"build_rules_ms": build_ms, "n_active": R.n_active, "nnz": R.nnz,
+                     "rows_ms": timed(lambda: R.assemble_rows(one, vm, None, which=WQ_MASS), nrep, torch),
+                     "remainder_ms": timed(lambda: R.cut_assemble(one, vm, None, which=WQ_MASS | WQ_CUT_REMAINDER),
+                                           nrep, torch),
+                     "octree_ms": timed(lambda: R.cut_assemble(one, vm, None, which=WQ_MASS | WQ_CUT_OCTREE),
+                                        nrep, torch),
+                     "mass_ms": timed(mass, nrep, torch),
+                     "mass_f32_ms": timed(lambda: mass(one32, vm32), nrep, torch)}
+                mass()
+                t0 = time.perf_counter()
+                b = R.load_vector(f)
+                torch.cuda.synchronize()
+                r["load_vector_ms"] = (time.perf_counter() - t0) * 1e3
+                t0 = time.perf_counter()
+                ext = R.extension()
+                r["extension_ms"] = (time.perf_counter() - t0) * 1e3
+                t0 = time.perf_counter()
+                u, it, rel = R.project(ext, vm, b, tol=1e-12, max_iter=60000)
+                r["solve_ms"] = (time.perf_counter() - t0) * 1e3
+                fg = W.target_f(R.gauss_coords())
+                e2, n2 = R.l2_error(u, fg, f)
+                r.update({"cg_iterations": it, "cg_relres": rel, "rel_l2_error": math.sqrt(e2 / n2),
+                          "n_inner": ext.n_inner, "n_outer": ext.n_outer})
+                rec[scheme] = r
+                print(f"# h={h} p={p} {scheme}: err {r['rel_l2_error']:.3e} mass {r['mass_ms']:.3f} ms "
+                      f"cg {it}", file=sys.stderr, flush=True)
+                if not hyb:
+                    ref_rules, ref_ext, ref_f, ref_fg = R, ext, f, fg
+                else:
+                    del R
+                del ext
+            # Ref: conventional element-by-element Gauss on the same pattern, slots and octree
+            R = ref_rules
+            one = torch.ones(R.n_kappa, dtype=f64, device=dev)
+            og = torch.ones(R.n_gauss_elems * (p + 1) ** 3, dtype=f64, device=dev)
+            ms = timed(lambda: R.gauss_assemble(og, one, which=WQ_MASS), max(2, nrep // 2), torch)
+            ms32 = timed(lambda: R.gauss_assemble(og.float(), one.float(), which=WQ_MASS), max(2, nrep // 2), torch)
+            M, _ = R.gauss_assemble(og, one, which=WQ_MASS)
+            Mf, _ = R.gauss_assemble(ref_fg, ref_f, which=WQ_MASS)
+            rp = R.row_ptr()
+            rows = torch.repeat_interleave(torch.arange(R.n_active, device=dev), torch.diff(rp))
+            b = torch.zeros(R.n_active, dtype=f64, device=dev).index_add_(0, rows, Mf)
+            u, it, rel = R.project(ref_ext, M, b, tol=1e-12, max_iter=60000)
+            e2, n2 = R.l2_error(u, ref_fg, ref_f)
+            rec["ref"] = {"mass_ms": ms, "mass_f32_ms": ms32, "cg_iterations": it, "cg_relres": rel,
+                          "rel_l2_error": math.sqrt(e2 / n2)}
+            print(f"# h={h} p={p} ref: err {rec['ref']['rel_l2_error']:.3e} mass {ms:.3f} ms", file=sys.stderr,
+                  flush=True)
+            del R, ref_rules, ref_ext, M, Mf
+            print(json.dumps(rec), flush=True)
+
+
 def main():
     args = parse()
     if args.copy_probe:
         copy_probe()
+        return
+    if args.paper_sweep:
+        paper_sweep(args)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the library assembles on a "
@@ -259,7 +354,7 @@ def main():
     nrep = max(3, min(args.steps, 10))
     parts = {}
     kg = None
-    if wl.degree <= 4 and wl.octree_levels <= 3:
+    if wl.octree_levels <= 3:
         kg64 = W.kappa_at(wl, R.gauss_coords())
         kg = {"f64": kg64, "f32": kg64.float()}
     for k in ("f64", "f32"):
@@ -273,8 +368,8 @@ def main():
         }
         g = torch.ones(R.nnz, dtype=dt[k], device=dev)
         parts[k]["adjoint_ms"] = timed(lambda: R.adjoint(g, g), nrep, torch)
-        # conventional element-by-element Gauss assembly of the same matrices (built for p <= 4
-        # and octrees of depth <= 3 only)
+        # conventional element-by-element Gauss assembly of the same matrices (octrees of depth
+        # <= 3 only)
         if kg is not None:
             parts[k]["gauss_ms"] = timed(lambda: R.gauss_assemble(kg[k], kap[k]), max(2, nrep // 3), torch)
     step("f64")

@@ -175,8 +175,8 @@ int wq_assemble_adjoint(const wq_rules* rules, int dtype, uint32_t which, const 
  * (p+1)^3 Gauss points on every interior element and the octree points on every cut element,
  * local matrices added into the same pattern.  OVERWRITES all nnz entries of each requested
  * matrix.  kappa_gauss: (n_gauss_elems * (p+1)^3) values at the points wq_gauss_coords lists;
- * kappa: the slot vector of the other calls (its octree slots are read).  p <= 4 and octree
- * depth <= 3 only (WQ_EUNSUPPORTED otherwise).  Uses atomics: summation order varies. */
+ * kappa: the slot vector of the other calls (its octree slots are read).  Octree depth <= 3
+ * only (WQ_EUNSUPPORTED otherwise).  Uses atomics: summation order varies. */
 int gauss_assemble(const wq_rules* rules, int dtype, uint32_t which, const void* kappa_gauss, const void* kappa,
                    void* vals_mass, void* vals_stiff, void* stream);
 

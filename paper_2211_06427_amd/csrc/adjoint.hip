@@ -36,13 +36,17 @@ __global__ void k_fill(T* p, int64_t n, T v) {
 }
 
 // ----------------------------------------------------------------------------------------
-// interior rows (line blocks), transposed stages 3 -> 2 -> 1
+// interior rows (line blocks), transposed stages 3 -> 2 -> 1.  Stage 3^T: the block's q1
+// slab is split into NG contiguous ranges, one per thread group; a group visits every row
+// whose window meets its range, one thread per (j2, j3) column, and adds only the q1 of its
+// range, so every slab entry has a single owner and is updated without atomics.  Stage 1^T
+// adds into dkappa with atomics (grid points are shared with neighbouring line blocks).
 // ----------------------------------------------------------------------------------------
 template <typename T, int P, int WHICH, int RB>
 struct AdjCfg {
     static constexpr int M = 2 * P + 1, NW = 4 * P, MM = M * M;
-    static constexpr int GT = ((MM + 63) / 64) * 64;       // threads per stage-3 row group
-    static constexpr int NG = GT >= 256 ? 1 : 256 / GT;    // row groups
+    static constexpr int GT = ((MM + 63) / 64) * 64;       // threads per stage-3 group
+    static constexpr int NG = GT >= 256 ? 1 : 256 / GT;    // groups, each owning a q1 range
     static constexpr int NT = NG * GT;                     // threads per block: whole groups only
     static constexpr int NQ1 = 2 * RB + 4 * P;
     static constexpr int QC = P <= 4 ? 8 : 4;             // q1 chunk of the stage-2/1 pass
@@ -85,12 +89,15 @@ k_adj_interior(DevRules R, const T* __restrict__ gm, const T* __restrict__ gk, T
     const int m2 = hi2 - lo2 + 1, m3 = hi3 - lo3 + 1;
     const bool live = c < MM && jj2 >= lo2 && jj2 <= hi2 && jj3 >= lo3 && jj3 <= hi3;
     const int64_t nl = (int64_t)R.nfun[1] * R.nfun[2];
-    for (int r = grp; r < nrows; r += C::NG) {
+    const int qpart = (nq1 + C::NG - 1) / C::NG;
+    const int qlo_g = grp * qpart, qhi_g = min(nq1, qlo_g + qpart);     // this group's q1 range
+    for (int r = 0; r < nrows; ++r) {
         const int i1 = uni(i1s + r);
-        const int ra = uni(R.lex2act[(int64_t)i1 * nl + (int64_t)i2 * R.nfun[2] + i3]);
-        const int64_t base = R.row_ptr[ra];
         const int off = uni(R.xs[0][i1] - qbase);
         const int nw1 = uni(R.nwin[0][i1]);
+        if (off + nw1 <= qlo_g || off >= qhi_g) continue;
+        const int ra = uni(R.lex2act[(int64_t)i1 * nl + (int64_t)i2 * R.nfun[2] + i3]);
+        const int64_t base = R.row_ptr[ra];
         const int lo1 = i1 - p < 0 ? p - i1 : 0, hi1 = i1 + p > R.nfun[0] - 1 ? R.nfun[0] - 1 - i1 + p : 2 * p;
         T g0[M], g1[M];
 #pragma unroll
@@ -107,6 +114,7 @@ k_adj_interior(DevRules R, const T* __restrict__ gm, const T* __restrict__ gk, T
 #pragma unroll
         for (int q = 0; q < NW; ++q) {
             if (q >= nw1) break;
+            if (off + q < qlo_g || off + q >= qhi_g) continue;
             T a0 = 0, a1 = 0;
 #pragma unroll
             for (int jj1 = 0; jj1 < M; ++jj1) {
@@ -114,61 +122,49 @@ k_adj_interior(DevRules R, const T* __restrict__ gm, const T* __restrict__ gk, T
                 if (C::MASS) a0 += w0 * g0[jj1];
                 if (C::STIFF) { a0 += w11[jj1 * NW + q] * g1[jj1]; a1 += w0 * g1[jj1]; }
             }
-            if (live) {
-                atomicAdd(&s_a0[(off + q) * MM + c], a0);
-                if (C::STIFF) atomicAdd(&s_a1[(off + q) * MM + c], a1);
+            if (live) {                             // column c has one owner: no atomics
+                s_a0[(off + q) * MM + c] += a0;
+                if (C::STIFF) s_a1[(off + q) * MM + c] += a1;
             }
         }
     }
     __syncthreads();
-    // stages 2^T and 1^T by chunks of q1
+    // stages 2^T and 1^T by chunks of q1, one thread per output entry
     for (int q1c = 0; q1c < nq1; q1c += QC) {
         const int nqc = nq1 - q1c < QC ? nq1 - q1c : QC;
-        for (int it = threadIdx.x; it < nqc * M; it += C::NT) {
-            const int ql = it / M, j3 = it % M;
-            const int q1 = q1c + ql;
-            T b0[NW], b1[NW];
-#pragma unroll
-            for (int q2 = 0; q2 < NW; ++q2) { b0[q2] = 0; b1[q2] = 0; }
+        // B_v[ql][q2][j3] = sum_j2 W2 A: items (ql, q2, j3)
+        for (int it = threadIdx.x; it < nqc * nw2 * M; it += C::NT) {
+            const int ql = it / (nw2 * M), q2 = (it / M) % nw2, j3 = it % M;
+            const T* a0p = s_a0 + (q1c + ql) * MM + j3;
+            const T* a1p = s_a1 + (C::STIFF ? (q1c + ql) * MM + j3 : 0);
+            T b0 = 0, b1 = 0;
 #pragma unroll
             for (int j2 = 0; j2 < M; ++j2) {
-                const T a0 = s_a0[q1 * MM + j2 * M + j3];
-                const T a1 = C::STIFF ? s_a1[q1 * MM + j2 * M + j3] : (T)0;
-#pragma unroll
-                for (int q2 = 0; q2 < NW; ++q2) {
-                    if (q2 < nw2) {
-                        b0[q2] += s_w2[j2 * NW + q2] * a0;
-                        if (C::STIFF) { b0[q2] += s_w2[(M + j2) * NW + q2] * a1; b1[q2] += s_w2[j2 * NW + q2] * a1; }
-                    }
+                const T a0 = a0p[j2 * M];
+                const T w0 = s_w2[j2 * NW + q2];
+                b0 += w0 * a0;
+                if (C::STIFF) {
+                    const T a1 = a1p[j2 * M];
+                    b0 += s_w2[(M + j2) * NW + q2] * a1;
+                    b1 += w0 * a1;
                 }
             }
-#pragma unroll
-            for (int q2 = 0; q2 < NW; ++q2) {
-                if (q2 < nw2) {
-                    s_b[0][(ql * NW + q2) * M + j3] = b0[q2];
-                    if (C::STIFF) s_b[1][(ql * NW + q2) * M + j3] = b1[q2];
-                }
-            }
+            s_b[0][(ql * NW + q2) * M + j3] = b0;
+            if (C::STIFF) s_b[1][(ql * NW + q2) * M + j3] = b1;
         }
         __syncthreads();
-        for (int it = threadIdx.x; it < nqc * nw2; it += C::NT) {
-            const int ql = it / nw2, q2 = it % nw2;
-            T bb0[M], bb1[M];
+        // dkappa[q1][q2][q3] += sum_j3 W3 B: items (ql, q2, q3), consecutive threads along q3
+        for (int it = threadIdx.x; it < nqc * nw2 * nw3; it += C::NT) {
+            const int ql = it / (nw2 * nw3), q2 = (it / nw3) % nw2, q3 = it % nw3;
+            const T* b0p = s_b[0] + (ql * NW + q2) * M;
+            const T* b1p = s_b[1] + (ql * NW + q2) * M;
+            T v = 0;
 #pragma unroll
             for (int j3 = 0; j3 < M; ++j3) {
-                bb0[j3] = s_b[0][(ql * NW + q2) * M + j3];
-                bb1[j3] = C::STIFF ? s_b[1][(ql * NW + q2) * M + j3] : (T)0;
+                v += s_w3[j3 * NW + q3] * b0p[j3];
+                if (C::STIFF) v += s_w3[(M + j3) * NW + q3] * b1p[j3];
             }
-            T* dst = dk + ((int64_t)(qbase + q1c + ql) * nx2 + xs2 + q2) * nx3 + xs3;
-            for (int q3 = 0; q3 < nw3; ++q3) {
-                T v = 0;
-#pragma unroll
-                for (int j3 = 0; j3 < M; ++j3) {
-                    v += s_w3[j3 * NW + q3] * bb0[j3];
-                    if (C::STIFF) v += s_w3[(M + j3) * NW + q3] * bb1[j3];
-                }
-                atomicAdd(&dst[q3], v);
-            }
+            atomicAdd(&dk[((int64_t)(qbase + q1c + ql) * nx2 + xs2 + q2) * nx3 + xs3 + q3], v);
         }
         __syncthreads();
     }

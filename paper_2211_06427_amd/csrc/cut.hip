@@ -723,9 +723,11 @@ k_cut_local(DevRules R, const int32_t* __restrict__ elems, const T* __restrict__
 // a3, a2), so that the LDS block of one workgroup is P1 local rows (a1) instead of P1^2:
 // direction 3 is contracted for every a2 (recomputed per workgroup), direction 2 for this
 // a2 only, direction 1 on matrix cores with rows (a1 b1) and columns (b2 b3).
-template <typename T, int P, int WHICH>
+// SCATTER = true: add the rows into the CSR values with atomics (the conventional assembly).
+template <typename T, int P, int WHICH, bool SCATTER = false>
 __global__ void __launch_bounds__(256)
-k_cut_local_a2(DevRules R, const int32_t* __restrict__ elems, const T* __restrict__ mom, T* __restrict__ loc, int ce0) {
+k_cut_local_a2(DevRules R, const int32_t* __restrict__ elems, const T* __restrict__ mom, T* __restrict__ loc, int ce0,
+               const int32_t* __restrict__ act2cut = nullptr, T* __restrict__ vm = nullptr, T* __restrict__ vk = nullptr) {
     using C = MomCfg<P>;
     using MF = MfmaOp<T>;
     using v4 = typename MF::v4;
@@ -838,7 +840,7 @@ k_cut_local_a2(DevRules R, const int32_t* __restrict__ elems, const T* __restric
 #pragma unroll
     for (int v = 0; v < 2; ++v) {
         if ((v == 0 && !MASS) || (v == 1 && !STIFF)) continue;
-        T* out = loc + ((int64_t)(ce * P1 + a3) * 2 + v) * NBLK;
+        T* out = SCATTER ? nullptr : loc + ((int64_t)(ce * P1 + a3) * 2 + v) * NBLK;
         __syncthreads();                            // s_u is free (contractions / previous matrix done)
 #pragma unroll
         for (int ti = 0; ti < NTW; ++ti) {
@@ -857,9 +859,32 @@ k_cut_local_a2(DevRules R, const int32_t* __restrict__ elems, const T* __restric
                 }
         }
         __syncthreads();
-        for (int i = t; i < NROW; i += NT) {
-            const int a1 = i / NP, b = i % NP;
-            out[(int64_t)(a1 * P1 + a2) * NP + b] = s_blk[i];
+        if (!SCATTER) {
+            for (int i = t; i < NROW; i += NT) {
+                const int a1 = i / NP, b = i % NP;
+                out[(int64_t)(a1 * P1 + a2) * NP + b] = s_blk[i];
+            }
+        } else {
+            T* dst = v == 0 ? vm : vk;
+            for (int i = t; i < NROW; i += NT) {
+                const int a1 = i / NP, b = i % NP;
+                const int b1 = b / P2, b2 = (b / P1) % P1, b3 = b % P1;
+                const int I1 = e[0] + a1, I2 = e[1] + a2, I3 = e[2] + a3;
+                const int ra = R.lex2act[((int64_t)I1 * R.nfun[1] + I2) * R.nfun[2] + I3];
+                const int cr = act2cut[ra];
+                const int jj1 = b1 - a1 + P, jj2 = b2 - a2 + P, jj3 = b3 - a3 + P;
+                int o;
+                if (cr >= 0) {
+                    o = R.pos_map[(int64_t)cr * (2 * P + 1) * (2 * P + 1) * (2 * P + 1) +
+                                  (jj1 * (2 * P + 1) + jj2) * (2 * P + 1) + jj3];
+                } else {                            // interior row: its full window is stored
+                    const int lo1 = I1 - P < 0 ? P - I1 : 0;
+                    const int lo2 = I2 - P < 0 ? P - I2 : 0, hi2 = I2 + P > R.nfun[1] - 1 ? R.nfun[1] - 1 - I2 + P : 2 * P;
+                    const int lo3 = I3 - P < 0 ? P - I3 : 0, hi3 = I3 + P > R.nfun[2] - 1 ? R.nfun[2] - 1 - I3 + P : 2 * P;
+                    o = ((jj1 - lo1) * (hi2 - lo2 + 1) + (jj2 - lo2)) * (hi3 - lo3 + 1) + (jj3 - lo3);
+                }
+                if (o >= 0) atomicAdd(&dst[R.row_ptr[ra] + o], s_blk[i]);
+            }
         }
     }
 }
@@ -977,9 +1002,9 @@ k_gauss_moments(DevRules R, const T* __restrict__ kg, const double* __restrict__
     const int64_t el = blockIdx.x;
     const int t = threadIdx.x;
     const double vol = R.h[0] * R.h[1] * R.h[2] / 8.0;
-    if (t < NP) {
-        const int g1 = t / P2, g2 = (t / P1) % P1, g3 = t % P1;
-        s_wk[t] = (T)(gw[g1] * gw[g2] * gw[g3] * vol) * kg[el * NP + t];
+    for (int i = t; i < NP; i += NT) {
+        const int g1 = i / P2, g2 = (i / P1) % P1, g3 = i % P1;
+        s_wk[i] = (T)(gw[g1] * gw[g2] * gw[g3] * vol) * kg[el * NP + i];
     }
     if (t < NK * P1) s_b[t] = bern_i<T>(R)[t];
     __syncthreads();
@@ -1026,16 +1051,22 @@ static int launch_gauss_p(const wq_rules* H, const T* kg, const T* kappa, T* vm,
     T* mom = nullptr;
     hipError_t err = H->scratch_alloc((void**)&mom, sizeof(T) * (size_t)ne * C::NK3, s);
     if (err != hipSuccess) return wq_set_error(WQ_ENOMEM, "gauss_assemble: scratch allocation failed: %s", hipGetErrorString(err));
+    auto scatter = [&](const int32_t* elems, int64_t n, const T* m) {
+        if constexpr (P <= 4)
+            hipLaunchKernelGGL((k_cut_local<T, P, WHICH, true>), dim3((unsigned)(n * (P + 1))), dim3(256), 0, s, R, elems,
+                               m, (T*)nullptr, H->act2cut, vm, vk, 0);
+        else
+            hipLaunchKernelGGL((k_cut_local_a2<T, P, WHICH, true>), dim3((unsigned)(n * (P + 1) * (P + 1))), dim3(256), 0,
+                               s, R, elems, m, (T*)nullptr, 0, H->act2cut, vm, vk);
+    };
     if (ni > 0) {
         hipLaunchKernelGGL((k_gauss_moments<T, P>), dim3((unsigned)ni), dim3(256), 0, s, R, kg, (const double*)H->gw, mom);
-        hipLaunchKernelGGL((k_cut_local<T, P, WHICH, true>), dim3((unsigned)(ni * (P + 1))), dim3(256), 0, s, R, H->int_elems,
-                           (const T*)mom, (T*)nullptr, H->act2cut, vm, vk, 0);
+        scatter(H->int_elems, ni, (const T*)mom);
     }
     if (nc > 0) {
         T* mc = mom + (size_t)ni * C::NK3;
         hipLaunchKernelGGL((k_cut_moments<T, P>), dim3((unsigned)nc), dim3(256), 0, s, R, kappa, mc, 0);
-        hipLaunchKernelGGL((k_cut_local<T, P, WHICH, true>), dim3((unsigned)(nc * (P + 1))), dim3(256), 0, s, R, R.cut_elems,
-                           (const T*)mc, (T*)nullptr, H->act2cut, vm, vk, 0);
+        scatter(R.cut_elems, nc, (const T*)mc);
     }
     err = hipFreeAsync(mom, s);
     if (err != hipSuccess) return wq_set_error(WQ_EHIP, "gauss_assemble: scratch release failed: %s", hipGetErrorString(err));
@@ -1055,9 +1086,11 @@ int launch_gauss(const wq_rules* H, uint32_t which, const T* kg, const T* kappa,
         WQ_GAUSS_CASE(2)
         WQ_GAUSS_CASE(3)
         WQ_GAUSS_CASE(4)
+        WQ_GAUSS_CASE(5)
+        WQ_GAUSS_CASE(6)
 #undef WQ_GAUSS_CASE
     }
-    return wq_set_error(WQ_EUNSUPPORTED, "gauss_assemble: degree above 4 is not supported");
+    return WQ_OK;
 }
 
 #ifndef WQ_ONLY_F32

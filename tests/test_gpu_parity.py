@@ -169,10 +169,10 @@ _GAUSS = {}
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
-@pytest.mark.parametrize("name", ["uncut4_p1", "ball6_p2", "plane6_p3", "torus8_p2", "ball5_p4"])
+@pytest.mark.parametrize("name", ["uncut4_p1", "ball6_p2", "plane6_p3", "torus8_p2", "ball5_p4", "ball4_p5"])
 def test_gauss_assemble_matches_oracle(name, dtype):
     """Conventional element-by-element Gauss assembly against the oracle's element loop."""
-    wl = SMALL[name]
+    wl = SMALL.get(name) or HIGH[name]
     print("case gauss", name, dtype, flush=True)
     if name not in _GAUSS:
         P = Problem(wl)
@@ -192,9 +192,10 @@ def test_gauss_assemble_matches_oracle(name, dtype):
 
 
 def test_gauss_equals_wq_for_unit_kappa():
-    """kappa = 1: WQ is exact, so the WQ matrices equal the Gauss ones (uncut and cut)."""
-    for name in ("uncut5_p3", "ball6_p2"):
-        wl = SMALL[name]
+    """kappa = 1: WQ is exact, so the WQ matrices equal the Gauss ones (uncut and cut, up to
+    degree 6)."""
+    for name in ("uncut5_p3", "ball6_p2", "ball4_p5", "ball4_p6"):
+        wl = SMALL.get(name) or HIGH[name]
         R = rules_for(wl)
         one = torch.ones(R.n_kappa, dtype=torch.float64, device=R.device)
         og = torch.ones(R.n_gauss_elems * (wl.degree + 1) ** 3, dtype=torch.float64, device=R.device)
