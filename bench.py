@@ -75,14 +75,17 @@ def copy_probe():
     print(json.dumps({"copy_probe_bytes": 4 * n, "copies": 3}))
 
 
-# HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch),
-# scaled by what the same counters read for `bench.py --copy-probe` (a 256 MiB copy reads
-# FETCH_SIZE = 128 MiB, WRITE_SIZE = 256 MiB: fetch x 2.0, write x 1.0).  Valid only for the
-# kernel source they were taken on: the digest of its text is checked, else traffic is null.
+# HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch, the
+# median over a run), scaled by what the same counters read for `bench.py --copy-probe` (a
+# 256 MiB copy reads FETCH_SIZE = 128 MiB, WRITE_SIZE = 256 MiB: fetch x 2.0, write x 1.0).  A
+# group of kernels sums its members.  Valid only for the kernel sources they were taken on:
+# the SHA-1 over the members' source digests is checked, else traffic is null.
 TRAFFIC = {
-    # (kernel, workload, dtype): (sha1 of the kernel's source text, fetch KiB, write KiB)
-    ("k_cut_remainder", "plane48_p4", "f32"): ("4702b1d161c06f3db40fc5605189d82d9b73aec3", 159367.3, 115167.4),
-    ("k_cut_remainder", "plane48_p4", "f64"): ("4702b1d161c06f3db40fc5605189d82d9b73aec3", 250484.9, 228916.3),
+    # (kernels, workload, dtype): (sha1 over the kernels' source digests, fetch KiB, write KiB)
+    (("k_cut_remainder",), "plane48_p4", "f32"): ("05a0d4aa6f6e58b4b3a3c5f552922a5bf6bb28b0", 159177.4, 115167.4),
+    (("k_cut_remainder",), "plane48_p4", "f64"): ("05a0d4aa6f6e58b4b3a3c5f552922a5bf6bb28b0", 251025.1, 228916.3),
+    (("k_rows_block", "k_rows_box", "k_rows_zero"), "plane48_p4", "f32"): ("01574deff6b788284331e48f2376cdd61c267fc6", 57726.9, 458689.5),
+    (("k_cut_moments", "k_cut_local", "k_cut_gather"), "plane48_p4", "f32"): ("747ff50a7cad0b53651a12e61d4bbe0fe61289c4", 759447.2, 775283.6),
 }
 
 
@@ -99,9 +102,17 @@ def kernel_digest(name):
     return None
 
 
-def measured_traffic(kernel, workload, dtype):
-    rec = TRAFFIC.get((kernel, workload, dtype))
-    if rec is None or kernel_digest(kernel) != rec[0]:
+def group_digest(kernels):
+    import hashlib
+    parts = [kernel_digest(k) for k in kernels]
+    if any(p is None for p in parts):
+        return None
+    return hashlib.sha1("".join(parts).encode()).hexdigest()
+
+
+def measured_traffic(kernels, workload, dtype):
+    rec = TRAFFIC.get((tuple(kernels), workload, dtype))
+    if rec is None or group_digest(kernels) != rec[0]:
         return None
     return (rec[1] * 2.0 + rec[2] * 1.0) * 1024
 
@@ -194,9 +205,10 @@ def cpu_baseline(wl, nrows):
 
 def paper_sweep(args):
     """Section 3.1 / 3.2: mass matrix of the cut cube [-1,1]^3 (kappa = 1, FP64), L2 projection of
-    f = sin(2xz) cos(3yz) with extended B-splines, relative L2 error, for the three schemes:
-    Ref (element-by-element Gauss), Hybrid Gauss and DWQ.  Times are HIP-event means over
-    repeated calls; the Ref load vector is the row sums of its mass matrix with kappa = f."""
+    f = sin(2xz) cos(3yz) with extended B-splines (Jacobi PCG to a relative residual of 1e-14),
+    relative L2 error, for the three schemes: Ref (element-by-element Gauss), Hybrid Gauss and
+    DWQ.  Times are HIP-event means over repeated calls; the Ref load vector is the row sums of
+    its mass matrix with kappa = f."""
     import torch
 
     import workloads as W
@@ -243,7 +255,7 @@ def paper_sweep(args):
                 ext = R.extension()
                 r["extension_ms"] = (time.perf_counter() - t0) * 1e3
                 t0 = time.perf_counter()
-                u, it, rel = R.project(ext, vm, b, tol=1e-12, max_iter=60000)
+                u, it, rel = R.project(ext, vm, b, tol=1e-14, max_iter=100000)
                 r["solve_ms"] = (time.perf_counter() - t0) * 1e3
                 fg = W.target_f(R.gauss_coords())
                 e2, n2 = R.l2_error(u, fg, f)
@@ -268,7 +280,7 @@ def paper_sweep(args):
             rp = R.row_ptr()
             rows = torch.repeat_interleave(torch.arange(R.n_active, device=dev), torch.diff(rp))
             b = torch.zeros(R.n_active, dtype=f64, device=dev).index_add_(0, rows, Mf)
-            u, it, rel = R.project(ref_ext, M, b, tol=1e-12, max_iter=60000)
+            u, it, rel = R.project(ref_ext, M, b, tol=1e-14, max_iter=100000)
             e2, n2 = R.l2_error(u, ref_fg, ref_f)
             rec["ref"] = {"mass_ms": ms, "mass_f32_ms": ms32, "cg_iterations": it, "cg_relres": rel,
                           "rel_l2_error": math.sqrt(e2 / n2)}
@@ -422,16 +434,19 @@ def main():
     probe_ms = timed(lambda: probe.fill_(0.5), 10, torch)
     write_probe = probe.numel() * probe.element_size() / (probe_ms * 1e-3) / 1e9
     del probe
-    roofs = {"rows": {"bound": "hbm", "kernel": "k_rows_interior + k_rows_cut + k_rows_zero (wq_assemble_rows)",
+    rows_kernels = "k_rows_block" if (main_dt == "f32" and wl.degree <= 4) else "k_rows_interior"
+    roofs = {"rows": {"bound": "hbm", "kernel": f"{rows_kernels} + k_rows_box + k_rows_zero (wq_assemble_rows)",
                       "achieved": rows_bytes / (timed_ms["rows"] * 1e-3) / 1e9, "peak": PEAK["hbm_GBps"],
-                      "unit": "GB/s", "traffic": None, "write_probe_GBps": write_probe}}
+                      "unit": "GB/s", "traffic": measured_traffic(("k_rows_block", "k_rows_box", "k_rows_zero"), wl.name,
+                                                                  main_dt),
+                      "write_probe_GBps": write_probe}}
     roofs["rows"]["frac_of_write_probe"] = roofs["rows"]["achieved"] / write_probe
     # remainder (k_cut_remainder, one launch): per (cut row, remainder element) pair the three
     # sum-factorized stages of mass + stiffness, 2 P1^4 + 3 P1^4 + 3 P1^4 FMA
     rem_flop = 2 * R.n_rem_pairs * 8 * P1 ** 4
     roofs["remainder"] = {"bound": "alu", "kernel": "k_cut_remainder (cut_assemble, remainder part)",
                           "achieved": rem_flop / (timed_ms["remainder"] * 1e-3) / 1e12, "peak": peak,
-                          "unit": "TFLOP/s", "traffic": measured_traffic("k_cut_remainder", wl.name, main_dt)}
+                          "unit": "TFLOP/s", "traffic": measured_traffic(("k_cut_remainder",), wl.name, main_dt)}
     # cut elements in moment form (k_cut_moments + k_cut_local + k_cut_gather), M + K: moments
     # with direction 3 per leaf P1^3 NK, direction 2 per column P1^2 NK^2, direction 1 per
     # x-group NK^3 P1; then per element and a3: 2 NK^3 P1 + 3 NK^2 P1^3 + 3 NK P1^5
@@ -439,9 +454,13 @@ def main():
                + R.n_cut_elems * P1 * (2 * NK ** 3 * P1 + 3 * NK ** 2 * P1 ** 3 + 3 * NK * P1 ** 5))
     roofs["octree"] = {"bound": "alu", "kernel": "k_cut_moments + k_cut_local + k_cut_gather (cut_assemble, octree part)",
                        "achieved": 2 * oct_fma / (timed_ms["octree"] * 1e-3) / 1e12, "peak": peak, "unit": "TFLOP/s",
-                       "traffic": None}
+                       "traffic": measured_traffic(("k_cut_moments", "k_cut_local", "k_cut_gather"), wl.name, main_dt)}
     for v in roofs.values():
         v["frac"] = v["achieved"] / v["peak"]
+    # flop per HBM byte of the counted traffic (where it was measured)
+    for name, fl in (("remainder", rem_flop), ("octree", 2 * oct_fma)):
+        if roofs[name]["traffic"]:
+            roofs[name]["intensity_flop_per_byte"] = fl / roofs[name]["traffic"]
     # the longest single kernel of a step (rocprofv3 summary in profiles/) is k_cut_remainder
     dominant = "remainder"
     roof = roofs[dominant]
