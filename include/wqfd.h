@@ -227,9 +227,11 @@ int wq_extension_build(const wq_rules* rules, void* stream, wq_extension** out);
 int wq_extension_info_get(const wq_extension* ext, wq_extension_info* out);
 void wq_extension_free(wq_extension* ext);
 
-/* u = E c with E^T M E c = E^T b by conjugate gradients with the Jacobi preconditioner
- * (diagonal of E^T M E), from c = 0, stopping when ||r|| <= tol ||E^T b|| (checked every 8
- * iterations) or after max_iter iterations.  vals_mass: (nnz) mass values (FP64, kappa = 1 for
+/* u = E c with E^T M E c = E^T b by preconditioned conjugate gradients from c = 0, stopping
+ * when ||r|| <= tol ||E^T b|| (checked every 8 iterations) or after max_iter iterations.  The
+ * preconditioner is S R K^{-1} R^T S: K = K1 x K2 x K3 the mass matrix of all functions of the
+ * background mesh (banded Cholesky factors of the 1D masses, built with the extension), R^T
+ * the zero extension from the inner functions, S = diag(sqrt(diag(K)_i / diag(E^T M E)_i)).  vals_mass: (nnz) mass values (FP64, kappa = 1 for
  * the paper's projection), b: (n_active), u: (n_active) output; all device.  *iters and
  * *relres (host, may be NULL) receive the iteration count and the final relative residual.
  * ext must come from the same rules handle.  Synchronous (the host reads the residual);

@@ -39,6 +39,11 @@ struct wq_extension {
     int64_t* et_ptr = nullptr;            // CSR of E^T, rows = inner functions, columns ascending
     int32_t* et_col = nullptr;
     double* et_val = nullptr;
+    // preconditioner: box mass matrix K1 x K2 x K3 of the whole background mesh
+    int32_t* inner_lex = nullptr;         // (n_inner) lexicographic function index
+    int32_t* lex_inner = nullptr;         // (nfun product) inner index or -1
+    double* kchol[3] = {nullptr, nullptr, nullptr};   // banded Cholesky factor of K_d, [i][k] = L(i, i-k)
+    double* kdiag[3] = {nullptr, nullptr, nullptr};   // diagonal of K_d
     std::vector<void*> allocs;
     ~wq_extension() {
         for (void* q : allocs) (void)hipFree(q);
@@ -179,6 +184,42 @@ __global__ void k_ext_values(DevRules R, int64_t n_active, const int32_t* outer_
             for (int c = 0; c <= p; ++c) e_val[o++] = lam[0][a] * lam[1][b] * lam[2][c];
 }
 
+// band of the 1D box mass matrix, out[i][k] = K_d(i, i - k) for k = 0..p (0 outside), by the
+// element Gauss rule: sum over the elements shared by B_i and B_{i-k}
+__global__ void k_mass1d(DevRules R, int d, double* out, double* diag) {
+    const int p = R.p, P1 = p + 1, n = R.nfun[d];
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= n * P1) return;
+    const int i = id / P1, k = id % P1, j = i - k;
+    double v = 0.0;
+    if (j >= 0) {
+        for (int e = max(i - p, 0); e <= min(j, R.nel[d] - 1); ++e)
+            for (int g = 0; g < P1; ++g) {
+                const double* B = R.Bval[d] + ((int64_t)e * P1 + g) * P1;
+                v += R.gw[g] * R.h[d] * 0.5 * B[i - e] * B[j - e];
+            }
+    }
+    out[id] = v;
+    if (k == 0) diag[i] = v;
+}
+
+// in-place banded Cholesky K = L L^T, band [i][k] = L(i, i-k) (one thread: n <= a few hundred)
+__global__ void k_band_chol(int n, int p, double* L, int* bad) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    const int P1 = p + 1;
+    for (int i = 0; i < n; ++i)
+        for (int j = max(0, i - p); j <= i; ++j) {
+            double v = L[i * P1 + (i - j)];
+            for (int m = max(0, i - p); m < j; ++m) v -= L[i * P1 + (i - m)] * L[j * P1 + (j - m)];
+            if (j == i) {
+                if (!(v > 0.0)) { bad[0] = 1; v = 1.0; }
+                L[i * P1] = sqrt(v);
+            } else {
+                L[i * P1 + (i - j)] = v / L[j * P1];
+            }
+        }
+}
+
 __global__ void k_gather_f64(const double* src, const int64_t* perm, int64_t n, double* dst) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) dst[i] = src[perm[i]];
@@ -311,43 +352,97 @@ __global__ void k_jacobi(const int64_t* et_ptr, const int32_t* et_col, const dou
     bad[i] = ok ? 0 : 1;
 }
 
-// start: z = invD r, p = z, partials of r.z and r.r
-__global__ __launch_bounds__(RED_THREADS) void k_pcg_start(const double* r, const double* invD, int64_t n, double* z,
-                                                           double* p, double* partials) {
-    double acc[2] = {0.0, 0.0};
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const double zi = invD[i] * r[i];
-        z[i] = zi;
-        p[i] = zi;
-        acc[0] += r[i] * zi;
-        acc[1] += r[i] * r[i];
-    }
-    block_partials<2>(acc, partials, gridDim.x);
-}
-
-// alpha = rz / pq; x += alpha p; r -= alpha q; z = invD r; partials of r.z and r.r
-__global__ __launch_bounds__(RED_THREADS) void k_pcg_xr(double* x, double* r, double* z, const double* p,
-                                                        const double* q, const double* invD, int64_t n,
-                                                        const double* sc, int cur, double* partials) {
-    const double alpha = sc[SC_RZ + cur] / sc[SC_PQ];
-    double acc[2] = {0.0, 0.0};
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        x[i] += alpha * p[i];
-        const double ri = r[i] - alpha * q[i];
-        r[i] = ri;
-        const double zi = invD[i] * ri;
-        z[i] = zi;
-        acc[0] += ri * zi;
-        acc[1] += ri * ri;
-    }
-    block_partials<2>(acc, partials, gridDim.x);
-}
-
 // beta = rz_next / rz; p = z + beta p
 __global__ void k_pcg_p(double* p, const double* z, int64_t n, const double* sc, int cur) {
     const double beta = sc[SC_RZ + (cur ^ 1)] / sc[SC_RZ + cur];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = z[i] + beta * p[i];
+}
+
+// Preconditioner z = S R K^{-1} R^T S r: K = K1 x K2 x K3 the mass matrix of every function of
+// the background mesh, R^T the zero extension from the inner functions to the whole grid, S the
+// diagonal sqrt(diag(K)_i / diag(E^T M E)_i) that restores the row scale of functions with
+// little support in the domain.
+// g[lex] = s_i r_i at inner functions, 0 elsewhere
+__global__ void k_prec_scatter(const int32_t* lex_inner, int64_t nlex, const double* sc, const double* r, double* g) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nlex) return;
+    const int32_t i = lex_inner[k];
+    g[k] = i >= 0 ? sc[i] * r[i] : 0.0;
+}
+
+// K_d^{-1} along direction d of the grid g (nfun[0] x nfun[1] x nfun[2]): one thread per line,
+// forward then backward substitution with the band factor
+__global__ void k_prec_lines(DevRules R, int d, const double* L, double* g) {
+    const int p = R.p, P1 = p + 1;
+    const int n0 = R.nfun[0], n1 = R.nfun[1], n2 = R.nfun[2];
+    const int n = R.nfun[d];
+    const int64_t nlines = (int64_t)n0 * n1 * n2 / n;
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= nlines) return;
+    int64_t base, stride;
+    if (d == 2) { base = id * n2; stride = 1; }
+    else if (d == 1) { base = (id / n2) * (int64_t)n1 * n2 + id % n2; stride = n2; }
+    else { base = id; stride = (int64_t)n1 * n2; }
+    for (int i = 0; i < n; ++i) {                 // L y = x
+        double v = g[base + i * stride];
+        for (int m = max(0, i - p); m < i; ++m) v -= L[i * P1 + (i - m)] * g[base + m * stride];
+        g[base + i * stride] = v / L[i * P1];
+    }
+    for (int i = n - 1; i >= 0; --i) {            // L^T x = y
+        double v = g[base + i * stride];
+        for (int m = i + 1; m <= min(n - 1, i + p); ++m) v -= L[m * P1 + (m - i)] * g[base + m * stride];
+        g[base + i * stride] = v / L[i * P1];
+    }
+}
+
+// z_i = s_i g[lex_i]; partials of r.z into slot 0 (grid RED_BLOCKS x RED_THREADS)
+__global__ __launch_bounds__(RED_THREADS) void k_prec_gather(const int32_t* inner_lex, int64_t n, const double* sc,
+                                                             const double* g, const double* r, double* z,
+                                                             double* partials) {
+    double acc[1] = {0.0};
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double zi = sc[i] * g[inner_lex[i]];
+        z[i] = zi;
+        acc[0] += r[i] * zi;
+    }
+    block_partials<1>(acc, partials, gridDim.x);
+}
+
+// s_i = sqrt(prod_d diag(K_d)(i_d) * invD_i)
+__global__ void k_prec_scale(DevRules R, const int32_t* inner_lex, int64_t n, const double* k0, const double* k1,
+                             const double* k2, const double* invD, double* sc) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int I[3];
+    unlex3(inner_lex[i], R.nfun, I);
+    sc[i] = sqrt(k0[I[0]] * k1[I[1]] * k2[I[2]] * invD[i]);
+}
+
+// alpha = rz / pq; x += alpha p; r -= alpha q; partials of r.r into slot 1
+__global__ __launch_bounds__(RED_THREADS) void k_pcg_xr2(double* x, double* r, const double* p, const double* q,
+                                                         int64_t n, const double* sc, int cur, double* partials) {
+    const double alpha = sc[SC_RZ + cur] / sc[SC_PQ];
+    double acc[1] = {0.0};
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        x[i] += alpha * p[i];
+        const double ri = r[i] - alpha * q[i];
+        r[i] = ri;
+        acc[0] += ri * ri;
+    }
+    block_partials<1>(acc, partials + RED_BLOCKS, gridDim.x);
+}
+
+__global__ __launch_bounds__(RED_THREADS) void k_dot_self(const double* r, int64_t n, double* partials) {
+    double acc[1] = {0.0};
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        acc[0] += r[i] * r[i];
+    block_partials<1>(acc, partials, gridDim.x);
+}
+
+__global__ void k_copy_f64(const double* a, int64_t n, double* b) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = a[i];
 }
 
 // ---------------------------------------------------------------------------------------
@@ -653,6 +748,35 @@ int projection_build_extension(const wq_rules* H, hipStream_t s, wq_extension** 
         hipLaunchKernelGGL(k_gather_f64, blocks_for(nnz), dim3(256), 0, s, (const double*)X->e_val,
                            (const int64_t*)perm_d, nnz, X->et_val);
     if (!hip_ok(hipGetLastError()) || !hip_ok(hipStreamSynchronize(s))) return fail(WQ_EHIP, "values of E failed");
+    // preconditioner: inner <-> lexicographic maps, band Cholesky factors of the 1D box masses
+    std::vector<int32_t> inner_lex(std::max<int64_t>(ni, 1)), lex_inner(nlex, -1);
+    for (int64_t lex = 0; lex < nlex; ++lex) {
+        const int32_t act = h_lex2act[lex];
+        if (act >= 0 && inner_of[act] >= 0) {
+            lex_inner[lex] = inner_of[act];
+            inner_lex[inner_of[act]] = (int32_t)lex;
+        }
+    }
+    int* bad_d = nullptr;
+    if (!hip_ok(X->alloc(&X->inner_lex, ni)) || !hip_ok(X->alloc(&X->lex_inner, nlex)) || !hip_ok(X->alloc(&bad_d, 1)))
+        return fail(WQ_ENOMEM, "device allocation failed");
+    for (int d = 0; d < 3; ++d)
+        if (!hip_ok(X->alloc(&X->kchol[d], (int64_t)R.nfun[d] * P1)) || !hip_ok(X->alloc(&X->kdiag[d], R.nfun[d])))
+            return fail(WQ_ENOMEM, "device allocation failed");
+    const int zero = 0;
+    if (!hip_ok(hipMemcpyAsync(X->inner_lex, inner_lex.data(), sizeof(int32_t) * ni, hipMemcpyHostToDevice, s)) ||
+        !hip_ok(hipMemcpyAsync(X->lex_inner, lex_inner.data(), sizeof(int32_t) * nlex, hipMemcpyHostToDevice, s)) ||
+        !hip_ok(hipMemcpyAsync(bad_d, &zero, sizeof(int), hipMemcpyHostToDevice, s)))
+        return fail(WQ_EHIP, "upload of the preconditioner maps failed");
+    for (int d = 0; d < 3; ++d) {
+        hipLaunchKernelGGL(k_mass1d, blocks_for((int64_t)R.nfun[d] * P1), dim3(256), 0, s, R, d, X->kchol[d], X->kdiag[d]);
+        hipLaunchKernelGGL(k_band_chol, dim3(1), dim3(1), 0, s, R.nfun[d], p, X->kchol[d], bad_d);
+    }
+    int bad = 0;
+    if (!hip_ok(hipGetLastError()) || !hip_ok(hipMemcpyAsync(&bad, bad_d, sizeof(int), hipMemcpyDeviceToHost, s)) ||
+        !hip_ok(hipStreamSynchronize(s)))
+        return fail(WQ_EHIP, "preconditioner factors failed");
+    if (bad) return fail(WQ_ESINGULAR, "a 1D mass matrix is not positive definite");
     *out = X;
     return WQ_OK;
 }
@@ -682,23 +806,38 @@ int projection_solve(const wq_rules* H, const wq_extension* X, const double* M, 
     if (relres) *relres = 0.0;
     if (na == 0) return WQ_OK;
     const DevRules& R = H->R;
+    const int64_t nlex = (int64_t)R.nfun[0] * R.nfun[1] * R.nfun[2];
     Scratch sc(H, s);
     double *x = sc.get<double>(ni), *r = sc.get<double>(ni), *z = sc.get<double>(ni), *p = sc.get<double>(ni);
     double *q = sc.get<double>(ni), *invD = sc.get<double>(ni), *ta = sc.get<double>(na), *tb = sc.get<double>(na);
+    double *sv = sc.get<double>(ni), *grid = sc.get<double>(nlex);
     double *part = sc.get<double>(2 * RED_BLOCKS), *scal = sc.get<double>(SC_N);
     int8_t* bad = sc.get<int8_t>(ni);
     if (sc.failed) return wq_set_error(WQ_ENOMEM, "wq_project: scratch allocation failed");
-    const dim3 gi = blocks_for(ni), ga = blocks_for(na), gw = blocks_for(na * 64);
+    const dim3 gi = blocks_for(ni), ga = blocks_for(na), gw = blocks_for(na * 64), gl = blocks_for(nlex);
     const dim3 gr(RED_BLOCKS), tr(RED_THREADS);
-    // Jacobi
+    auto precond = [&]() {       // z = S R K^{-1} R^T S r, partials of r.z into slot 0
+        hipLaunchKernelGGL(k_prec_scatter, gl, dim3(256), 0, s, (const int32_t*)X->lex_inner, nlex, (const double*)sv,
+                           (const double*)r, grid);
+        for (int d = 2; d >= 0; --d)
+            hipLaunchKernelGGL(k_prec_lines, blocks_for(nlex / R.nfun[d]), dim3(256), 0, s, R, d, (const double*)X->kchol[d],
+                               grid);
+        hipLaunchKernelGGL(k_prec_gather, gr, tr, 0, s, (const int32_t*)X->inner_lex, ni, (const double*)sv,
+                           (const double*)grid, (const double*)r, z, part);
+    };
+    // diagonal of E^T M E and the preconditioner's scaling
     hipLaunchKernelGGL(k_jacobi, gi, dim3(256), 0, s, (const int64_t*)X->et_ptr, (const int32_t*)X->et_col,
                        (const double*)X->et_val, (const int64_t*)R.row_ptr, (const int32_t*)R.col_idx, M, ni, invD, bad);
-    // r = E^T b, x = 0, z = invD r, p = z
+    hipLaunchKernelGGL(k_prec_scale, gi, dim3(256), 0, s, R, (const int32_t*)X->inner_lex, ni, (const double*)X->kdiag[0],
+                       (const double*)X->kdiag[1], (const double*)X->kdiag[2], (const double*)invD, sv);
+    // r = E^T b, x = 0, z = prec(r), p = z
     hipLaunchKernelGGL(k_apply_ET, gr, tr, 0, s, (const int64_t*)X->et_ptr, (const int32_t*)X->et_col,
                        (const double*)X->et_val, b, ni, r, (const double*)nullptr, part);
     hipLaunchKernelGGL(k_fill_f64, gi, dim3(256), 0, s, x, ni, 0.0);
-    hipLaunchKernelGGL(k_pcg_start, gr, tr, 0, s, (const double*)r, (const double*)invD, ni, z, p, part);
+    hipLaunchKernelGGL(k_dot_self, gr, tr, 0, s, (const double*)r, ni, part + RED_BLOCKS);
+    precond();
     hipLaunchKernelGGL(k_reduce<2>, dim3(1), tr, 0, s, (const double*)part, (int64_t)RED_BLOCKS, scal + SC_RZ, scal + SC_RR);
+    hipLaunchKernelGGL(k_copy_f64, gi, dim3(256), 0, s, (const double*)z, ni, p);
     double h_sc[SC_N];
     std::vector<int8_t> h_bad(ni);
     if (hipGetLastError() != hipSuccess ||
@@ -724,8 +863,9 @@ int projection_solve(const wq_rules* H, const wq_extension* X, const double* M, 
                                (const double*)X->et_val, (const double*)tb, ni, q, (const double*)p, part);
             hipLaunchKernelGGL(k_reduce<1>, dim3(1), tr, 0, s, (const double*)part, (int64_t)RED_BLOCKS, scal + SC_PQ,
                                scal + SC_PQ);
-            hipLaunchKernelGGL(k_pcg_xr, gr, tr, 0, s, x, r, z, (const double*)p, (const double*)q, (const double*)invD,
-                               ni, (const double*)scal, cur, part);
+            hipLaunchKernelGGL(k_pcg_xr2, gr, tr, 0, s, x, r, (const double*)p, (const double*)q, ni,
+                               (const double*)scal, cur, part);
+            precond();
             hipLaunchKernelGGL(k_reduce<2>, dim3(1), tr, 0, s, (const double*)part, (int64_t)RED_BLOCKS,
                                scal + SC_RZ + (cur ^ 1), scal + SC_RR);
             hipLaunchKernelGGL(k_pcg_p, gi, dim3(256), 0, s, p, (const double*)z, ni, (const double*)scal, cur);
