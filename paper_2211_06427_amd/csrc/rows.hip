@@ -1,19 +1,19 @@
 // Row assembly by sum factorization over weighted-quadrature rules (Section 1: sum
 // factorization, weighted quadrature and the row loop; Section 2.2 for DWQ rows).
 //
-// Interior rows: one workgroup per line block of up to RB consecutive interior rows along
-// direction 1 (fixed i2, i3).  Stages 1-2 contract directions 3 and 2 once for the whole
-// block into an LDS slab T2[q1][j2 j3]; stage 3 contracts direction 1 per row, one lane per
-// (j2, j3) column, with the row's direction-1 weights read as wave-uniform scalars, and
-// stores each row's (2p+1)^3 values with coalesced writes.
+// Interior rows: one workgroup per line block of consecutive interior rows along direction 1
+// (fixed i2, i3).  Stages 1-2 contract directions 3 and 2 once for the whole block into an
+// LDS slab T2[q1][j2 j3]; stage 3 contracts direction 1 per row, one lane per (j2, j3)
+// column, and stores each row's (2p+1)^3 values with coalesced writes.  FP32 at p <= 4 uses
+// k_rows_block (blocks of at most 8 rows, every contraction over the compile-time band of its
+// window class, four workgroups per CU); FP64, p > 4 and the BF16x3 experiment use
+// k_rows_interior.
 //
-// Cut rows: one workgroup per cut row.  Rows with a DWQ box use the one-sided rule in the
-// split direction and the standard rules in the others (kappa gathered through the slot
-// map); rows without a box are zeroed (their support is handled by cut_assemble).
-#include <type_traits>
-
-#include "rows.h"
-
+// Cut rows: rows with a DWQ box use the one-sided rule in the split direction and the
+// standard rules in the others (kappa gathered through the slot map): k_rows_box at p <= 4
+// (the whole box in LDS), k_rows_cut otherwise; rows without a box are zeroed by k_rows_zero
+// (their support is handled by cut_assemble).  The cut rows run on a second stream beside
+// the interior rows.
 template <typename T> __device__ inline const T* wt_table(const DevRules& R, int d);
 template <> __device__ inline const double* wt_table<double>(const DevRules& R, int d) { return R.Wt64[d]; }
 template <> __device__ inline const float* wt_table<float>(const DevRules& R, int d) { return R.Wt32[d]; }
