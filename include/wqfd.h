@@ -77,14 +77,21 @@ typedef struct {
 
 typedef struct {
     int32_t octree_levels;   /* depth of the cut-element octree, 0..5 (default 3) */
-    int32_t flags;           /* 0 or WQ_OPT_HYBRID_GAUSS */
+    int32_t flags;           /* 0, WQ_OPT_HYBRID_GAUSS or WQ_OPT_GAUSS_ROWS */
 } wq_options;
 
 /* Option flag: the "Hybrid Gauss" scheme of Section 3.1 (list of compared schemes) instead of
  * DWQ.  Interior rows keep weighted quadrature; no cut row gets a DWQ box, so the whole
  * regular support of every cut row (its interior elements) is integrated by element Gauss
- * rules with sum factorization in cut_assemble.  Slots and pattern are unchanged. */
-enum { WQ_OPT_HYBRID_GAUSS = 1 };
+ * rules with sum factorization in cut_assemble.  Slots and pattern are unchanged.
+ * Option flag WQ_OPT_GAUSS_ROWS (comparison, not in the paper): no weighted quadrature at all;
+ * every active row is handled like a cut row without a box, i.e. wq_assemble_rows zeroes it
+ * and cut_assemble integrates every interior element of its support by element Gauss rules
+ * with sum factorization and its cut elements by the octree.  The result is the conventional
+ * Gauss assembly (gauss_assemble), formed row by row without atomics, so that the gain of
+ * weighted quadrature can be measured on the same row-owned engineering.  The slot layout
+ * then holds a Gauss block for every interior element; n_rows_interior is 0. */
+enum { WQ_OPT_HYBRID_GAUSS = 1, WQ_OPT_GAUSS_ROWS = 2 };
 
 typedef struct wq_rules wq_rules;   /* opaque; owns its device buffers */
 

@@ -35,9 +35,11 @@ class Rules:
     """Kappa-independent data of one mesh + domain (built on the GPU, FP64)."""
 
     def __init__(self, nel, degree, levelset=None, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), octree_levels=3,
-                 device=None, hybrid_gauss=False):
+                 device=None, hybrid_gauss=False, gauss_rows=False):
         """hybrid_gauss=True: the Hybrid Gauss scheme (no DWQ boxes; the regular support of
-        every cut row goes through element Gauss with sum factorization)."""
+        every cut row goes through element Gauss with sum factorization).  gauss_rows=True: no
+        weighted quadrature; every row by element Gauss with sum factorization (the
+        conventional Gauss matrices, row-owned and atomic-free; for comparison)."""
         lib = L.load()
         if isinstance(nel, int):
             nel = (nel, nel, nel)
@@ -49,8 +51,10 @@ class Rules:
             ls.c = (C.c_double * 3)(*levelset.c)
             ls.n = (C.c_double * 3)(*levelset.n)
             ls.r0, ls.r1 = float(levelset.r0), float(levelset.r1)
-        opts = L.WqOptions(int(octree_levels), L.WQ_OPT_HYBRID_GAUSS if hybrid_gauss else 0)
+        opts = L.WqOptions(int(octree_levels), (L.WQ_OPT_HYBRID_GAUSS if hybrid_gauss else 0) |
+                           (L.WQ_OPT_GAUSS_ROWS if gauss_rows else 0))
         self.hybrid_gauss = bool(hybrid_gauss)
+        self.gauss_rows = bool(gauss_rows)
         h = C.c_void_p()
         with torch.cuda.device(self.device):
             L.check(lib.wq_build_rules(C.byref(mesh), C.byref(ls), C.byref(opts),
@@ -69,8 +73,8 @@ class Rules:
         self.nfun = tuple(info.nfun)
 
     @classmethod
-    def from_workload(cls, wl, device=None, hybrid_gauss=False):
-        return cls(wl.nel, wl.degree, wl.levelset, wl.lo, wl.hi, wl.octree_levels, device, hybrid_gauss)
+    def from_workload(cls, wl, device=None, hybrid_gauss=False, gauss_rows=False):
+        return cls(wl.nel, wl.degree, wl.levelset, wl.lo, wl.hi, wl.octree_levels, device, hybrid_gauss, gauss_rows)
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -14,6 +14,10 @@
 // (the whole box in LDS), k_rows_cut otherwise; rows without a box are zeroed by k_rows_zero
 // (their support is handled by cut_assemble).  The cut rows run on a second stream beside
 // the interior rows.
+#include <type_traits>
+
+#include "rows.h"
+
 template <typename T> __device__ inline const T* wt_table(const DevRules& R, int d);
 template <> __device__ inline const double* wt_table<double>(const DevRules& R, int d) { return R.Wt64[d]; }
 template <> __device__ inline const float* wt_table<float>(const DevRules& R, int d) { return R.Wt32[d]; }

@@ -409,7 +409,7 @@ __global__ void k_active_index(int64_t nf, const int32_t* flag, const int64_t* o
 }
 
 __global__ void k_row_count(DevRules R, int64_t na, const int32_t* act2lex, const int8_t* fcls, int32_t* cnt,
-                            int32_t* cut_flag) {
+                            int32_t* cut_flag, int all_rows) {
     int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= na) return;
     int I[3];
@@ -425,7 +425,7 @@ __global__ void k_row_count(DevRules R, int64_t na, const int32_t* act2lex, cons
             for (int k = lo[2]; k <= hi[2]; ++k)
                 c += fcls[((int64_t)a * R.nfun[1] + b) * R.nfun[2] + k] != CLS_OUT;
     cnt[r] = c;
-    cut_flag[r] = fcls[act2lex[r]] == CLS_CUT;
+    cut_flag[r] = all_rows || fcls[act2lex[r]] == CLS_CUT;      // all_rows: every row takes the cut-row path
 }
 
 __global__ void k_col_fill(DevRules R, int64_t na, const int32_t* act2lex, const int32_t* lex2act,
@@ -1161,7 +1161,10 @@ int build_rules(const wq_mesh* mesh, const wq_levelset* ls, const wq_options* op
     int64_t* row_ptr = B.keep<int64_t>(na + 1);
     if (!rcnt || !cflag || !row_ptr) return B.fail();
     R.row_ptr = row_ptr;
-    if (na > 0) hipLaunchKernelGGL(k_row_count, grid_for(na), dim3(256), 0, stream, R, na, act2lex, fcls, rcnt, cflag);
+    const bool gauss_rows = opts && (opts->flags & WQ_OPT_GAUSS_ROWS);
+    if (na > 0)
+        hipLaunchKernelGGL(k_row_count, grid_for(na), dim3(256), 0, stream, R, na, act2lex, fcls, rcnt, cflag,
+                           gauss_rows ? 1 : 0);
     int64_t nnz = 0;
     if (scan_exclusive(B, rcnt, row_ptr, na, &nnz)) return B.fail();
     H->nnz = nnz;
@@ -1191,7 +1194,7 @@ int build_rules(const wq_mesh* mesh, const wq_levelset* ls, const wq_options* op
     if (na > 0) hipLaunchKernelGGL(k_cut_list, grid_for(na), dim3(256), 0, stream, na, cflag, coff, cut_rows, act2cut);
     if (ncut > 0)
         hipLaunchKernelGGL(k_split, grid_for(ncut, 64), dim3(64), 0, stream, R, ncut, cut_rows, act2lex, ecls, split, box,
-                           key_used, nmax, (opts && (opts->flags & WQ_OPT_HYBRID_GAUSS)) ? 1 : 0);
+                           key_used, nmax, (opts && (opts->flags & (WQ_OPT_HYBRID_GAUSS | WQ_OPT_GAUSS_ROWS))) ? 1 : 0);
     {
         int32_t* sflag = B.tmp<int32_t>(ncut + 1);
         int64_t* soff = B.tmp<int64_t>(ncut + 1);
@@ -1244,13 +1247,14 @@ int build_rules(const wq_mesh* mesh, const wq_levelset* ls, const wq_options* op
         hipLaunchKernelGGL(k_line_count, grid_for(nl), dim3(256), 0, stream, R, fcls, rb, lc);
         int64_t nb = 0;
         if (scan_exclusive(B, lc, loff, nl, &nb)) return B.fail();
+        if (gauss_rows) nb = 0;                  // every row is on the cut-row path
         int4* blocks = B.keep<int4>(nb > 0 ? nb : 1);
         if (!blocks) return B.fail();
         R.lblocks = blocks; R.n_lblocks = nb;
-        hipLaunchKernelGGL(k_line_fill, grid_for(nl), dim3(256), 0, stream, R, fcls, rb, loff, blocks);
+        if (nb > 0) hipLaunchKernelGGL(k_line_fill, grid_for(nl), dim3(256), 0, stream, R, fcls, rb, loff, blocks);
         // blocks of at most 8 rows for the FP32 row kernel (p <= 4)
         R.fblocks = nullptr; R.n_fblocks = 0;
-        if (p <= 4) {
+        if (p <= 4 && !gauss_rows) {
             hipLaunchKernelGGL(k_line_count, grid_for(nl), dim3(256), 0, stream, R, fcls, 8, lc);
             int64_t nf = 0;
             if (scan_exclusive(B, lc, loff, nl, &nf)) return B.fail();

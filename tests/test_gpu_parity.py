@@ -568,6 +568,28 @@ def _row_scaled(a, b, rp, rows_sel=None):
     return float((d[ok] / m[ok]).max())
 
 
+@pytest.mark.parametrize("name", ["ball6_p2", "plane6_p3", "ball5_p4", "ball4_p5", "plane48_p4"])
+def test_gauss_rows_equal_conventional(name):
+    """WQ_OPT_GAUSS_ROWS: every row by element Gauss with sum factorization (row-owned, no
+    atomics, no weighted quadrature) gives the conventional element-by-element Gauss matrices
+    (the same integrals summed in another order)."""
+    wl = SMALL.get(name) or HIGH.get(name) or W.workload(name)
+    print("case gauss_rows", name, flush=True)
+    from paper_2211_06427_amd import Rules
+    Rg = Rules.from_workload(wl, gauss_rows=True)
+    Rc = rules_for(wl)
+    assert Rg.n_rows_interior == 0 and Rg.n_line_blocks == 0 and Rg.n_rows_split == 0
+    assert Rg.nnz == Rc.nnz and torch.equal(Rg.row_ptr(), Rc.row_ptr())
+    rp = Rc.row_ptr()
+    dtypes = (torch.float32,) if name == "plane48_p4" else (torch.float64, torch.float32)
+    for dtype in dtypes:
+        vm, vk = Rg.assemble(kappa_slots(Rg, wl, dtype))
+        gm, gk = Rc.gauss_assemble(W.kappa_at(wl, Rc.gauss_coords()).to(dtype), kappa_slots(Rc, wl, dtype))
+        torch.cuda.synchronize()
+        assert _row_scaled(vm, gm, rp) <= TOL[dtype] and _row_scaled(vk, gk, rp) <= TOL[dtype]
+        del vm, vk, gm, gk
+
+
 # BF16x3 split products (hi*hi + hi*lo + lo*hi): each product within 3 * 2^-16 (4.6e-5) of
 # the exact one relative to |a||b| (two 8-bit roundings per operand, the lo*lo term dropped);
 # a row entry sums <= 4p such products, so the error relative to the row maximum stays near
