@@ -284,6 +284,19 @@ def paper_sweep(args):
             e2, n2 = R.l2_error(u, ref_fg, ref_f)
             rec["ref"] = {"mass_ms": ms, "mass_f32_ms": ms32, "cg_iterations": it, "cg_relres": rel,
                           "rel_l2_error": math.sqrt(e2 / n2)}
+            # the same Gauss integrals formed row by row with sum factorization, no atomics
+            Rg = Rules.from_workload(wl, gauss_rows=True)
+            og_, vg = torch.ones(Rg.n_kappa, dtype=f64, device=dev), torch.empty(Rg.nnz, dtype=f64, device=dev)
+
+            def mass_g(o=og_, v=vg):
+                Rg.assemble_rows(o, v, None, which=WQ_MASS)
+                Rg.cut_assemble(o, v, None, which=WQ_MASS)
+
+            mass_g()
+            o32, v32 = og_.float(), torch.empty(Rg.nnz, dtype=torch.float32, device=dev)
+            rec["gauss_rows"] = {"mass_ms": timed(mass_g, nrep, torch),
+                                 "mass_f32_ms": timed(lambda: mass_g(o32, v32), nrep, torch)}
+            del Rg, og_, vg, o32, v32
             print(f"# h={h} p={p} ref: err {rec['ref']['rel_l2_error']:.3e} mass {ms:.3f} ms", file=sys.stderr,
                   flush=True)
             del R, ref_rules, ref_ext, M, Mf
@@ -420,6 +433,21 @@ def main():
         step_h()
         schemes[k]["hybrid_gauss_ms"] = timed(step_h, nrep, torch)
     del Rh
+    # the conventional Gauss matrices formed row by row with sum factorization and no atomics
+    # (no weighted quadrature): the same-engineering comparison for the gain of WQ / DWQ
+    Rg = Rules.from_workload(wl, gauss_rows=True)
+    kg_slots = W.kappa_at(wl, Rg.kappa_xyz())
+    for k in ("f64", "f32"):
+        vm, vk = vals[k]
+        kr = kg_slots.to(dt[k])
+
+        def step_g():
+            Rg.assemble_rows(kr, vm, vk)
+            Rg.cut_assemble(kr, vm, vk)
+
+        step_g()
+        schemes[k]["gauss_rows_ms"] = timed(step_g, nrep, torch)
+    del Rg, kg_slots
 
     # --- rooflines (durations from the timed region) -----------------------------------
     esz = 8 if main_dt == "f64" else 4
@@ -485,6 +513,7 @@ def main():
         "adjoint_over_forward": {k: parts[k]["adjoint_ms"] / parts[k]["step_ms"] for k in parts},
         "speedup_vs_gauss_assembly": ({k: parts[k]["gauss_ms"] / parts[k]["step_ms"] for k in parts}
                                       if kg is not None else None),
+        "speedup_vs_gauss_rows": {k: schemes[k]["gauss_rows_ms"] / parts[k]["step_ms"] for k in parts},
         "fp32_rel_err_vs_fp64": err32,
         "bf16x3_experiment": bf3,
         "schemes_ms": schemes,

@@ -15,6 +15,7 @@
 //     octrees take k_cut_octree: one workgroup per (cut element, a3, group of a1), the
 //     local matrix contracted leaf by leaf and added into the CSR values with atomics.
 #include <algorithm>
+#include <mutex>
 
 #include "rows.h"
 #include "moments.h"
@@ -1169,7 +1170,11 @@ template <typename T, int P, int WHICH>
 static int launch_cut_p(const wq_rules* H, uint32_t parts, const T* kappa, T* vm, T* vk, hipStream_t s, void* buf,
                         size_t cap) {
     const DevRules& R = H->R;
-    if ((parts & WQ_CUT_REMAINDER) && R.n_cut > 0)
+    // both parts in one call, default scratch, moment form: the remainder overlaps the octree
+    // moments and local rows (launched below); otherwise the parts run one after the other
+    const bool overlap = (parts & WQ_CUT_REMAINDER) && (parts & WQ_CUT_OCTREE) && R.n_cut > 0 && R.n_cut_elems > 0 &&
+                         R.levels <= 3 && !buf && H->side;
+    if ((parts & WQ_CUT_REMAINDER) && R.n_cut > 0 && !overlap)
         hipLaunchKernelGGL((k_cut_remainder<T, P, WHICH>), dim3((unsigned)R.n_cut), dim3(RemCfg<P>::NT), 0, s, R, kappa, vm,
                            vk);
     if ((parts & WQ_CUT_OCTREE) && R.n_cut_elems > 0) {
@@ -1187,7 +1192,38 @@ static int launch_cut_p(const wq_rules* H, uint32_t parts, const T* kappa, T* vm
             hipError_t err = H->scratch_alloc((void**)&mom, sizeof(T) * (size_t)(per * R.n_cut_elems), s);
             if (err != hipSuccess)
                 return wq_set_error(WQ_ENOMEM, "cut_assemble: scratch allocation failed: %s", hipGetErrorString(err));
-            launch_moment_form<T, P, WHICH>(H, kappa, vm, vk, mom, R.n_cut_elems, s);
+            if (overlap) {
+                // moments and local rows on the side stream while the remainder runs on s (they
+                // touch no values); the gather waits for both
+                using C = MomCfg<P>;
+                const int64_t n = R.n_cut_elems;
+                T* loc = mom + n * C::NK3;
+                std::lock_guard<std::mutex> lock(*H->side_mu);
+                if (hipEventRecord(H->ev_fork, s) == hipSuccess && hipStreamWaitEvent(H->side, H->ev_fork, 0) == hipSuccess) {
+                    hipLaunchKernelGGL((k_cut_moments<T, P>), dim3((unsigned)n), dim3(256), 0, H->side, R, kappa, mom, 0);
+                    if constexpr (P <= 4)
+                        hipLaunchKernelGGL((k_cut_local<T, P, WHICH>), dim3((unsigned)(n * (P + 1))), dim3(256), 0, H->side, R,
+                                           R.cut_elems, (const T*)mom, loc, nullptr, nullptr, nullptr, 0);
+                    else
+                        hipLaunchKernelGGL((k_cut_local_a2<T, P, WHICH>), dim3((unsigned)(n * (P + 1) * (P + 1))), dim3(256), 0,
+                                           H->side, R, R.cut_elems, (const T*)mom, loc, 0);
+                    hipLaunchKernelGGL((k_cut_remainder<T, P, WHICH>), dim3((unsigned)R.n_cut), dim3(RemCfg<P>::NT), 0, s, R,
+                                       kappa, vm, vk);
+                    if (hipEventRecord(H->ev_join, H->side) != hipSuccess || hipStreamWaitEvent(s, H->ev_join, 0) != hipSuccess) {
+                        (void)hipGetLastError();
+                        (void)hipStreamSynchronize(H->side);
+                    }
+                    hipLaunchKernelGGL((k_cut_gather<T, P, WHICH>), dim3((unsigned)R.n_cut), dim3(RemCfg<P>::NT), 0, s, R,
+                                       (const T*)loc, vm, vk, 0, (int)n, (int64_t)0);
+                } else {
+                    (void)hipGetLastError();
+                    hipLaunchKernelGGL((k_cut_remainder<T, P, WHICH>), dim3((unsigned)R.n_cut), dim3(RemCfg<P>::NT), 0, s, R,
+                                       kappa, vm, vk);
+                    launch_moment_form<T, P, WHICH>(H, kappa, vm, vk, mom, R.n_cut_elems, s);
+                }
+            } else {
+                launch_moment_form<T, P, WHICH>(H, kappa, vm, vk, mom, R.n_cut_elems, s);
+            }
             err = hipFreeAsync(mom, s);
             if (err != hipSuccess)
                 return wq_set_error(WQ_EHIP, "cut_assemble: scratch release failed: %s", hipGetErrorString(err));

@@ -568,6 +568,28 @@ def _row_scaled(a, b, rp, rows_sel=None):
     return float((d[ok] / m[ok]).max())
 
 
+@pytest.mark.parametrize("name", ["plane6_p3", "ball4_p6", "plane48_p4"])
+def test_cut_parts_in_one_call(name):
+    """cut_assemble with both parts in one call (the remainder beside the octree moments and
+    local rows on a second stream) equals the two parts called in turn, bitwise."""
+    wl = SMALL.get(name) or HIGH.get(name) or W.workload(name)
+    print("case cut one call", name, flush=True)
+    from paper_2211_06427_amd._lib import WQ_CUT_OCTREE, WQ_CUT_REMAINDER
+    R = rules_for(wl)
+    for dtype in (torch.float64, torch.float32):
+        k = kappa_slots(R, wl, dtype)
+        a = [torch.empty(R.nnz, dtype=dtype, device=R.device) for _ in range(2)]
+        b = [torch.empty(R.nnz, dtype=dtype, device=R.device) for _ in range(2)]
+        R.assemble_rows(k, *a)
+        R.cut_assemble(k, *a)
+        R.assemble_rows(k, *b)
+        R.cut_assemble(k, *b, parts=WQ_CUT_REMAINDER)
+        R.cut_assemble(k, *b, parts=WQ_CUT_OCTREE)
+        torch.cuda.synchronize()
+        assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+        del a, b
+
+
 @pytest.mark.parametrize("name", ["ball6_p2", "plane6_p3", "ball5_p4", "ball4_p5", "plane48_p4"])
 def test_gauss_rows_equal_conventional(name):
     """WQ_OPT_GAUSS_ROWS: every row by element Gauss with sum factorization (row-owned, no
