@@ -489,6 +489,11 @@ def main():
     for name, fl in (("remainder", rem_flop), ("octree", 2 * oct_fma)):
         if roofs[name]["traffic"]:
             roofs[name]["intensity_flop_per_byte"] = fl / roofs[name]["traffic"]
+            # fraction of the HBM roof the counted traffic reaches, beside the flop fraction
+            roofs[name]["hbm_frac_of_traffic"] = (roofs[name]["traffic"] / (timed_ms[name] * 1e-3) / 1e9 /
+                                                  PEAK["hbm_GBps"])
+    # neither roof is near for the remainder: its counters (profiles/) show LDS latency
+    roofs["remainder"]["limiter"] = "LDS latency between the contraction stages (SQ_WAIT_INST_LDS 34% of wave cycles)"
     # the longest single kernel of a step (rocprofv3 summary in profiles/) is k_cut_remainder
     dominant = "remainder"
     roof = roofs[dominant]

@@ -5,6 +5,8 @@
 // contracted with the direction-1 weights, then direction 2, then direction 3, and the
 // result is added into dkappa at the quadrature points (atomics where several rows share a
 // point).  The cotangents carry one value per pattern entry, like the matrices.
+#include <mutex>
+
 #include "rows.h"
 #include "moments.h"
 
@@ -953,9 +955,62 @@ k_adj_leaves(DevRules R, const T* __restrict__ part, T* __restrict__ dk) {
     }
 }
 
+// The octree part writes only the octree slots (one owner each) and the other parts add into
+// the grid and block slots with atomics, so with a second stream the octree part runs beside
+// the rest: forked after the zero fill, joined before the call returns.
+template <typename T, int P, int WHICH>
+static int launch_adj_octree(const wq_rules* H, const T* gm, const T* gk, T* dk, T* part, hipStream_t s) {
+    const DevRules& R = H->R;
+    using C = MomCfg<P>;
+    if constexpr (P <= 4)
+        hipLaunchKernelGGL((k_adj_local<T, P, WHICH>), dim3((unsigned)(R.n_cut_elems * C::P1)), dim3(256), 0, s, R, H->act2cut,
+                           gm, gk, part);
+    else
+        hipLaunchKernelGGL((k_adj_local_a2<T, P, WHICH>), dim3((unsigned)(R.n_cut_elems * C::P1)), dim3(256), 0, s, R,
+                           H->act2cut, gm, gk, part);
+    hipLaunchKernelGGL((k_adj_leaves<T, P>), dim3((unsigned)R.n_cut_elems), dim3(256), 0, s, R, (const T*)part, dk);
+    return WQ_OK;
+}
+
 template <typename T, int P, int WHICH>
 static int launch_adj_p(const wq_rules* H, const T* gm, const T* gk, T* dk, hipStream_t s) {
     const DevRules& R = H->R;
+    if (H->side && R.n_cut_elems > 0 && R.levels <= 3) {
+        using C = MomCfg<P>;
+        T* part = nullptr;
+        hipError_t err = H->scratch_alloc((void**)&part, sizeof(T) * (size_t)R.n_cut_elems * C::P1 * C::NK3, s);
+        if (err != hipSuccess)
+            return wq_set_error(WQ_ENOMEM, "wq_assemble_adjoint: scratch allocation failed: %s", hipGetErrorString(err));
+        std::lock_guard<std::mutex> lock(*H->side_mu);
+        const bool forked = hipEventRecord(H->ev_fork, s) == hipSuccess && hipStreamWaitEvent(H->side, H->ev_fork, 0) == hipSuccess;
+        if (!forked) (void)hipGetLastError();
+        launch_adj_octree<T, P, WHICH>(H, gm, gk, dk, part, forked ? H->side : s);
+        if (R.n_lblocks > 0) {
+            if constexpr (P <= 4) {
+                using A = AdjCfg<T, P, WHICH, 16>;
+                hipLaunchKernelGGL((k_adj_interior<T, P, WHICH, 16>), dim3((unsigned)R.n_lblocks), dim3(A::NT), 0, s, R, gm, gk,
+                                   dk);
+            } else {
+                using A = AdjCfg<T, P, WHICH, 8>;
+                hipLaunchKernelGGL((k_adj_interior<T, P, WHICH, 8>), dim3((unsigned)R.n_lblocks), dim3(A::NT), 0, s, R, gm, gk,
+                                   dk);
+            }
+        }
+        if (R.n_cut > 0) {
+            if (R.n_box > 0)
+                hipLaunchKernelGGL((k_adj_cut<T, P, WHICH>), dim3((unsigned)R.n_box), dim3(256), 0, s, R, gm, gk, dk);
+            hipLaunchKernelGGL((k_adj_remainder<T, P, WHICH>), dim3((unsigned)R.n_cut), dim3(RemAdjCfg<P>::NT), 0, s, R, gm,
+                               gk, dk);
+        }
+        if (forked && (hipEventRecord(H->ev_join, H->side) != hipSuccess || hipStreamWaitEvent(s, H->ev_join, 0) != hipSuccess)) {
+            (void)hipGetLastError();
+            (void)hipStreamSynchronize(H->side);
+        }
+        err = hipFreeAsync(part, s);
+        if (err != hipSuccess)
+            return wq_set_error(WQ_EHIP, "wq_assemble_adjoint: scratch release failed: %s", hipGetErrorString(err));
+        return WQ_OK;
+    }
     if (R.n_lblocks > 0) {
         if constexpr (P <= 4) {
             using C = AdjCfg<T, P, WHICH, 16>;
