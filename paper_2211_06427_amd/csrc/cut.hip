@@ -159,6 +159,149 @@ k_cut_remainder(DevRules R, const T* __restrict__ kappa, T* __restrict__ vm, T* 
     }
 }
 
+// Eight consecutive values from LDS (16-byte aligned) in two or four vector loads.
+__device__ inline void lds8(const float* p, float (&r)[8]) {
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const f4 a = *reinterpret_cast<const f4*>(p), b = *reinterpret_cast<const f4*>(p + 4);
+    r[0] = a.x; r[1] = a.y; r[2] = a.z; r[3] = a.w; r[4] = b.x; r[5] = b.y; r[6] = b.z; r[7] = b.w;
+}
+__device__ inline void lds8(const double* p, double (&r)[8]) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const d2 a = *reinterpret_cast<const d2*>(p + 2 * i);
+        r[2 * i] = a.x;
+        r[2 * i + 1] = a.y;
+    }
+}
+
+// k_cut_remainder with every contracted operand a run of P1 consecutive values in LDS, padded
+// to 8 and read with vector loads: the row's 1D weights [d][I_d - e_d][a][k][g], kappa
+// [g1 g2][g3], the stage-1 result [g1 k3][g2] and the stage-2 result [k2 k3][g1].  Fewer LDS
+// instructions, more registers and LDS per workgroup: faster for FP32 at p = 5, 6 (64^3 p = 6:
+// 15.5 ms instead of 18.4), slower at p <= 4 and in FP64, where k_cut_remainder runs.
+template <typename T, int P, int WHICH>
+__global__ void __launch_bounds__(RemCfg<P>::NT)
+k_cut_remainder_v8(DevRules R, const T* __restrict__ kappa, T* __restrict__ vm, T* __restrict__ vk) {
+    using C = RemCfg<P>;
+    constexpr int P1 = C::P1, NP = C::NP, P2 = C::P2, M = 2 * P + 1, M3 = M * M * M, NT = C::NT, SLOT = C::SLOT;
+    constexpr int NSLOT = C::NSLOT, G8 = 8;
+    static_assert(P1 <= G8, "runs of at most 8");
+    constexpr bool MASS = (WHICH & 1) != 0, STIFF = (WHICH & 2) != 0;
+    // per-slot accumulators: inside one pass every output of a slot has one writer, so
+    // they are updated without atomics and summed over the slots at the end
+    __shared__ T s_accm[NSLOT][MASS ? M3 : 1], s_acck[NSLOT][STIFF ? M3 : 1];
+    __shared__ __align__(16) T s_wt[3][P1][2][P1][G8];     // [d][I_d - e_d][a][k][g]
+    __shared__ __align__(16) T s_kap[NSLOT][P2][G8];        // [g1 g2][g3]
+    __shared__ __align__(16) T s_t1[NSLOT][2][P2][G8];      // [v][g1 k3][g2]
+    __shared__ __align__(16) T s_t2[NSLOT][2][P2][G8];      // [v][k2 k3][g1]
+    __shared__ int2 s_list[NP];
+    const int64_t cr = blockIdx.x;
+    const int ra = R.cut_rows[cr];
+    int I[3];
+    unlex3i(R.act2lex[ra], R.nfun, I);
+    const int t = threadIdx.x;
+    const int l0 = R.rem_ptr[cr], nrem = R.rem_ptr[cr + 1] - l0;
+    if (nrem == 0) return;
+    for (int k = t; k < NSLOT * M3; k += NT) {
+        if (MASS) s_accm[k / M3][k % M3] = 0;
+        if (STIFF) s_acck[k / M3][k % M3] = 0;
+    }
+    for (int q = t; q < 3 * P1 * 2 * P2; q += NT) {
+        const int d = q / (P1 * 2 * P2), kI = (q / (2 * P2)) % P1, rest = q % (2 * P2);
+        const int a = rest / P2, k = (rest / P1) % P1, g = rest % P1;
+        const int e = I[d] - kI;
+        s_wt[d][kI][a][k][g] = (e >= 0 && e < R.nel[d]) ? rem_tab<T>(R, d)[((int64_t)e * P1 + kI) * 2 * P2 + rest] : (T)0;
+    }
+    for (int k = t; k < nrem; k += NT) s_list[k] = R.rem_list[l0 + k];
+    __syncthreads();
+    const int sl = t / SLOT, u = t % SLOT;
+    const bool act_u = u < NP;
+    const int d1 = u / P2, d2 = (u / P1) % P1, d3 = u % P1;       // u = (d1, d2, d3)
+    // pipeline: kappa one pass ahead, its slot index two passes ahead
+    T kap_c = 0;
+    int bs_n = 0;
+    if (act_u && sl < nrem) kap_c = kappa[R.blk_slot[(int64_t)s_list[sl].y * NP + u]];
+    if (act_u && sl + NSLOT < nrem) bs_n = R.blk_slot[(int64_t)s_list[sl + NSLOT].y * NP + u];
+    for (int r0 = 0; r0 < nrem; r0 += NSLOT) {
+        const int r = r0 + sl;
+        const bool active = r < nrem;
+        if (active && act_u) s_kap[sl][d1 * P1 + d2][d3] = kap_c;
+        kap_c = (act_u && r + NSLOT < nrem) ? kappa[bs_n] : (T)0;
+        bs_n = (act_u && r + 2 * NSLOT < nrem) ? R.blk_slot[(int64_t)s_list[r + 2 * NSLOT].y * NP + u] : 0;
+        const int pk = active ? s_list[r].x : 0;
+        const int kI0 = pk & 15, kI1 = (pk >> 4) & 15, kI2 = (pk >> 8) & 15;
+        __syncthreads();
+        if (active && act_u) {                      // stage 1: T1[v][g1 k3][g2], u = (g1, g2, k3)
+            T kv[G8], w0[G8], w1[G8];
+            lds8(s_kap[sl][d1 * P1 + d2], kv);
+            lds8(s_wt[2][kI2][0][d3], w0);
+            T a0 = 0, a1 = 0;
+            if (STIFF) lds8(s_wt[2][kI2][1][d3], w1);
+#pragma unroll
+            for (int g3 = 0; g3 < P1; ++g3) {
+                a0 += w0[g3] * kv[g3];
+                if (STIFF) a1 += w1[g3] * kv[g3];
+            }
+            s_t1[sl][0][d1 * P1 + d3][d2] = a0;
+            if (STIFF) s_t1[sl][1][d1 * P1 + d3][d2] = a1;
+        }
+        __syncthreads();
+        if (active && act_u) {                      // stage 2: T2[v][k2 k3][g1], u = (g1, k2, k3)
+            T t0[G8], t1[G8], w0[G8], w1[G8];
+            lds8(s_t1[sl][0][d1 * P1 + d3], t0);
+            lds8(s_wt[1][kI1][0][d2], w0);
+            if (STIFF) {
+                lds8(s_t1[sl][1][d1 * P1 + d3], t1);
+                lds8(s_wt[1][kI1][1][d2], w1);
+            }
+            T m0 = 0, ms = 0;
+#pragma unroll
+            for (int g2 = 0; g2 < P1; ++g2) {
+                m0 += w0[g2] * t0[g2];
+                if (STIFF) ms = fmat(w0[g2], t1[g2], fmat(w1[g2], t0[g2], ms));
+            }
+            s_t2[sl][0][d2 * P1 + d3][d1] = m0;
+            if (STIFF) s_t2[sl][1][d2 * P1 + d3][d1] = ms;
+        }
+        __syncthreads();
+        if (active && act_u) {                      // stage 3: out[k1][k2][k3], u = (k1, k2, k3)
+            T t0[G8], t1[G8], w0[G8], w1[G8];
+            lds8(s_t2[sl][0][d2 * P1 + d3], t0);
+            lds8(s_wt[0][kI0][0][d1], w0);
+            if (STIFF) {
+                lds8(s_t2[sl][1][d2 * P1 + d3], t1);
+                lds8(s_wt[0][kI0][1][d1], w1);
+            }
+            T am = 0, ak = 0;
+#pragma unroll
+            for (int g1 = 0; g1 < P1; ++g1) {
+                am += w0[g1] * t0[g1];
+                if (STIFF) ak = fmat(w0[g1], t1[g1], fmat(w1[g1], t0[g1], ak));
+            }
+            // trial J = e + (d1, d2, d3) = I + (d - kI): local index d - kI + P
+            const int jj = ((d1 - kI0 + P) * M + (d2 - kI1 + P)) * M + (d3 - kI2 + P);
+            if (MASS) s_accm[sl][jj] += am;
+            if (STIFF) s_acck[sl][jj] += ak;
+        }
+        __syncthreads();
+    }
+    const int32_t* pos = R.pos_map + cr * (int64_t)M3;
+    const int64_t rb = R.row_ptr[ra];
+    for (int k = t; k < M3; k += NT) {
+        const int o = pos[k];
+        if (o < 0) continue;
+        T am = 0, ak = 0;
+#pragma unroll
+        for (int i = 0; i < NSLOT; ++i) {
+            if (MASS) am += s_accm[i][k];
+            if (STIFF) ak += s_acck[i][k];
+        }
+        if (MASS) vm[rb + o] += am;
+        if (STIFF) vk[rb + o] += ak;
+    }
+}
+
 // ----------------------------------------------------------------------------------------
 // (ii) octree cut elements
 // ----------------------------------------------------------------------------------------
@@ -1167,6 +1310,17 @@ static constexpr int64_t moment_form_per_elem() {
 // buf == nullptr: scratch from the handle's stream-ordered pool; else the caller's buffer of
 // cap bytes, filled batch by batch (allocation-free variant)
 template <typename T, int P, int WHICH>
+static void launch_remainder(const wq_rules* H, const T* kappa, T* vm, T* vk, hipStream_t s) {
+    const DevRules& R = H->R;
+    if constexpr (sizeof(T) == 4 && P >= 5)
+        hipLaunchKernelGGL((k_cut_remainder_v8<T, P, WHICH>), dim3((unsigned)R.n_cut), dim3(RemCfg<P>::NT), 0, s, R, kappa,
+                           vm, vk);
+    else
+        hipLaunchKernelGGL((k_cut_remainder<T, P, WHICH>), dim3((unsigned)R.n_cut), dim3(RemCfg<P>::NT), 0, s, R, kappa, vm,
+                           vk);
+}
+
+template <typename T, int P, int WHICH>
 static int launch_cut_p(const wq_rules* H, uint32_t parts, const T* kappa, T* vm, T* vk, hipStream_t s, void* buf,
                         size_t cap) {
     const DevRules& R = H->R;
@@ -1174,9 +1328,7 @@ static int launch_cut_p(const wq_rules* H, uint32_t parts, const T* kappa, T* vm
     // moments and local rows (launched below); otherwise the parts run one after the other
     const bool overlap = (parts & WQ_CUT_REMAINDER) && (parts & WQ_CUT_OCTREE) && R.n_cut > 0 && R.n_cut_elems > 0 &&
                          R.levels <= 3 && !buf && H->side;
-    if ((parts & WQ_CUT_REMAINDER) && R.n_cut > 0 && !overlap)
-        hipLaunchKernelGGL((k_cut_remainder<T, P, WHICH>), dim3((unsigned)R.n_cut), dim3(RemCfg<P>::NT), 0, s, R, kappa, vm,
-                           vk);
+    if ((parts & WQ_CUT_REMAINDER) && R.n_cut > 0 && !overlap) launch_remainder<T, P, WHICH>(H, kappa, vm, vk, s);
     if ((parts & WQ_CUT_OCTREE) && R.n_cut_elems > 0) {
         if (R.levels <= 3) {
             const int64_t per = moment_form_per_elem<P>();
@@ -1207,8 +1359,7 @@ static int launch_cut_p(const wq_rules* H, uint32_t parts, const T* kappa, T* vm
                     else
                         hipLaunchKernelGGL((k_cut_local_a2<T, P, WHICH>), dim3((unsigned)(n * (P + 1) * (P + 1))), dim3(256), 0,
                                            H->side, R, R.cut_elems, (const T*)mom, loc, 0);
-                    hipLaunchKernelGGL((k_cut_remainder<T, P, WHICH>), dim3((unsigned)R.n_cut), dim3(RemCfg<P>::NT), 0, s, R,
-                                       kappa, vm, vk);
+                    launch_remainder<T, P, WHICH>(H, kappa, vm, vk, s);
                     if (hipEventRecord(H->ev_join, H->side) != hipSuccess || hipStreamWaitEvent(s, H->ev_join, 0) != hipSuccess) {
                         (void)hipGetLastError();
                         (void)hipStreamSynchronize(H->side);
@@ -1217,8 +1368,7 @@ static int launch_cut_p(const wq_rules* H, uint32_t parts, const T* kappa, T* vm
                                        (const T*)loc, vm, vk, 0, (int)n, (int64_t)0);
                 } else {
                     (void)hipGetLastError();
-                    hipLaunchKernelGGL((k_cut_remainder<T, P, WHICH>), dim3((unsigned)R.n_cut), dim3(RemCfg<P>::NT), 0, s, R,
-                                       kappa, vm, vk);
+                    launch_remainder<T, P, WHICH>(H, kappa, vm, vk, s);
                     launch_moment_form<T, P, WHICH>(H, kappa, vm, vk, mom, R.n_cut_elems, s);
                 }
             } else {
