@@ -69,7 +69,8 @@ class Problem:
     # --- derived data ---------------------------------------------------------------
     def slots(self, with_octree=True) -> Slots:
         if self._slots is None:
-            self._slots = Slots(self.lines, self.dom, self.wl.octree_levels)
+            self._slots = Slots(self.lines, self.dom, self.wl.octree_levels,
+                                fit=getattr(self.wl, "cut_rule", "octree") == "fit")
         if with_octree:
             self._slots.enumerate_octree()
         return self._slots

@@ -29,6 +29,8 @@ import math
 
 import numpy as np
 
+from .spline import gauss_legendre
+
 OUT, IN, CUT = 0, 1, 2
 
 
@@ -238,6 +240,28 @@ def octree_points(lines, ls, e, levels: int):
     return np.concatenate(xs), np.concatenate(ws)
 
 
+def fitted_rule(lines, e, pts, w):
+    """A rule of NK^3 = (2p+1)^3 points for cut element e that integrates every polynomial of
+    degree <= 2p in each variable as the octree rule (pts, w) does: the tensor Gauss-Legendre
+    points of NK nodes on the element, weights from the Legendre moments of the octree rule
+    (m = (V x V x V) w_fit, V[k][g] = L_k(node g), solved direction by direction).  The
+    products B_a B_b and their gradients' products lie in that space, so with kappa = 1 the cut
+    element's matrices are the octree's."""
+    p = lines[0].p
+    nk = 2 * p + 1
+    xi, _ = gauss_legendre(nk)
+    V = np.polynomial.legendre.legvander(xi, 2 * p).T                 # [k][g]
+    lo = [lines[d].lo + e[d] * lines[d].h for d in range(3)]
+    t = [2.0 * (pts[:, d] - lo[d]) / lines[d].h - 1.0 for d in range(3)]
+    L = [np.polynomial.legendre.legvander(t[d], 2 * p) for d in range(3)]   # [q][k]
+    m = np.einsum("q,qa,qb,qc->abc", w, L[0], L[1], L[2])
+    Vi = np.linalg.inv(V)
+    wf = np.einsum("ai,bj,ck,ijk->abc", Vi, Vi, Vi, m).ravel()          # Vi[g][k]
+    c1 = [lo[d] + (1.0 + xi) / 2.0 * lines[d].h for d in range(3)]
+    xf = np.stack(np.meshgrid(*c1, indexing="ij"), -1).reshape(-1, 3)
+    return xf, wf
+
+
 # ----------------------------------------------------------------------------------------
 # slot layout (kappa input / dL/dkappa output)
 # ----------------------------------------------------------------------------------------
@@ -250,11 +274,12 @@ class Slots:
              coordinates are WQ points is always addressed through the grid, so its
              block entry is never used;
     [octree] for every cut element in lexicographic order, its octree points in
-             the order of octree_points().
+             the order of octree_points() (fit = True: the NK^3 points of its fitted rule,
+             fitted_rule()).
     """
 
-    def __init__(self, lines, dom: Domain, levels: int):
-        self.lines, self.dom, self.levels = lines, dom, levels
+    def __init__(self, lines, dom: Domain, levels: int, fit: bool = False):
+        self.lines, self.dom, self.levels, self.fit = lines, dom, levels, fit
         p = lines[0].p
         self.nx = tuple(len(l.X) for l in lines)
         self.n_grid = int(np.prod(self.nx))
@@ -281,7 +306,8 @@ class Slots:
 
     def octree(self, e):
         if e not in self._oct:
-            self._oct[e] = octree_points(self.lines, self.dom.ls, e, self.levels)
+            pts, w = octree_points(self.lines, self.dom.ls, e, self.levels)
+            self._oct[e] = fitted_rule(self.lines, e, pts, w) if self.fit else (pts, w)
         return self._oct[e]
 
     def gauss_slot(self, eg):

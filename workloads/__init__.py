@@ -64,6 +64,7 @@ class Workload:
     lo: tuple = (0.0, 0.0, 0.0)
     hi: tuple = (1.0, 1.0, 1.0)
     octree_levels: int = 3
+    cut_rule: str = "octree"   # "octree" | "fit": cut elements by the octree or by its fitted rule
     notes: str = field(default="", compare=False)
 
 
@@ -85,11 +86,17 @@ def workload(name: str) -> Workload:
 
 
 def custom(nel, degree, levelset=LevelSet(), kappa="one", seed=0, octree_levels=3,
-           lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0)) -> Workload:
+           lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), cut_rule="octree") -> Workload:
     if isinstance(nel, int):
         nel = (nel, nel, nel)
     return Workload(f"custom{nel}_p{degree}", tuple(nel), degree, levelset, kappa, seed,
-                    octree_levels=octree_levels, lo=tuple(lo), hi=tuple(hi))
+                    octree_levels=octree_levels, lo=tuple(lo), hi=tuple(hi), cut_rule=cut_rule)
+
+
+def with_cut_rule(w: Workload, cut_rule: str) -> Workload:
+    """The same workload with the cut elements integrated by the octree or its fitted rule."""
+    import dataclasses
+    return dataclasses.replace(w, name=f"{w.name}_{cut_rule}", cut_rule=cut_rule)
 
 
 # ----------------------------------------------------------------------------------------
