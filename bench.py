@@ -205,9 +205,9 @@ def cpu_baseline(wl, nrows):
 
 def paper_sweep(args):
     """Section 3.1 / 3.2: mass matrix of the cut cube [-1,1]^3 (kappa = 1, FP64), L2 projection of
-    f = sin(2xz) cos(3yz) with extended B-splines (Jacobi PCG to a relative residual of 1e-14),
-    relative L2 error, for the three schemes: Ref (element-by-element Gauss), Hybrid Gauss and
-    DWQ.  Times are HIP-event means over repeated calls; the Ref load vector is the row sums of
+    f = sin(2xz) cos(3yz) with extended B-splines (PCG to a relative residual of 1e-14), relative
+    L2 error, for the three schemes: Ref (element-by-element Gauss), Hybrid Gauss and DWQ, plus
+    DWQ with the fitted cut-element rule.  Times are HIP-event means over repeated calls; the Ref load vector is the row sums of
     its mass matrix with kappa = f."""
     import torch
 
@@ -223,9 +223,10 @@ def paper_sweep(args):
             rec = {"h": h, "p": p}
             nrep = 5 if h <= 32 else 2
             ref_rules = None
-            for scheme, hyb in (("dwq", False), ("hybrid", True)):
+            for scheme, hyb in (("dwq", False), ("hybrid", True), ("dwq_fit", False)):
+                wls = W.with_cut_rule(wl, "fit") if scheme == "dwq_fit" else wl
                 t0 = time.perf_counter()
-                R = Rules.from_workload(wl, hybrid_gauss=hyb)
+                R = Rules.from_workload(wls, hybrid_gauss=hyb)
                 torch.cuda.synchronize()
                 build_ms = (time.perf_counter() - t0) * 1e3
                 one = torch.ones(R.n_kappa, dtype=f64, device=dev)
@@ -264,7 +265,7 @@ def paper_sweep(args):
                 rec[scheme] = r
                 print(f"# h={h} p={p} {scheme}: err {r['rel_l2_error']:.3e} mass {r['mass_ms']:.3f} ms "
                       f"cg {it}", file=sys.stderr, flush=True)
-                if not hyb:
+                if scheme == "dwq":
                     ref_rules, ref_ext, ref_f, ref_fg = R, ext, f, fg
                 else:
                     del R
@@ -448,6 +449,21 @@ def main():
         step_g()
         schemes[k]["gauss_rows_ms"] = timed(step_g, nrep, torch)
     del Rg, kg_slots
+    # DWQ with the fitted cut-element rule ((2p+1)^3 points per cut element instead of the octree)
+    Rf = Rules.from_workload(W.with_cut_rule(wl, "fit"))
+    kf_slots = W.kappa_at(wl, Rf.kappa_xyz())
+    for k in ("f64", "f32"):
+        vm, vk = vals[k]
+        kr = kf_slots.to(dt[k])
+
+        def step_f():
+            Rf.assemble_rows(kr, vm, vk)
+            Rf.cut_assemble(kr, vm, vk)
+
+        step_f()
+        schemes[k]["dwq_fit_ms"] = timed(step_f, nrep, torch)
+    schemes["fit_kappa_slots"] = {"octree": R.n_kappa, "fit": Rf.n_kappa}
+    del Rf, kf_slots
 
     # --- rooflines (durations from the timed region) -----------------------------------
     esz = 8 if main_dt == "f64" else 4

@@ -77,7 +77,7 @@ typedef struct {
 
 typedef struct {
     int32_t octree_levels;   /* depth of the cut-element octree, 0..5 (default 3) */
-    int32_t flags;           /* 0, WQ_OPT_HYBRID_GAUSS or WQ_OPT_GAUSS_ROWS */
+    int32_t flags;           /* 0 or WQ_OPT_HYBRID_GAUSS | WQ_OPT_GAUSS_ROWS | WQ_OPT_MOMENT_FIT */
 } wq_options;
 
 /* Option flag: the "Hybrid Gauss" scheme of Section 3.1 (list of compared schemes) instead of
@@ -91,7 +91,16 @@ typedef struct {
  * Gauss assembly (gauss_assemble), formed row by row without atomics, so that the gain of
  * weighted quadrature can be measured on the same row-owned engineering.  The slot layout
  * then holds a Gauss block for every interior element; n_rows_interior is 0. */
-enum { WQ_OPT_HYBRID_GAUSS = 1, WQ_OPT_GAUSS_ROWS = 2 };
+enum { WQ_OPT_HYBRID_GAUSS = 1, WQ_OPT_GAUSS_ROWS = 2, WQ_OPT_MOMENT_FIT = 4 };
+
+/* Option flag WQ_OPT_MOMENT_FIT (cheaper cut integration; the paper's cut-element scheme is
+ * higher order but costly, Section 3.2): every cut element's octree rule is replaced by a rule on
+ * the NK^3 = (2p+1)^3 tensor Gauss-Legendre points of the element whose weights reproduce the
+ * octree rule on every polynomial of degree <= 2p in each variable (fitted at build time from
+ * the octree's moments).  With kappa = 1 the matrices are the octree rule's; kappa is then needed
+ * at NK^3 points per cut element instead of (p+1)^3 per octree leaf.  The octree slots of the
+ * layout become these points (n_octree = n_cut_elems * NK^3, lexicographic per cut element) and
+ * octree_w their weights (which may be negative).  Octree depth <= 3 only. */
 
 typedef struct wq_rules wq_rules;   /* opaque; owns its device buffers */
 

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libwqfd.so")
 
 WQ_F64, WQ_F32, WQ_BF16X3 = 0, 1, 2
-WQ_OPT_HYBRID_GAUSS, WQ_OPT_GAUSS_ROWS = 1, 2
+WQ_OPT_HYBRID_GAUSS, WQ_OPT_GAUSS_ROWS, WQ_OPT_MOMENT_FIT = 1, 2, 4
 WQ_MASS, WQ_STIFF = 1, 2
 WQ_CUT_REMAINDER, WQ_CUT_OCTREE = 4, 8
 STATUS = {0: "WQ_OK", -1: "WQ_EINVAL", -2: "WQ_ENOMEM", -3: "WQ_EHIP", -4: "WQ_ESINGULAR", -5: "WQ_EUNSUPPORTED"}

@@ -35,11 +35,14 @@ class Rules:
     """Kappa-independent data of one mesh + domain (built on the GPU, FP64)."""
 
     def __init__(self, nel, degree, levelset=None, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), octree_levels=3,
-                 device=None, hybrid_gauss=False, gauss_rows=False):
+                 device=None, hybrid_gauss=False, gauss_rows=False, cut_rule="octree"):
         """hybrid_gauss=True: the Hybrid Gauss scheme (no DWQ boxes; the regular support of
         every cut row goes through element Gauss with sum factorization).  gauss_rows=True: no
         weighted quadrature; every row by element Gauss with sum factorization (the
-        conventional Gauss matrices, row-owned and atomic-free; for comparison)."""
+        conventional Gauss matrices, row-owned and atomic-free; for comparison).  cut_rule="fit":
+        cut elements by the rule fitted to the octree on (2p+1)^3 Gauss points per element."""
+        if cut_rule not in ("octree", "fit"):
+            raise ValueError(f"cut_rule must be 'octree' or 'fit', got {cut_rule!r}")
         lib = L.load()
         if isinstance(nel, int):
             nel = (nel, nel, nel)
@@ -52,7 +55,9 @@ class Rules:
             ls.n = (C.c_double * 3)(*levelset.n)
             ls.r0, ls.r1 = float(levelset.r0), float(levelset.r1)
         opts = L.WqOptions(int(octree_levels), (L.WQ_OPT_HYBRID_GAUSS if hybrid_gauss else 0) |
-                           (L.WQ_OPT_GAUSS_ROWS if gauss_rows else 0))
+                           (L.WQ_OPT_GAUSS_ROWS if gauss_rows else 0) |
+                           (L.WQ_OPT_MOMENT_FIT if cut_rule == "fit" else 0))
+        self.cut_rule = cut_rule
         self.hybrid_gauss = bool(hybrid_gauss)
         self.gauss_rows = bool(gauss_rows)
         h = C.c_void_p()
@@ -74,7 +79,8 @@ class Rules:
 
     @classmethod
     def from_workload(cls, wl, device=None, hybrid_gauss=False, gauss_rows=False):
-        return cls(wl.nel, wl.degree, wl.levelset, wl.lo, wl.hi, wl.octree_levels, device, hybrid_gauss, gauss_rows)
+        return cls(wl.nel, wl.degree, wl.levelset, wl.lo, wl.hi, wl.octree_levels, device, hybrid_gauss, gauss_rows,
+                   getattr(wl, "cut_rule", "octree"))
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -955,6 +955,56 @@ k_adj_leaves(DevRules R, const T* __restrict__ part, T* __restrict__ dk) {
     }
 }
 
+template <typename T> __device__ inline const T* fit_v_a(const DevRules& R);
+template <> __device__ inline const double* fit_v_a<double>(const DevRules& R) { return R.fit_V64; }
+template <> __device__ inline const float* fit_v_a<float>(const DevRules& R) { return R.fit_V32; }
+
+// Fitted cut rule: dkappa at the NK^3 points of a cut element, w_g sum_k Gmom[k] B_k1(tau_g1)
+// B_k2(tau_g2) B_k3(tau_g3), Gmom the element's moment cotangent (sum of its a3 shares);
+// contracted direction by direction, one workgroup per cut element (it owns the points).
+template <typename T, int P>
+__global__ void __launch_bounds__(256)
+k_adj_fit(DevRules R, const T* __restrict__ part, T* __restrict__ dk) {
+    using C = MomCfg<P>;
+    constexpr int P1 = C::P1, NK = C::NK, NK2 = C::NK2, NK3 = C::NK3, NT = C::NT;
+    __shared__ T s_a[NK3], s_b[NK3];
+    __shared__ T s_v[NK * NK];
+    const int64_t ce = blockIdx.x;
+    const int t = threadIdx.x;
+    for (int i = t; i < NK * NK; i += NT) s_v[i] = fit_v_a<T>(R)[i];
+    for (int i = t; i < NK3; i += NT) {
+        T g = 0;
+#pragma unroll
+        for (int a3 = 0; a3 < P1; ++a3) g += part[(ce * P1 + a3) * NK3 + i];
+        s_a[i] = g;                                 // [k1][k2 k3]
+    }
+    __syncthreads();
+    for (int i = t; i < NK3; i += NT) {             // [g1][k2 k3]
+        const int g1 = i / NK2, k23 = i % NK2;
+        T v = 0;
+#pragma unroll
+        for (int k1 = 0; k1 < NK; ++k1) v += s_v[k1 * NK + g1] * s_a[k1 * NK2 + k23];
+        s_b[i] = v;
+    }
+    __syncthreads();
+    for (int i = t; i < NK3; i += NT) {             // [g1 g2][k3]
+        const int g1 = i / NK2, g2 = (i / NK) % NK, k3 = i % NK;
+        T v = 0;
+#pragma unroll
+        for (int k2 = 0; k2 < NK; ++k2) v += s_v[k2 * NK + g2] * s_b[(g1 * NK + k2) * NK + k3];
+        s_a[i] = v;
+    }
+    __syncthreads();
+    const int64_t s0 = R.n_grid + R.n_block + ce * NK3;
+    for (int i = t; i < NK3; i += NT) {             // [g1 g2][g3]
+        const int g12 = i / NK, g3 = i % NK;
+        T v = 0;
+#pragma unroll
+        for (int k3 = 0; k3 < NK; ++k3) v += s_v[k3 * NK + g3] * s_a[g12 * NK + k3];
+        dk[s0 + i] = oct_wt_a<T>(R)[ce * NK3 + i] * v;
+    }
+}
+
 // The octree part writes only the octree slots (one owner each) and the other parts add into
 // the grid and block slots with atomics, so with a second stream the octree part runs beside
 // the rest: forked after the zero fill, joined before the call returns.
@@ -968,7 +1018,10 @@ static int launch_adj_octree(const wq_rules* H, const T* gm, const T* gk, T* dk,
     else
         hipLaunchKernelGGL((k_adj_local_a2<T, P, WHICH>), dim3((unsigned)(R.n_cut_elems * C::P1)), dim3(256), 0, s, R,
                            H->act2cut, gm, gk, part);
-    hipLaunchKernelGGL((k_adj_leaves<T, P>), dim3((unsigned)R.n_cut_elems), dim3(256), 0, s, R, (const T*)part, dk);
+    if (R.fit)
+        hipLaunchKernelGGL((k_adj_fit<T, P>), dim3((unsigned)R.n_cut_elems), dim3(256), 0, s, R, (const T*)part, dk);
+    else
+        hipLaunchKernelGGL((k_adj_leaves<T, P>), dim3((unsigned)R.n_cut_elems), dim3(256), 0, s, R, (const T*)part, dk);
     return WQ_OK;
 }
 
@@ -1040,7 +1093,10 @@ static int launch_adj_p(const wq_rules* H, const T* gm, const T* gk, T* dk, hipS
                 else
                     hipLaunchKernelGGL((k_adj_local_a2<T, P, WHICH>), dim3((unsigned)(R.n_cut_elems * C::P1)), dim3(256), 0,
                                        s, R, H->act2cut, gm, gk, part);
-                hipLaunchKernelGGL((k_adj_leaves<T, P>), dim3((unsigned)R.n_cut_elems), dim3(256), 0, s, R, (const T*)part, dk);
+                if (R.fit)
+        hipLaunchKernelGGL((k_adj_fit<T, P>), dim3((unsigned)R.n_cut_elems), dim3(256), 0, s, R, (const T*)part, dk);
+    else
+        hipLaunchKernelGGL((k_adj_leaves<T, P>), dim3((unsigned)R.n_cut_elems), dim3(256), 0, s, R, (const T*)part, dk);
                 err = hipFreeAsync(part, s);
                 if (err != hipSuccess)
                     return wq_set_error(WQ_EHIP, "wq_assemble_adjoint: scratch release failed: %s", hipGetErrorString(err));

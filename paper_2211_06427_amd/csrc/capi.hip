@@ -97,8 +97,11 @@ int wq_build_rules(const wq_mesh* mesh, const wq_levelset* ls, const wq_options*
     if (opts) o = *opts;
     if (o.octree_levels < 0 || o.octree_levels > 5)
         return wq_set_error(WQ_EINVAL, "wq_build_rules: octree_levels must be in 0..5 (got %d)", o.octree_levels);
-    if (o.flags & ~(WQ_OPT_HYBRID_GAUSS | WQ_OPT_GAUSS_ROWS))
+    if (o.flags & ~(WQ_OPT_HYBRID_GAUSS | WQ_OPT_GAUSS_ROWS | WQ_OPT_MOMENT_FIT))
         return wq_set_error(WQ_EINVAL, "wq_build_rules: unknown option flags 0x%x", o.flags);
+    if ((o.flags & WQ_OPT_MOMENT_FIT) && o.octree_levels > 3)
+        return wq_set_error(WQ_EUNSUPPORTED, "wq_build_rules: the fitted cut rule needs octree_levels <= 3 (got %d)",
+                            o.octree_levels);
     return build_rules(mesh, ls, &o, (hipStream_t)stream, out);
 }
 

@@ -81,6 +81,11 @@ struct DevRules {
     const float* bern_q32[3];
     const double* bern_i64;             // [interval][k][g]: degree-2p Bernstein values at octree Gauss points
     const float* bern_i32;
+    // fitted cut-element rule (WQ_OPT_MOMENT_FIT): the NK^3 tensor Gauss points of every cut
+    // element replace its octree points in the slot layout; oct_w then holds their weights
+    int fit;
+    const double* fit_V64;              // [k][g]: degree-2p Bernstein polynomial k at fitted node g
+    const float* fit_V32;
     int64_t n_cut_elems, n_cells;
     // slots
     int64_t n_grid, n_block, n_kappa;

@@ -690,6 +690,60 @@ k_cut_moments(DevRules R, const T* __restrict__ kappa, T* __restrict__ mom, int 
     }
 }
 
+template <typename T> __device__ inline const T* fit_v(const DevRules& R);
+template <> __device__ inline const double* fit_v<double>(const DevRules& R) { return R.fit_V64; }
+template <> __device__ inline const float* fit_v<float>(const DevRules& R) { return R.fit_V32; }
+
+// Moments of one cut element on its fitted rule: Mom[k1 k2 k3] = sum_g w_g kappa_g
+// B_k1(tau_g1) B_k2(tau_g2) B_k3(tau_g3) over the NK^3 tensor points, contracted direction by
+// direction (3, then 2, then 1).  One workgroup per cut element from ce0 on.
+template <typename T, int P>
+__global__ void __launch_bounds__(256)
+k_cut_moments_fit(DevRules R, const T* __restrict__ kappa, T* __restrict__ mom, int ce0) {
+    using C = MomCfg<P>;
+    constexpr int NK = C::NK, NK2 = C::NK2, NK3 = C::NK3, NT = C::NT;
+    __shared__ T s_a[NK3], s_b[NK3];
+    __shared__ T s_v[NK * NK];
+    const int64_t ce = (int64_t)ce0 + blockIdx.x;
+    const int t = threadIdx.x;
+    const int64_t s0 = R.n_grid + R.n_block + ce * NK3;
+    for (int i = t; i < NK * NK; i += NT) s_v[i] = fit_v<T>(R)[i];
+    for (int i = t; i < NK3; i += NT) s_a[i] = oct_wt<T>(R)[ce * NK3 + i] * kappa[s0 + i];
+    __syncthreads();
+    for (int i = t; i < NK3; i += NT) {             // [g1 g2][k3]
+        const int g12 = i / NK, k3 = i % NK;
+        T v = 0;
+#pragma unroll
+        for (int g3 = 0; g3 < NK; ++g3) v += s_v[k3 * NK + g3] * s_a[g12 * NK + g3];
+        s_b[i] = v;
+    }
+    __syncthreads();
+    for (int i = t; i < NK3; i += NT) {             // [g1][k2 k3]
+        const int g1 = i / NK2, k2 = (i / NK) % NK, k3 = i % NK;
+        T v = 0;
+#pragma unroll
+        for (int g2 = 0; g2 < NK; ++g2) v += s_v[k2 * NK + g2] * s_b[(g1 * NK + g2) * NK + k3];
+        s_a[i] = v;
+    }
+    __syncthreads();
+    for (int i = t; i < NK3; i += NT) {             // [k1][k2 k3]
+        const int k1 = i / NK2, k23 = i % NK2;
+        T v = 0;
+#pragma unroll
+        for (int g1 = 0; g1 < NK; ++g1) v += s_v[k1 * NK + g1] * s_a[g1 * NK2 + k23];
+        mom[(int64_t)blockIdx.x * NK3 + i] = v;
+    }
+}
+
+// moments of cut elements [c0, c0 + n) by the octree or the fitted rule
+template <typename T, int P>
+static void launch_moments(const wq_rules* H, const T* kappa, T* mom, int64_t c0, int64_t n, hipStream_t s) {
+    if (H->R.fit)
+        hipLaunchKernelGGL((k_cut_moments_fit<T, P>), dim3((unsigned)n), dim3(256), 0, s, H->R, kappa, mom, (int)c0);
+    else
+        hipLaunchKernelGGL((k_cut_moments<T, P>), dim3((unsigned)n), dim3(256), 0, s, H->R, kappa, mom, (int)c0);
+}
+
 
 // k_cut_local: one workgroup per (cut element, a3) contracts Mom with the Q tables
 // (directions 3 and 2 on the vector ALU, direction 1 on matrix cores) and stores the local
@@ -1209,7 +1263,7 @@ static int launch_gauss_p(const wq_rules* H, const T* kg, const T* kappa, T* vm,
     }
     if (nc > 0) {
         T* mc = mom + (size_t)ni * C::NK3;
-        hipLaunchKernelGGL((k_cut_moments<T, P>), dim3((unsigned)nc), dim3(256), 0, s, R, kappa, mc, 0);
+        launch_moments<T, P>(H, kappa, mc, 0, nc, s);
         scatter(R.cut_elems, nc, (const T*)mc);
     }
     err = hipFreeAsync(mom, s);
@@ -1280,7 +1334,7 @@ static void launch_moment_form(const wq_rules* H, const T* kappa, T* vm, T* vk, 
         const int64_t c1 = c0 + nb < nce ? c0 + nb : nce, n = c1 - c0;
         T* mom = buf;
         T* loc = buf + n * C::NK3;
-        hipLaunchKernelGGL((k_cut_moments<T, P>), dim3((unsigned)n), dim3(256), 0, s, R, kappa, mom, (int)c0);
+        launch_moments<T, P>(H, kappa, mom, c0, n, s);
         if constexpr (P <= 4)
             hipLaunchKernelGGL((k_cut_local<T, P, WHICH>), dim3((unsigned)(n * (P + 1))), dim3(256), 0, s, R, R.cut_elems,
                                (const T*)mom, loc, nullptr, nullptr, nullptr, (int)c0);
@@ -1352,7 +1406,7 @@ static int launch_cut_p(const wq_rules* H, uint32_t parts, const T* kappa, T* vm
                 T* loc = mom + n * C::NK3;
                 std::lock_guard<std::mutex> lock(*H->side_mu);
                 if (hipEventRecord(H->ev_fork, s) == hipSuccess && hipStreamWaitEvent(H->side, H->ev_fork, 0) == hipSuccess) {
-                    hipLaunchKernelGGL((k_cut_moments<T, P>), dim3((unsigned)n), dim3(256), 0, H->side, R, kappa, mom, 0);
+                    launch_moments<T, P>(H, kappa, mom, 0, n, H->side);
                     if constexpr (P <= 4)
                         hipLaunchKernelGGL((k_cut_local<T, P, WHICH>), dim3((unsigned)(n * (P + 1))), dim3(256), 0, H->side, R,
                                            R.cut_elems, (const T*)mom, loc, nullptr, nullptr, nullptr, 0);
@@ -1415,4 +1469,24 @@ template int launch_cut<double>(const wq_rules*, uint32_t, uint32_t, const doubl
 #ifndef WQ_ONLY_F64
 template int launch_cut<float>(const wq_rules*, uint32_t, uint32_t, const float*, float*, float*, hipStream_t, void*,
                                size_t);
+#endif
+
+#ifndef WQ_ONLY_F32
+// octree moments of every cut element in the basis of table (interval layout of bern_i: the
+// rule build fits the cut rule from Legendre moments)
+int launch_octree_moments_f64(const wq_rules* H, const double* table, const double* kappa, double* mom, hipStream_t s) {
+    const int64_t n = H->R.n_cut_elems;
+    if (n == 0) return WQ_OK;
+    DevRules R = H->R;
+    R.bern_i64 = table;
+    switch (R.p) {
+        case 1: hipLaunchKernelGGL((k_cut_moments<double, 1>), dim3((unsigned)n), dim3(256), 0, s, R, kappa, mom, 0); break;
+        case 2: hipLaunchKernelGGL((k_cut_moments<double, 2>), dim3((unsigned)n), dim3(256), 0, s, R, kappa, mom, 0); break;
+        case 3: hipLaunchKernelGGL((k_cut_moments<double, 3>), dim3((unsigned)n), dim3(256), 0, s, R, kappa, mom, 0); break;
+        case 4: hipLaunchKernelGGL((k_cut_moments<double, 4>), dim3((unsigned)n), dim3(256), 0, s, R, kappa, mom, 0); break;
+        case 5: hipLaunchKernelGGL((k_cut_moments<double, 5>), dim3((unsigned)n), dim3(256), 0, s, R, kappa, mom, 0); break;
+        default: hipLaunchKernelGGL((k_cut_moments<double, 6>), dim3((unsigned)n), dim3(256), 0, s, R, kappa, mom, 0); break;
+    }
+    return WQ_OK;
+}
 #endif

@@ -544,7 +544,11 @@ __global__ __launch_bounds__(256) void k_err_octree(DevRules R, const double* xy
     load_coefs<P>(R, e, u, c);
     __syncthreads();
     double se = 0.0, sf = 0.0;
-    const int64_t q0 = (int64_t)R.cell_begin[ce] * NP, q1 = (int64_t)R.cell_begin[ce + 1] * NP;
+    // points of the cut element: its octree leaves' Gauss points, or the NK^3 points of its
+    // fitted rule
+    constexpr int NK3 = (2 * P + 1) * (2 * P + 1) * (2 * P + 1);
+    const int64_t q0 = R.fit ? ce * NK3 : (int64_t)R.cell_begin[ce] * NP;
+    const int64_t q1 = R.fit ? (ce + 1) * NK3 : (int64_t)R.cell_begin[ce + 1] * NP;
     for (int64_t q = q0 + threadIdx.x; q < q1; q += blockDim.x) {
         const double w = R.oct_w[q];
         if (w == 0.0) continue;

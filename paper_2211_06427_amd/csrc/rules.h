@@ -112,3 +112,8 @@ struct Builder {
 
 int build_rules(const wq_mesh* mesh, const wq_levelset* ls, const wq_options* opts, hipStream_t stream,
                 wq_rules** out);
+
+// octree moments of every cut element with an FP64 kappa in the basis whose interval values
+// table holds (layout of the Bernstein interval table; cut.hip).  The rule build fits the cut
+// rule from Legendre moments.
+int launch_octree_moments_f64(const wq_rules* H, const double* table, const double* kappa, double* mom, hipStream_t s);

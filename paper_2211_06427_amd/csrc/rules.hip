@@ -1010,6 +1010,103 @@ __global__ void k_octree_weights(DevRules R, const double* gxi, const double* gw
     xyz[s * 3 + 0] = x[0]; xyz[s * 3 + 1] = x[1]; xyz[s * 3 + 2] = x[2];
 }
 
+// Legendre polynomial L_k(x), k <= 2p, by the three-term recurrence
+__device__ inline double legendre(int k, double x) {
+    double l0 = 1.0, l1 = x;
+    if (k == 0) return l0;
+    for (int n = 1; n < k; ++n) {
+        const double l2 = ((2 * n + 1) * x * l1 - n * l0) / (n + 1);
+        l0 = l1; l1 = l2;
+    }
+    return l1;
+}
+
+// L[(iv * (2p+1) + k) * P1 + g]: L_k(2t - 1) at the g-th Gauss point t of octree interval iv
+// (the layout of k_bern_intervals); the fitted rule's moments are taken in this basis.
+__global__ void k_leg_intervals(DevRules R, const double* gxi, double* L) {
+    const int p = R.p, p1 = p + 1, nk = 2 * p + 1;
+    const int ni = (2 << R.levels) - 1;
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= ni * nk * p1) return;
+    const int g = id % p1, k = (id / p1) % nk, iv = id / (p1 * nk);
+    int dep = 0;
+    while ((2 << dep) - 1 <= iv) ++dep;
+    const int off = iv - ((1 << dep) - 1);
+    const double t = (off + (1.0 + gxi[g]) / 2.0) / (double)(1 << dep);
+    L[id] = legendre(k, 2.0 * t - 1.0);
+}
+
+// Fitted cut rule tables.  V[k][g] = B_k(tau_g), the degree-2p Bernstein polynomials at the NK
+// Gauss nodes tau_g = (1 + xi_g) / 2 of the element (the assembly forms Bernstein moments on the
+// fitted points with it).  Ainv[g][k] = W_g (2k + 1) / 2 L_k(xi_g) is the inverse of the Legendre
+// matrix [k][g] = L_k(xi_g): the NK-point Gauss rule integrates L_k L_j (degree <= 4p < 2 NK)
+// exactly, so sum_g L_k(xi_g) Ainv[g][j] is the orthogonality relation.  The fitted weights are
+// Ainv applied to the Legendre moments in each direction; Legendre moments of a positive rule are
+// bounded by its total weight and Ainv's entries by (2p + 1) / 2 * W_g, so nothing cancels
+// beyond the final sums (an inverse Bernstein matrix grows with the degree).
+__global__ void k_fit_tables(int p, const double* xi, const double* wg, double* V, double* Ainv) {
+    const int nk = 2 * p + 1;
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= nk * nk) return;
+    const int a = id / nk, b = id % nk;
+    V[id] = bernstein(2 * p, a, 0.5 * (1.0 + xi[b]));              // [k = a][g = b]
+    Ainv[id] = wg[a] * (2 * b + 1) * 0.5 * legendre(b, xi[a]);      // [g = a][k = b]
+}
+
+// fitted weights of one cut element: w[g1 g2 g3] = sum_k Ainv[g1][k1] Ainv[g2][k2] Ainv[g3][k3] m[k],
+// m the Legendre moments of the element's octree rule (kappa = 1); one workgroup per element
+__global__ void __launch_bounds__(256) k_fit_weights(int p, const double* Ainv, const double* m, double* w) {
+    const int nk = 2 * p + 1, nk2 = nk * nk, nk3 = nk2 * nk;
+    __shared__ double s_a[WQ_MMAX * WQ_MMAX * WQ_MMAX], s_b[WQ_MMAX * WQ_MMAX * WQ_MMAX];
+    __shared__ double s_ai[WQ_MMAX * WQ_MMAX];
+    const int64_t ce = blockIdx.x;
+    for (int i = threadIdx.x; i < nk2; i += blockDim.x) s_ai[i] = Ainv[i];
+    for (int i = threadIdx.x; i < nk3; i += blockDim.x) s_a[i] = m[ce * nk3 + i];
+    __syncthreads();
+    for (int i = threadIdx.x; i < nk3; i += blockDim.x) {      // [k1 k2][g3]
+        const int k12 = i / nk, g3 = i % nk;
+        double v = 0.0;
+        for (int k3 = 0; k3 < nk; ++k3) v += s_ai[g3 * nk + k3] * s_a[k12 * nk + k3];
+        s_b[i] = v;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nk3; i += blockDim.x) {      // [k1][g2 g3]
+        const int k1 = i / nk2, g2 = (i / nk) % nk, g3 = i % nk;
+        double v = 0.0;
+        for (int k2 = 0; k2 < nk; ++k2) v += s_ai[g2 * nk + k2] * s_b[(k1 * nk + k2) * nk + g3];
+        s_a[i] = v;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nk3; i += blockDim.x) {      // [g1][g2 g3]
+        const int g1 = i / nk2, g23 = i % nk2;
+        double v = 0.0;
+        for (int k1 = 0; k1 < nk; ++k1) v += s_ai[g1 * nk + k1] * s_a[k1 * nk2 + g23];
+        w[ce * nk3 + i] = v;
+    }
+}
+
+// coordinates of the fitted points: slot n_grid + n_block + ce * NK^3 + g, g lexicographic
+__global__ void k_fit_xyz(DevRules R, int64_t nce, const int32_t* cut_elems, const double* xi, int64_t base,
+                          double* xyz) {
+    const int nk = 2 * R.p + 1, nk3 = nk * nk * nk;
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= nce * nk3) return;
+    const int64_t ce = id / nk3;
+    const int g = (int)(id % nk3), g1 = g / (nk * nk), g2 = (g / nk) % nk, g3 = g % nk;
+    const int64_t eid = cut_elems[ce];
+    const int e3 = (int)(eid % R.nel[2]), e2 = (int)((eid / R.nel[2]) % R.nel[1]);
+    const int e1 = (int)(eid / ((int64_t)R.nel[1] * R.nel[2]));
+    const int64_t sl = base + id;
+    xyz[sl * 3 + 0] = R.lo[0] + (e1 + 0.5 * (1.0 + xi[g1])) * R.h[0];
+    xyz[sl * 3 + 1] = R.lo[1] + (e2 + 0.5 * (1.0 + xi[g2])) * R.h[1];
+    xyz[sl * 3 + 2] = R.lo[2] + (e3 + 0.5 * (1.0 + xi[g3])) * R.h[2];
+}
+
+__global__ void k_fill_f64(double* a, int64_t n, double v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = v;
+}
+
 // canonical slot of every Gauss point of every block element (grid slot when the point is a
 // WQ grid point, else the block entry)
 __global__ void k_blk_slot(DevRules R, const int32_t* block_elems, int64_t nb, int32_t* out) {
@@ -1162,6 +1259,7 @@ int build_rules(const wq_mesh* mesh, const wq_levelset* ls, const wq_options* op
     if (!rcnt || !cflag || !row_ptr) return B.fail();
     R.row_ptr = row_ptr;
     const bool gauss_rows = opts && (opts->flags & WQ_OPT_GAUSS_ROWS);
+    const bool fit_rule = opts && (opts->flags & WQ_OPT_MOMENT_FIT);
     if (na > 0)
         hipLaunchKernelGGL(k_row_count, grid_for(na), dim3(256), 0, stream, R, na, act2lex, fcls, rcnt, cflag,
                            gauss_rows ? 1 : 0);
@@ -1425,8 +1523,9 @@ int build_rules(const wq_mesh* mesh, const wq_levelset* ls, const wq_options* op
         R.n_block = H->n_block_elems * npe;
         H->n_oct = R.n_cells * npe;
         R.n_kappa = R.n_grid + R.n_block + H->n_oct;
-        double* xyz = B.keep<double>(R.n_kappa * 3);
-        double* ow = B.keep<double>(H->n_oct > 0 ? H->n_oct : 1);
+        // with the fitted rule the octree slots and weights only serve the fit below
+        double* xyz = fit_rule ? B.tmp<double>(R.n_kappa * 3) : B.keep<double>(R.n_kappa * 3);
+        double* ow = fit_rule ? B.tmp<double>(H->n_oct > 0 ? H->n_oct : 1) : B.keep<double>(H->n_oct > 0 ? H->n_oct : 1);
         if (!xyz || !ow) return B.fail();
         R.oct_w = ow;
         H->kappa_xyz = xyz;
@@ -1446,7 +1545,7 @@ int build_rules(const wq_mesh* mesh, const wq_levelset* ls, const wq_options* op
             hipLaunchKernelGGL(k_convert<float>, grid_for(n), dim3(256), 0, stream, w, w32, n);
             R.rem_w64[d] = w; R.rem_w32[d] = w32;
         }
-        float* ow32 = B.keep<float>(H->n_oct > 0 ? H->n_oct : 1);
+        float* ow32 = fit_rule ? B.tmp<float>(H->n_oct > 0 ? H->n_oct : 1) : B.keep<float>(H->n_oct > 0 ? H->n_oct : 1);
         if (!ow32) return B.fail();
         R.oct_w32 = ow32;
         if (H->n_oct > 0) {
@@ -1454,6 +1553,49 @@ int build_rules(const wq_mesh* mesh, const wq_levelset* ls, const wq_options* op
                                H->cell_cut, ow, xyz);
             hipLaunchKernelGGL(k_convert<float>, grid_for(H->n_oct), dim3(256), 0, stream, ow, ow32, H->n_oct);
         }
+    }
+    // fitted cut rule: Legendre moments of each cut element's octree rule (kappa = 1), weights
+    // on the element's NK^3 tensor Gauss points, and the slot layout with those points
+    R.fit = 0; R.fit_V64 = nullptr; R.fit_V32 = nullptr;
+    if (fit_rule) {
+        const int nk = 2 * p + 1, ni = (2 << R.levels) - 1;
+        const int64_t nk3 = (int64_t)nk * nk * nk, nce = R.n_cut_elems;
+        double* fxi = B.tmp<double>(nk);
+        double* fw = B.tmp<double>(nk);
+        double* V = B.keep<double>(nk * nk);
+        float* V32 = B.keep<float>(nk * nk);
+        double* Ainv = B.tmp<double>(nk * nk);
+        double* leg = B.tmp<double>((int64_t)ni * nk * (p + 1));
+        double* ones = B.tmp<double>(R.n_kappa);
+        double* mom = B.tmp<double>(nce > 0 ? nce * nk3 : 1);
+        double* wf = B.keep<double>(nce > 0 ? nce * nk3 : 1);
+        float* wf32 = B.keep<float>(nce > 0 ? nce * nk3 : 1);
+        const int64_t nkap = R.n_grid + R.n_block + nce * nk3;
+        double* xyz2 = B.keep<double>(nkap * 3);
+        if (!fxi || !fw || !V || !V32 || !Ainv || !leg || !ones || !mom || !wf || !wf32 || !xyz2) return B.fail();
+        hipLaunchKernelGGL(k_gauss, dim3(1), dim3(1), 0, stream, nk, fxi, fw);
+        hipLaunchKernelGGL(k_fit_tables, dim3(1), dim3(256), 0, stream, p, (const double*)fxi, (const double*)fw, V, Ainv);
+        hipLaunchKernelGGL(k_convert<float>, dim3(1), dim3(256), 0, stream, V, V32, (int64_t)nk * nk);
+        if (nce > 0) {
+            hipLaunchKernelGGL(k_leg_intervals, grid_for((int64_t)ni * nk * (p + 1)), dim3(256), 0, stream, R, gxi, leg);
+            hipLaunchKernelGGL(k_fill_f64, grid_for(R.n_kappa), dim3(256), 0, stream, ones, R.n_kappa, 1.0);
+            int st = launch_octree_moments_f64(H, leg, ones, mom, stream);
+            if (st) return B.fail_msg(st, "moments of the octree rule failed");
+            hipLaunchKernelGGL(k_fit_weights, dim3((unsigned)nce), dim3(256), 0, stream, p, (const double*)Ainv,
+                               (const double*)mom, wf);
+            hipLaunchKernelGGL(k_convert<float>, grid_for(nce * nk3), dim3(256), 0, stream, wf, wf32, nce * nk3);
+        }
+        if (B.check(hipMemcpyAsync(xyz2, H->kappa_xyz, sizeof(double) * 3 * (R.n_grid + R.n_block), hipMemcpyDeviceToDevice,
+                                   stream)))
+            return B.fail();
+        if (nce > 0)
+            hipLaunchKernelGGL(k_fit_xyz, grid_for(nce * nk3), dim3(256), 0, stream, R, nce, R.cut_elems, (const double*)fxi,
+                               R.n_grid + R.n_block, xyz2);
+        H->n_oct = nce * nk3;
+        R.n_kappa = nkap;
+        R.oct_w = wf; R.oct_w32 = wf32;
+        H->kappa_xyz = xyz2;
+        R.fit = 1; R.fit_V64 = V; R.fit_V32 = V32;
     }
     if (B.check(hipGetLastError())) return B.fail();
     int herr = 0;

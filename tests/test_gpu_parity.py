@@ -13,6 +13,8 @@ import torch
 import oracle_pool
 import workloads as W
 from oracle.assemble import Problem, kappa_numpy
+from oracle.domain import octree_points
+from oracle.spline import gauss_legendre
 
 pytestmark = pytest.mark.gpu
 
@@ -566,6 +568,102 @@ def _row_scaled(a, b, rp, rows_sel=None):
     if rows_sel is not None:
         ok &= rows_sel
     return float((d[ok] / m[ok]).max())
+
+
+FIT = {
+    "ball6_p2_fit": W.with_cut_rule(SMALL["ball6_p2"], "fit"),
+    "plane6_p3_fit": W.with_cut_rule(SMALL["plane6_p3"], "fit"),
+    "ball5_p4_fit": W.with_cut_rule(SMALL["ball5_p4"], "fit"),
+    "ball4_p5_fit": W.with_cut_rule(HIGH["ball4_p5"], "fit"),
+}
+
+
+@pytest.mark.parametrize("name", list(FIT))
+def test_fitted_cut_rule_matches_oracle(name):
+    """WQ_OPT_MOMENT_FIT: slot layout (NK^3 points per cut element), weights, matrices (FP64 and
+    FP32) and the adjoint against the oracle's fitted rule."""
+    wl = FIT[name]
+    print("case fit", name, flush=True)
+    R = rules_for(wl)
+    P = Problem(wl)
+    nk3 = (2 * wl.degree + 1) ** 3
+    assert R.n_octree == R.n_cut_elems * nk3
+    sl = P.slots()
+    assert R.n_kappa == sl.n_slots
+    assert np.abs(R.kappa_xyz().cpu().numpy() - sl.coords()).max() <= 1e-14
+    # weights per cut element within 1e-13 of the element's octree weight sum (the Legendre
+    # moments are sums of positive terms bounded by it)
+    wg = R.octree_w().cpu().numpy().reshape(-1, nk3)
+    for c, e in enumerate(sl.cut):
+        vol = np.abs(octree_points(P.lines, P.dom.ls, e, sl.levels)[1]).sum()
+        assert np.abs(wg[c] - sl.octree(e)[1]).max() <= 1e-13 * vol, (e, vol)
+    M, K = oracle_pool.full_wq(wl, n_active=R.n_active)
+    rp = P.row_ptr()
+    # Rounding model of the fitted rule (the bar's scale).  (i) Its weights have both signs, so an
+    # entry is a sum of terms that can be much larger than itself: scale |w| |kappa|.  (ii) A
+    # weight is a linear map of the element's Legendre moments, which are sums of positive octree
+    # weights; it is fixed to rounding relative to the element's Omega-volume vol_e spread over
+    # the points like the Gauss weights: scale vol_e W_g / |e| |kappa|.  The row scale is the
+    # largest of the row's maximum and the row maximum of the matrices with the weights
+    # |w_g| + vol_e W_g / |e| on the cut elements and |kappa|.  (A perturbation of the weights by
+    # 1e-16 vol_e alone moves row-scaled entries by up to 5e-9 on plane6_p3, by 4e-14 against
+    # this scale.)
+    Pa = Problem(wl)
+    sla = Pa.slots(with_octree=False)
+    nk = 2 * wl.degree + 1
+    _, gwk = gauss_legendre(nk)
+    gw3 = np.einsum("a,b,c->abc", gwk, gwk, gwk).ravel() / 8.0
+    for e in sla.cut:
+        xf, wf = sla.octree(e)
+        vol = np.abs(octree_points(Pa.lines, Pa.dom.ls, e, sla.levels)[1]).sum()
+        sla._oct[e] = (xf, np.abs(wf) + vol * gw3)
+    kap_abs = kappa_numpy(wl)
+    Ma, Ka = Pa.assemble_full_wq(lambda x: np.abs(kap_abs(x)))
+
+    def scaled_err(got, ref, ref_abs):
+        e = 0.0
+        for r in range(len(rp) - 1):
+            a, b = rp[r], rp[r + 1]
+            if b > a:
+                sc = max(np.abs(ref[a:b]).max(), np.abs(ref_abs[a:b]).max())
+                if sc > 0:
+                    e = max(e, np.abs(got[a:b] - ref[a:b]).max() / sc)
+        return e
+
+    for dtype in (torch.float64, torch.float32):
+        vm, vk = R.assemble(kappa_slots(R, wl, dtype))
+        em = scaled_err(vm.cpu().numpy(), M, Ma)
+        ek = scaled_err(vk.cpu().numpy(), K, Ka)
+        assert em <= TOL[dtype] and ek <= TOL[dtype], (dtype, em, ek)
+        assert row_errors(vm.cpu().numpy(), M, rp)[1] <= TOL[dtype]
+    GM = W.random_values(111, R.nnz)
+    GK = W.random_values(112, R.nnz)
+    ref = oracle_pool.adjoint(wl, GM, GK)
+    got = R.adjoint(torch.tensor(GM, device=R.device), torch.tensor(GK, device=R.device)).cpu().numpy()
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_fitted_cut_rule_plane48():
+    """48^3 p=4: with kappa = 1 the fitted rule gives the octree's matrices; with the random
+    field the two differ only by the fitted rule's quadrature error on the cut elements."""
+    wl = W.workload("plane48_p4")
+    print("case fit plane48", flush=True)
+    Ro = rules_for(wl)
+    Rf = rules_for(W.with_cut_rule(wl, "fit"))
+    assert Rf.n_octree == Rf.n_cut_elems * 9 ** 3 and Rf.n_octree * 10 < Ro.n_octree
+    rp = Ro.row_ptr()
+    one_o = torch.ones(Ro.n_kappa, dtype=torch.float64, device=Ro.device)
+    one_f = torch.ones(Rf.n_kappa, dtype=torch.float64, device=Rf.device)
+    # entrywise against the matrix maximum: a fitted weight is fixed only to rounding relative to
+    # its element's Omega-volume, so rows that see a sliver of Omega carry errors large against
+    # their own maximum (the small cases bound them against the rounding scale of the rule)
+    for a, b in zip(Rf.assemble(one_f), Ro.assemble(one_o)):
+        assert float((a - b).abs().max()) <= 1e-12 * float(b.abs().max())
+        assert float((a - b).norm() / b.norm()) <= 1e-13
+    fo = Ro.assemble(kappa_slots(Ro, wl, torch.float64))
+    ff = Rf.assemble(kappa_slots(Rf, wl, torch.float64))
+    for a, b in zip(ff, fo):
+        assert float((a - b).norm() / b.norm()) <= 1e-3
 
 
 @pytest.mark.parametrize("name", ["plane6_p3", "ball4_p6", "plane48_p4"])
