@@ -154,52 +154,62 @@ def support(tk: np.ndarray, p: int, i: int):
 # ----------------------------------------------------------------------------------------
 def exact_gram(line: Line, tk: np.ndarray, i: int, j: int, a: int) -> float:
     """int B_i^(a) B_j^(a) over the common support, by (p+1)-point Gauss per element (exact)."""
+    return _gram(line, tk, i, a, lambda t, x: bspline(t, line.p, j, x, a), support(tk, line.p, j))
+
+
+def _gram(line: Line, tk: np.ndarray, i: int, at: int, fn, sup) -> float:
+    """int B_i^(at) fn over supp B_i intersected with sup (element range), (p+1)-point Gauss per
+    element; exact when fn is a piecewise polynomial of degree <= p on the elements."""
     p = line.p
     t = line.knot_coord(tk)
     ai, bi = support(tk, p, i)
-    aj, bj = support(tk, p, j)
     s = 0.0
-    for e in range(max(ai, aj), min(bi, bj)):
-        x = line.gauss_coord(e, np.arange(p + 1))
-        s += float(np.sum(line.gauss_weight(np.arange(p + 1))
-                          * bspline(t, p, i, x, a) * bspline(t, p, j, x, a)))
+    g = np.arange(p + 1)
+    for e in range(max(ai, sup[0]), min(bi, sup[1])):
+        x = line.gauss_coord(e, g)
+        s += float(np.sum(line.gauss_weight(g) * bspline(t, p, i, x, at) * fn(t, x)))
     return s
 
 
-def exactness_system(line: Line, tk: np.ndarray, i: int, a: int, xq: np.ndarray):
-    """Exactness conditions of the rule of test function i at points xq: (A, b), one row
-    per condition, A[c, q] = (condition function c)(x_q).
+def rule_orders(a):
+    """(test derivative order, trial derivative order) of a rule family: 0 = (0, 0) mass,
+    1 = (1, 1) stiffness, (1, 0) and (0, 1) the mixed families of a full coefficient tensor."""
+    return (a, a) if a in (0, 1) else (int(a[0]), int(a[1]))
 
-    a = 0: the conditions are sum_q w_q B_j(x_q) = int B_i B_j for every j whose support
+
+def exactness_system(line: Line, tk: np.ndarray, i: int, a, xq: np.ndarray):
+    """Exactness conditions of the rule of test function i at points xq: (A, b), one row
+    per condition, A[c, q] = (condition function c)(x_q).  a: family (rule_orders), test
+    derivative order at and trial derivative order ac.
+
+    ac = 0: the conditions are sum_q w_q B_j(x_q) = int B_i^(at) B_j for every j whose support
     overlaps supp B_i in positive measure.
-    a = 1: the conditions sum_q w_q B_j'(x_q) = int B_i' B_j' for those j span, on supp B_i,
+    ac = 1: the conditions sum_q w_q B_j'(x_q) = int B_i^(at) B_j' for those j span, on supp B_i,
     the same space as the degree p-1 B-splines N_k over the same knots that are nonzero
     there (each B_j' is a combination of N_j and N_{j+1}; the B_j' lose one dimension
-    because they sum to zero on the support).  Imposing sum_q w_q N_k(x_q) = int B_i' N_k
+    because they sum to zero on the support).  Imposing sum_q w_q N_k(x_q) = int B_i^(at) N_k
     for those k therefore gives the same set of admissible weights, with one condition
     per dimension instead of a redundant one."""
     p = line.p
+    at, ac = rule_orders(a)
     t = line.knot_coord(tk)
     sa, sb = support(tk, p, i)
-    if a == 0:
+    if ac == 0:
         J = [j for j in range(len(tk) - p - 1)
              if max(sa, support(tk, p, j)[0]) < min(sb, support(tk, p, j)[1])]
         A = np.array([bspline(t, p, j, xq) for j in J])
-        b = np.array([exact_gram(line, tk, i, j, 0) for j in J])
+        b = np.array([_gram(line, tk, i, at, lambda tt, x, j=j: bspline(tt, p, j, x), support(tk, p, j))
+                      for j in J])
         return A, b
     K = [k for k in range(len(tk) - p) if tk[k] < tk[k + p] and max(sa, tk[k]) < min(sb, tk[k + p])]
     A = np.array([bspline(t, p - 1, k, xq) for k in K])
-    b = np.zeros(len(K))
-    g = np.arange(p + 1)
-    for c, k in enumerate(K):
-        for e in range(max(sa, int(tk[k])), min(sb, int(tk[k + p]))):
-            x = line.gauss_coord(e, g)
-            b[c] += float(np.sum(line.gauss_weight(g) * bspline(t, p, i, x, 1) * bspline(t, p - 1, k, x)))
+    b = np.array([_gram(line, tk, i, at, lambda tt, x, k=k: bspline(tt, p - 1, k, x), (int(tk[k]), int(tk[k + p])))
+                  for k in K])
     return A, b
 
 
 def wq_rule(line: Line, tk: np.ndarray, pts, full_gauss: set, i: int, a: int):
-    """Weighted-quadrature rule of test function i (knots tk) for derivative order a.
+    """Weighted-quadrature rule of test function i (knots tk) for family a (rule_orders).
 
     pts: the global point list ((element, gauss index), ascending); full_gauss: the
     elements that keep all their Gauss points.  Returns (list of points, weights).
@@ -222,7 +232,7 @@ def wq_rule(line: Line, tk: np.ndarray, pts, full_gauss: set, i: int, a: int):
     xq = line.coord(Q)
     if all(e in full_gauss for e in range(sa, sb)):
         wg = np.array([line.gauss_weight(g) for (_, g) in Q])
-        return Q, wg * bspline(t, p, i, xq, a)
+        return Q, wg * bspline(t, p, i, xq, rule_orders(a)[0])
     A, b = exactness_system(line, tk, i, a, xq)
     s = 1.0 / np.linalg.norm(A, axis=1)
     Qf, Rf = np.linalg.qr((A * s[:, None]).T)
@@ -231,12 +241,22 @@ def wq_rule(line: Line, tk: np.ndarray, pts, full_gauss: set, i: int, a: int):
 
 
 class Rules1D:
-    """All standard WQ rules of one direction: rule[a][i] = (points, weights)."""
+    """All standard WQ rules of one direction: rule[a][i] = (points, weights); the mixed
+    families (1, 0) and (0, 1) on demand through family()."""
 
     def __init__(self, line: Line):
         self.line = line
         self.rule = [[wq_rule(line, line.tk, line.X, line.full_gauss_elems, i, a)
                       for i in range(line.n)] for a in (0, 1)]
+        self._mixed = {}
+
+    def family(self, a, i):
+        if a in (0, 1):
+            return self.rule[a][i]
+        key = (rule_orders(a), i)
+        if key not in self._mixed:
+            self._mixed[key] = wq_rule(self.line, self.line.tk, self.line.X, self.line.full_gauss_elems, i, a)
+        return self._mixed[key]
 
 
 # ----------------------------------------------------------------------------------------

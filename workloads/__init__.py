@@ -210,3 +210,62 @@ def poly2_f(xyz):
 
 
 FUNCTIONS = {"target_f": target_f, "poly2_f": poly2_f}
+
+
+# ----------------------------------------------------------------------------------------
+# full coefficient tensors (stiffness under a geometry map)
+# ----------------------------------------------------------------------------------------
+# Component order of a symmetric 3x3 tensor field at the slots: C11, C22, C33, C12, C13, C23.
+TENSOR_COMPONENTS = ((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2))
+MAP_EPS = 0.05
+
+
+def _lib_of(xyz):
+    return torch if isinstance(xyz, torch.Tensor) else np
+
+
+def map_jacobian(xyz):
+    """DF of the map F_i(x) = x_i + eps sin(pi x_{i+1}) sin(pi x_{i+2}) (indices mod 3,
+    eps = 0.05), a smooth bijection of the unit cube onto itself (the boundary terms vanish):
+    (P, 3, 3) array, DF[:, i, j] = dF_i / dx_j."""
+    L = _lib_of(xyz)
+    pi = math.pi
+    s = L.sin(pi * xyz)
+    c = L.cos(pi * xyz)
+    P = xyz.shape[0]
+    J = L.zeros((P, 3, 3), dtype=xyz.dtype) if L is np else torch.zeros((P, 3, 3), dtype=xyz.dtype, device=xyz.device)
+    for i in range(3):
+        a, b = (i + 1) % 3, (i + 2) % 3
+        J[:, i, i] = 1.0
+        J[:, i, a] = MAP_EPS * pi * c[:, a] * s[:, b]
+        J[:, i, b] = MAP_EPS * pi * s[:, a] * c[:, b]
+    return J
+
+
+def map_tensor(xyz):
+    """Coefficient tensor of the Laplacian pulled back through the map: C = |det DF|
+    DF^{-1} DF^{-T} at the points, (P, 3, 3)."""
+    L = _lib_of(xyz)
+    J = map_jacobian(xyz)
+    Ji = L.linalg.inv(J)
+    det = L.linalg.det(J)
+    return L.abs(det)[:, None, None] * (Ji @ Ji.transpose(0, 2, 1) if L is np else Ji @ Ji.transpose(1, 2))
+
+
+def constant_tensor(seed: int):
+    """A seeded symmetric positive definite constant tensor: C = A A^T / 3 + I / 2, A with
+    N(0,1) entries (numpy.random.default_rng(seed), row-major)."""
+    A = np.random.default_rng(seed).standard_normal((3, 3))
+    return A @ A.T / 3.0 + 0.5 * np.eye(3)
+
+
+def tensor_components(C):
+    """(P, 3, 3) tensors -> (6, P) components in TENSOR_COMPONENTS order (the layout the
+    library takes at the slots)."""
+    L = _lib_of(C)
+    return L.stack([C[:, d, e] for d, e in TENSOR_COMPONENTS])
+
+
+TENSOR_FIELDS = {
+    "map": map_tensor,
+}
