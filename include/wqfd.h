@@ -77,7 +77,7 @@ typedef struct {
 
 typedef struct {
     int32_t octree_levels;   /* depth of the cut-element octree, 0..5 (default 3) */
-    int32_t flags;           /* 0 or WQ_OPT_HYBRID_GAUSS | WQ_OPT_GAUSS_ROWS | WQ_OPT_MOMENT_FIT */
+    int32_t flags;           /* 0 or WQ_OPT_HYBRID_GAUSS | WQ_OPT_GAUSS_ROWS | WQ_OPT_MOMENT_FIT | WQ_OPT_TENSOR */
 } wq_options;
 
 /* Option flag: the "Hybrid Gauss" scheme of Section 3.1 (list of compared schemes) instead of
@@ -91,7 +91,7 @@ typedef struct {
  * Gauss assembly (gauss_assemble), formed row by row without atomics, so that the gain of
  * weighted quadrature can be measured on the same row-owned engineering.  The slot layout
  * then holds a Gauss block for every interior element; n_rows_interior is 0. */
-enum { WQ_OPT_HYBRID_GAUSS = 1, WQ_OPT_GAUSS_ROWS = 2, WQ_OPT_MOMENT_FIT = 4 };
+enum { WQ_OPT_HYBRID_GAUSS = 1, WQ_OPT_GAUSS_ROWS = 2, WQ_OPT_MOMENT_FIT = 4, WQ_OPT_TENSOR = 8 };
 
 /* Option flag WQ_OPT_MOMENT_FIT (cheaper cut integration; the paper's cut-element scheme is
  * higher order but costly, Section 3.2): every cut element's octree rule is replaced by a rule on
@@ -101,6 +101,12 @@ enum { WQ_OPT_HYBRID_GAUSS = 1, WQ_OPT_GAUSS_ROWS = 2, WQ_OPT_MOMENT_FIT = 4 };
  * at NK^3 points per cut element instead of (p+1)^3 per octree leaf.  The octree slots of the
  * layout become these points (n_octree = n_cut_elems * NK^3, lexicographic per cut element) and
  * octree_w their weights (which may be negative).  Octree depth <= 3 only. */
+
+/* Option flag WQ_OPT_TENSOR (Section 2 takes the identity as the geometry map and notes that
+ * this loses no generality; under a map F the Laplacian stiffness has the full symmetric
+ * coefficient tensor C = |det DF| DF^-1 DF^-T): the rule build adds the mixed 1D rule
+ * families (1, 0) (test derivative, trial value) and (0, 1) (test value, trial derivative),
+ * standard and one-sided, that wq_assemble_tensor needs.  Degrees 1..4 only. */
 
 typedef struct wq_rules wq_rules;   /* opaque; owns its device buffers */
 
@@ -186,6 +192,20 @@ int cut_assemble_noalloc(const wq_rules* rules, int dtype, uint32_t which, const
  * its bit is absent from which. */
 int wq_assemble_adjoint(const wq_rules* rules, int dtype, uint32_t which, const void* G_mass,
                         const void* G_stiff, void* dkappa, void* stream);
+
+/* Stiffness matrix with a full symmetric coefficient tensor (Section 2, opening paragraph:
+ * the identity geometry map lifted; Eq. (1) for the cut rows):
+ *   K_IJ = int_Omega grad B_I . C grad B_J = sum_{d,e} int C_de d_d B_I d_e B_J.
+ * Interior rows and the DWQ box of cut rows by weighted quadrature with sum factorization,
+ * term (d, e) using the family (1, 0) in direction d, (0, 1) in direction e, (1, 1) when d = e
+ * and (0, 0) elsewhere; the element Gauss remainder and the cut elements (octree, or the
+ * fitted rule under WQ_OPT_MOMENT_FIT) of cut rows by element quadrature, row by row.
+ * C: device array (6, n_kappa), row-major: the components C11, C22, C33, C12, C13, C23 at
+ * every slot.  vals_stiff: (nnz) device output, OVERWRITTEN; the mass matrix of a map only
+ * changes its scalar coefficient and comes from wq_assemble_rows / cut_assemble.  Needs rules
+ * built with WQ_OPT_TENSOR (WQ_EINVAL otherwise); dtype WQ_F64 or WQ_F32.  Sums run in a
+ * fixed order (no atomics).  Asynchronous on stream. */
+int wq_assemble_tensor(const wq_rules* rules, int dtype, const void* C, void* vals_stiff, void* stream);
 
 /* Conventional assembly for comparison (Section 3.1, "Standard Gauss"): element by element,
  * (p+1)^3 Gauss points on every interior element and the octree points on every cut element,

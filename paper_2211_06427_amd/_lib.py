@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libwqfd.so")
 
 WQ_F64, WQ_F32, WQ_BF16X3 = 0, 1, 2
-WQ_OPT_HYBRID_GAUSS, WQ_OPT_GAUSS_ROWS, WQ_OPT_MOMENT_FIT = 1, 2, 4
+WQ_OPT_HYBRID_GAUSS, WQ_OPT_GAUSS_ROWS, WQ_OPT_MOMENT_FIT, WQ_OPT_TENSOR = 1, 2, 4, 8
 WQ_MASS, WQ_STIFF = 1, 2
 WQ_CUT_REMAINDER, WQ_CUT_OCTREE = 4, 8
 STATUS = {0: "WQ_OK", -1: "WQ_EINVAL", -2: "WQ_ENOMEM", -3: "WQ_EHIP", -4: "WQ_ESINGULAR", -5: "WQ_EUNSUPPORTED"}
@@ -16,7 +16,7 @@ STATUS = {0: "WQ_OK", -1: "WQ_EINVAL", -2: "WQ_ENOMEM", -3: "WQ_EHIP", -4: "WQ_E
 EXPORTS = ["wq_build_rules", "wq_rules_info_get", "wq_assemble_rows", "cut_assemble", "wq_assemble_adjoint",
            "wq_rules_free", "wq_last_error", "gauss_assemble", "wq_gauss_coords", "cut_assemble_noalloc",
            "wq_load_vector", "wq_extension_build", "wq_extension_info_get", "wq_extension_free", "wq_project",
-           "wq_l2_error"]
+           "wq_l2_error", "wq_assemble_tensor"]
 
 
 class WqMesh(C.Structure):
@@ -74,6 +74,7 @@ def load(path: str = LIB_PATH):
     lib.wq_assemble_adjoint.argtypes = [vp, i32, u32, vp, vp, vp, vp]
     lib.gauss_assemble.argtypes = [vp, i32, u32, vp, vp, vp, vp, vp]
     lib.wq_gauss_coords.argtypes = [vp, vp, vp]
+    lib.wq_assemble_tensor.argtypes = [vp, i32, vp, vp, vp]
     lib.wq_load_vector.argtypes = [vp, vp, vp, vp]
     lib.wq_extension_build.argtypes = [vp, vp, C.POINTER(vp)]
     lib.wq_extension_info_get.argtypes = [vp, C.POINTER(WqExtensionInfo)]
@@ -87,7 +88,7 @@ def load(path: str = LIB_PATH):
     lib.wq_last_error.restype = C.c_char_p
     for name in ("wq_build_rules", "wq_rules_info_get", "wq_assemble_rows", "cut_assemble", "wq_assemble_adjoint",
                  "cut_assemble_noalloc", "gauss_assemble", "wq_gauss_coords", "wq_load_vector", "wq_extension_build",
-                 "wq_extension_info_get", "wq_project", "wq_l2_error"):
+                 "wq_extension_info_get", "wq_project", "wq_l2_error", "wq_assemble_tensor"):
         getattr(lib, name).restype = i32
     _lib = lib
     return lib

@@ -35,12 +35,13 @@ class Rules:
     """Kappa-independent data of one mesh + domain (built on the GPU, FP64)."""
 
     def __init__(self, nel, degree, levelset=None, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), octree_levels=3,
-                 device=None, hybrid_gauss=False, gauss_rows=False, cut_rule="octree"):
+                 device=None, hybrid_gauss=False, gauss_rows=False, cut_rule="octree", tensor=False):
         """hybrid_gauss=True: the Hybrid Gauss scheme (no DWQ boxes; the regular support of
         every cut row goes through element Gauss with sum factorization).  gauss_rows=True: no
         weighted quadrature; every row by element Gauss with sum factorization (the
         conventional Gauss matrices, row-owned and atomic-free; for comparison).  cut_rule="fit":
-        cut elements by the rule fitted to the octree on (2p+1)^3 Gauss points per element."""
+        cut elements by the rule fitted to the octree on (2p+1)^3 Gauss points per element.
+        tensor=True: also build the mixed rule families of assemble_tensor (p <= 4)."""
         if cut_rule not in ("octree", "fit"):
             raise ValueError(f"cut_rule must be 'octree' or 'fit', got {cut_rule!r}")
         lib = L.load()
@@ -56,7 +57,8 @@ class Rules:
             ls.r0, ls.r1 = float(levelset.r0), float(levelset.r1)
         opts = L.WqOptions(int(octree_levels), (L.WQ_OPT_HYBRID_GAUSS if hybrid_gauss else 0) |
                            (L.WQ_OPT_GAUSS_ROWS if gauss_rows else 0) |
-                           (L.WQ_OPT_MOMENT_FIT if cut_rule == "fit" else 0))
+                           (L.WQ_OPT_MOMENT_FIT if cut_rule == "fit" else 0) |
+                           (L.WQ_OPT_TENSOR if tensor else 0))
         self.cut_rule = cut_rule
         self.hybrid_gauss = bool(hybrid_gauss)
         self.gauss_rows = bool(gauss_rows)
@@ -78,9 +80,9 @@ class Rules:
         self.nfun = tuple(info.nfun)
 
     @classmethod
-    def from_workload(cls, wl, device=None, hybrid_gauss=False, gauss_rows=False):
+    def from_workload(cls, wl, device=None, hybrid_gauss=False, gauss_rows=False, tensor=False):
         return cls(wl.nel, wl.degree, wl.levelset, wl.lo, wl.hi, wl.octree_levels, device, hybrid_gauss, gauss_rows,
-                   getattr(wl, "cut_rule", "octree"))
+                   getattr(wl, "cut_rule", "octree"), tensor)
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -173,6 +175,19 @@ class Rules:
         self.assemble_rows(kappa, vm, vk, which, bf16x3)
         self.cut_assemble(kappa, vm, vk, which)
         return vm, vk
+
+    def assemble_tensor(self, coef, out=None):
+        """Stiffness values with a full symmetric coefficient tensor: coef (6, n_kappa) components
+        C11, C22, C33, C12, C13, C23 at the slots (float64 or float32)."""
+        if coef.dim() != 2 or coef.shape[0] != 6 or coef.shape[1] != self.n_kappa or not coef.is_contiguous() or \
+                coef.device != self.device or coef.dtype not in (torch.float64, torch.float32):
+            raise ValueError(f"assemble_tensor: expected a contiguous (6, {self.n_kappa}) float tensor on {self.device}, "
+                             f"got {tuple(coef.shape)} {coef.dtype} on {coef.device}")
+        vk = torch.empty(self.nnz, dtype=coef.dtype, device=self.device) if out is None else out
+        _need(vk, self.nnz, coef.dtype, self.device, "vals_stiff")
+        L.check(L.load().wq_assemble_tensor(self._h, _DT[coef.dtype], _ptr(coef), _ptr(vk),
+                                            C.c_void_p(_stream_handle(self.device))))
+        return vk
 
     def gauss_coords(self):
         """(n_gauss_elems * (p+1)^3, 3) coordinates of the interior elements' Gauss points."""

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libwqfd.so")
 # (source, object, extra flags): the kernel files are compiled once per value type
 SOURCES = [("capi.hip", "capi.o", []), ("rules.hip", "rules.o", []), ("projection.hip", "projection.o", [])] + [
-    (f"{s}.hip", f"{s}_{t}.o", [f"-DWQ_ONLY_{t.upper()}"]) for s in ("rows", "cut", "adjoint") for t in ("f64", "f32")]
+    (f"{s}.hip", f"{s}_{t}.o", [f"-DWQ_ONLY_{t.upper()}"]) for s in ("rows", "cut", "adjoint", "tensor") for t in ("f64", "f32")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

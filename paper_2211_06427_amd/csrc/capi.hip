@@ -97,8 +97,11 @@ int wq_build_rules(const wq_mesh* mesh, const wq_levelset* ls, const wq_options*
     if (opts) o = *opts;
     if (o.octree_levels < 0 || o.octree_levels > 5)
         return wq_set_error(WQ_EINVAL, "wq_build_rules: octree_levels must be in 0..5 (got %d)", o.octree_levels);
-    if (o.flags & ~(WQ_OPT_HYBRID_GAUSS | WQ_OPT_GAUSS_ROWS | WQ_OPT_MOMENT_FIT))
+    if (o.flags & ~(WQ_OPT_HYBRID_GAUSS | WQ_OPT_GAUSS_ROWS | WQ_OPT_MOMENT_FIT | WQ_OPT_TENSOR))
         return wq_set_error(WQ_EINVAL, "wq_build_rules: unknown option flags 0x%x", o.flags);
+    if ((o.flags & WQ_OPT_TENSOR) && mesh->degree > 4)
+        return wq_set_error(WQ_EUNSUPPORTED, "wq_build_rules: the coefficient-tensor stiffness supports degrees 1..4 (got %d)",
+                            mesh->degree);
     if ((o.flags & WQ_OPT_MOMENT_FIT) && o.octree_levels > 3)
         return wq_set_error(WQ_EUNSUPPORTED, "wq_build_rules: the fitted cut rule needs octree_levels <= 3 (got %d)",
                             o.octree_levels);
@@ -200,6 +203,19 @@ int wq_assemble_adjoint(const wq_rules* r, int dtype, uint32_t which, const void
         st = launch_adjoint<float>(r, which, (const float*)gm, (const float*)gk, (float*)dk, (hipStream_t)stream);
     if (st) return st;
     return check_launch("wq_assemble_adjoint");
+}
+
+int wq_assemble_tensor(const wq_rules* r, int dtype, const void* C, void* vals_stiff, void* stream) {
+    if (!r) return wq_set_error(WQ_EINVAL, "wq_assemble_tensor: rules handle is NULL");
+    if (dtype != WQ_F64 && dtype != WQ_F32) return wq_set_error(WQ_EINVAL, "wq_assemble_tensor: dtype must be F64 or F32");
+    if (!C || !vals_stiff) return wq_set_error(WQ_EINVAL, "wq_assemble_tensor: NULL argument");
+    if (!r->R.tensor)
+        return wq_set_error(WQ_EINVAL, "wq_assemble_tensor: the rules were built without WQ_OPT_TENSOR");
+    if (r->nnz == 0) return WQ_OK;
+    int st = dtype == WQ_F64 ? launch_tensor<double>(r, (const double*)C, (double*)vals_stiff, (hipStream_t)stream)
+                             : launch_tensor<float>(r, (const float*)C, (float*)vals_stiff, (hipStream_t)stream);
+    if (st) return wq_set_error(st, "wq_assemble_tensor: unsupported degree %d", r->R.p);
+    return check_launch("wq_assemble_tensor");
 }
 
 int wq_gauss_coords(const wq_rules* r, double* xyz, void* stream) {

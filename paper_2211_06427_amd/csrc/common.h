@@ -29,6 +29,9 @@ struct DevRules {
     const int32_t* nwin[3];             // window size of function i
     const double* Wt64[3];              // [i][a][jj][q], n x 2 x m x nw
     const float* Wt32[3];
+    int tensor;                         // WQ_OPT_TENSOR: mixed families built
+    const double* Wtx64[3];             // [i][f][jj][q]: f = 0 family (1, 0) times B_j, f = 1 family (0, 1) times B_j'
+    const float* Wtx32[3];
     const int8_t* qlo[3];               // [i][jj]: nonzero q range of W[i][.][jj][.]
     const int8_t* qhi[3];
     const double* Bval[3];              // [y][k]: B_{e+k}(y), k = 0..p (e = element of y)
@@ -57,6 +60,8 @@ struct DevRules {
     const int32_t* dwq_y;               // [r][ndq]
     const double* dwq_Wt64;             // [r][a][jj][ndq]
     const float* dwq_Wt32;
+    const double* dwq_Wtx64;            // [r][f][jj][ndq], mixed families as Wtx64
+    const float* dwq_Wtx32;
     // element Gauss blocks
     const int32_t* elem_block;          // element -> block or -1
     const int32_t* blk_slot;            // [block][(p+1)^3] canonical kappa slot of each Gauss point

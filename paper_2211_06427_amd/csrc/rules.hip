@@ -184,7 +184,11 @@ __global__ void k_dir_tables(DevRules R, int d, const double* gxi, double* ycoor
 // are combinations of them and span the same space there (less one dimension, since they
 // sum to zero), so sum_q w_q N_k(x_q) = int B_l' N_k fixes the same weights without a
 // redundant condition.  Returns 0, or WQ_ESINGULAR when a pivot vanishes.
-__device__ int wq_local_rule(const double* T, int nT, int p, int l, int a, const double* xq, const double* gq,
+//
+// Families of a full coefficient tensor (at = test derivative order, ac = trial derivative
+// order): (0, 0) and (1, 1) above, and the mixed (1, 0) (conditions on the B_j, right-hand
+// sides int B_l' B_j) and (0, 1) (conditions on the N_k, right-hand sides int B_l N_k).
+__device__ int wq_local_rule(const double* T, int nT, int p, int l, int at, int ac, const double* xq, const double* gq,
                              int nq, bool shortcut, const double* gxi, const double* gw, double* w) {
     double N[WQ_PMAX + 1], dN[WQ_PMAX + 1];
     if (shortcut) {
@@ -192,14 +196,14 @@ __device__ int wq_local_rule(const double* T, int nT, int p, int l, int a, const
             int s = find_span(T, nT, p, xq[q]);
             basis_funs(T, p, s, xq[q], N, dN);
             int r = l - (s - p);
-            double b = (r >= 0 && r <= p) ? (a ? dN[r] : N[r]) : 0.0;
+            double b = (r >= 0 && r <= p) ? (at ? dN[r] : N[r]) : 0.0;
             w[q] = gq[q] * b;
         }
         return 0;
     }
-    // condition functions: degree pc = p - a over T, indices clo..chi (nonzero and
+    // condition functions: degree pc = p - ac over T, indices clo..chi (nonzero and
     // overlapping supp B_l)
-    const int pc = p - a;
+    const int pc = p - ac;
     const int nfc = nT - pc - 1;
     double tl = T[l], tr = T[l + p + 1];
     int clo = -1, chi = -1;
@@ -229,7 +233,7 @@ __device__ int wq_local_rule(const double* T, int nT, int p, int l, int a, const
             double x = t0 + (1.0 + gxi[g]) / 2.0 * (t1 - t0);
             double wg = gw[g] * (t1 - t0) / 2.0;
             basis_funs(T, p, k, x, N, dN);
-            double bl = a ? dN[l - (k - p)] : N[l - (k - p)];
+            double bl = at ? dN[l - (k - p)] : N[l - (k - p)];
             basis_funs(T, pc, k, x, Nc, dNc);
             for (int c = 0; c < mc; ++c) {
                 int r = clo + c - (k - pc);
@@ -295,12 +299,15 @@ __device__ inline void local_knots(const DevRules& R, int d, int i, double* T) {
 // ----------------------------------------------------------------------------------------
 // standard 1D WQ rules: one thread per (direction, function, derivative order)
 // ----------------------------------------------------------------------------------------
-__global__ void k_std_rules(DevRules R, int d, const double* gxi, const double* gw, int32_t* xs, int32_t* nwin,
-                            double* Wt, int8_t* qlo, int8_t* qhi, int* err) {
+// nfam = 2: families (0, 0), (1, 1) into Wt; nfam = 4 adds (1, 0), (0, 1) into Wtx.
+__global__ void k_std_rules(DevRules R, int d, int nfam, const double* gxi, const double* gw, int32_t* xs, int32_t* nwin,
+                            double* Wt, double* Wtx, int8_t* qlo, int8_t* qhi, int* err) {
     int tid = blockIdx.x * blockDim.x + threadIdx.x;
     int n = R.nfun[d], p = R.p, p1 = p + 1, m = R.m, NW = R.nw, nel = R.nel[d];
-    if (tid >= 2 * n) return;
-    int i = tid >> 1, a = tid & 1;
+    if (tid >= nfam * n) return;
+    const int i = tid / nfam, f = tid % nfam;
+    const int at = f == 0 || f == 3 ? 0 : 1, ac = f == 0 || f == 2 ? 0 : 1;
+    const int a = f;                                   // a < 2: the (a, a) family
     int elo = i - p < 0 ? 0 : i - p, ehi = i < nel - 1 ? i : nel - 1;   // inclusive
     // points: X points of elements elo..ehi (contiguous X range)
     int x0 = -1, cnt = 0;
@@ -324,10 +331,10 @@ __global__ void k_std_rules(DevRules R, int d, const double* gxi, const double* 
     double T[3 * WQ_PMAX + 2];
     local_knots(R, d, i, T);
     double w[WQ_NQREF];
-    int st = wq_local_rule(T, 3 * p + 2, p, p, a, xq, gq, cnt, all_gauss, gxi, gw, w);
+    int st = wq_local_rule(T, 3 * p + 2, p, p, at, ac, xq, gq, cnt, all_gauss, gxi, gw, w);
     if (st) { atomicExch(err, st); return; }
-    // premultiply with the trial functions j = i-p+jj: W[jj][q] = w_q B_j^(a)(x_q)
-    double* out = Wt + (((int64_t)i * 2 + a) * m) * NW;
+    // premultiply with the trial functions j = i-p+jj: W[jj][q] = w_q B_j^(ac)(x_q)
+    double* out = f < 2 ? Wt + (((int64_t)i * 2 + f) * m) * NW : Wtx + (((int64_t)i * 2 + f - 2) * m) * NW;
     for (int jj = 0; jj < m; ++jj) {
         int j = i - p + jj;
         int lo = -1, hi = -1;
@@ -337,7 +344,7 @@ __global__ void k_std_rules(DevRules R, int d, const double* gxi, const double* 
                 int y = yq[q], e = y / p1;
                 int k = j - e;          // functions on element e are e..e+p
                 if (k >= 0 && k <= p) {
-                    double bj = a ? R.dBval[d][(int64_t)y * p1 + k] : R.Bval[d][(int64_t)y * p1 + k];
+                    double bj = ac ? R.dBval[d][(int64_t)y * p1 + k] : R.Bval[d][(int64_t)y * p1 + k];
                     v = w[q] * bj;
                     if (lo < 0) lo = q;
                     hi = q + 1;
@@ -521,8 +528,9 @@ __global__ void k_split_rule(DevRules R, int64_t ncut, const int32_t* cut_rows, 
 // ----------------------------------------------------------------------------------------
 // one-sided DWQ rules (Section 2.2 steps 3-6): one thread per distinct (d, i, s, side)
 // ----------------------------------------------------------------------------------------
-__global__ void k_dwq_rules(DevRules R, int nkeys, const int32_t* key_used, const int64_t* key_off, int nmax,
-                            const double* gxi, const double* gw, int32_t* np_out, int32_t* y_out, double* Wt, int* err) {
+__global__ void k_dwq_rules(DevRules R, int nkeys, const int32_t* key_used, const int64_t* key_off, int nmax, int nfam,
+                            const double* gxi, const double* gw, int32_t* np_out, int32_t* y_out, double* Wt, double* Wtx,
+                            int* err) {
     int key = blockIdx.x * blockDim.x + threadIdx.x;
     if (key >= nkeys || !key_used[key]) return;
     int p = R.p, p1 = p + 1, m = R.m, NDQ = R.ndq;
@@ -578,8 +586,8 @@ __global__ void k_dwq_rules(DevRules R, int nkeys, const int32_t* key_used, cons
     }
     np_out[r] = nq;
     for (int q = 0; q < NDQ; ++q) y_out[(int64_t)r * NDQ + q] = q < nq ? yq[q] : yq[0];
-    double wacc[2][WQ_NDQMAX];
-    for (int a = 0; a < 2; ++a)
+    double wacc[4][WQ_NDQMAX];
+    for (int a = 0; a < nfam; ++a)
         for (int q = 0; q < nq; ++q) wacc[a][q] = 0.0;
     double side_lo = R.lo[d] + (double)slo * R.h[d], side_hi = R.lo[d] + (double)(shi + 1) * R.h[d];
     // step 5: WQ weights of every refined function on the kept side inside supp B_i
@@ -601,17 +609,19 @@ __global__ void k_dwq_rules(DevRules R, int nkeys, const int32_t* key_used, cons
                 all_gauss = all_gauss && full;
             }
         }
-        for (int a = 0; a < 2; ++a) {
+        for (int a = 0; a < nfam; ++a) {
             double wl[WQ_NQREF];
-            int st = wq_local_rule(T, nT, p, l, a, xl, gl, nl, all_gauss, gxi, gw, wl);
+            const int at = a == 0 || a == 3 ? 0 : 1, ac = a == 0 || a == 2 ? 0 : 1;
+            int st = wq_local_rule(T, nT, p, l, at, ac, xl, gl, nl, all_gauss, gxi, gw, wl);
             if (st) { atomicExch(err, st); return; }
             // step 6: w = sum_l S_il wtilde_l
             for (int q = 0; q < nl; ++q) wacc[a][map[q]] += S[l] * wl[q];
         }
     }
     // premultiply with the original trial functions j = i-p+jj
-    for (int a = 0; a < 2; ++a) {
-        double* out = Wt + (((int64_t)r * 2 + a) * m) * NDQ;
+    for (int a = 0; a < nfam; ++a) {
+        const int ac = a == 0 || a == 2 ? 0 : 1;
+        double* out = a < 2 ? Wt + (((int64_t)r * 2 + a) * m) * NDQ : Wtx + (((int64_t)r * 2 + a - 2) * m) * NDQ;
         for (int jj = 0; jj < m; ++jj) {
             int j = i - p + jj;
             for (int q = 0; q < NDQ; ++q) {
@@ -620,7 +630,7 @@ __global__ void k_dwq_rules(DevRules R, int nkeys, const int32_t* key_used, cons
                     int k = j - eq[q];
                     if (k >= 0 && k <= p) {
                         int y = yq[q];
-                        v = wacc[a][q] * (a ? R.dBval[d][(int64_t)y * p1 + k] : R.Bval[d][(int64_t)y * p1 + k]);
+                        v = wacc[a][q] * (ac ? R.dBval[d][(int64_t)y * p1 + k] : R.Bval[d][(int64_t)y * p1 + k]);
                     }
                 }
                 out[jj * NDQ + q] = v;
@@ -1185,6 +1195,8 @@ int build_rules(const wq_mesh* mesh, const wq_levelset* ls, const wq_options* op
     R.levels = opts ? opts->octree_levels : 3;
     R.ls = *ls;
     H->mesh = *mesh;
+    const bool tensor = opts && (opts->flags & WQ_OPT_TENSOR);
+    R.tensor = tensor ? 1 : 0;
     int p1 = p + 1;
     int nmax = 0;
     for (int d = 0; d < 3; ++d) {
@@ -1227,8 +1239,19 @@ int build_rules(const wq_mesh* mesh, const wq_levelset* ls, const wq_options* op
         int8_t* qhi = B.keep<int8_t>((int64_t)n * R.m);
         if (!xs || !nw || !wt || !wt32 || !qlo || !qhi) return B.fail();
         R.xs[d] = xs; R.nwin[d] = nw; R.Wt64[d] = wt; R.Wt32[d] = wt32; R.qlo[d] = qlo; R.qhi[d] = qhi;
-        hipLaunchKernelGGL(k_std_rules, grid_for(2 * n, 64), dim3(64), 0, stream, R, d, gxi, gw, xs, nw, wt, qlo, qhi, d_err);
+        double* wtx = nullptr;
+        float* wtx32 = nullptr;
+        if (tensor) {
+            wtx = B.keep<double>(nwt);
+            wtx32 = B.keep<float>(nwt);
+            if (!wtx || !wtx32) return B.fail();
+        }
+        R.Wtx64[d] = wtx; R.Wtx32[d] = wtx32;
+        const int nfam = tensor ? 4 : 2;
+        hipLaunchKernelGGL(k_std_rules, grid_for(nfam * n, 64), dim3(64), 0, stream, R, d, nfam, gxi, gw, xs, nw, wt, wtx,
+                           qlo, qhi, d_err);
         hipLaunchKernelGGL(k_convert<float>, grid_for(nwt), dim3(256), 0, stream, wt, wt32, nwt);
+        if (tensor) hipLaunchKernelGGL(k_convert<float>, grid_for(nwt), dim3(256), 0, stream, wtx, wtx32, nwt);
     }
     if (B.check(hipGetLastError())) return B.fail();
 
@@ -1317,12 +1340,16 @@ int build_rules(const wq_mesh* mesh, const wq_levelset* ls, const wq_options* op
         int64_t nwt = nr * 2 * R.m * R.ndq;
         double* dwt = B.keep<double>(nwt);
         float* dwt32 = B.keep<float>(nwt);
-        if (!dnp || !dy || !dwt || !dwt32) return B.fail();
+        double* dwtx = tensor ? B.keep<double>(nwt) : nullptr;
+        float* dwtx32 = tensor ? B.keep<float>(nwt) : nullptr;
+        if (!dnp || !dy || !dwt || !dwt32 || (tensor && (!dwtx || !dwtx32))) return B.fail();
         R.dwq_np = dnp; R.dwq_y = dy; R.dwq_Wt64 = dwt; R.dwq_Wt32 = dwt32;
+        R.dwq_Wtx64 = dwtx; R.dwq_Wtx32 = dwtx32;
         if (ndwq > 0) {
             hipLaunchKernelGGL(k_dwq_rules, grid_for(nkeys, 64), dim3(64), 0, stream, R, nkeys, key_used, key_off, nmax,
-                               gxi, gw, dnp, dy, dwt, d_err);
+                               tensor ? 4 : 2, gxi, gw, dnp, dy, dwt, dwtx, d_err);
             hipLaunchKernelGGL(k_convert<float>, grid_for(nwt), dim3(256), 0, stream, dwt, dwt32, nwt);
+            if (tensor) hipLaunchKernelGGL(k_convert<float>, grid_for(nwt), dim3(256), 0, stream, dwtx, dwtx32, nwt);
         }
     }
     {

@@ -1,0 +1,370 @@
+// Stiffness matrix with a full symmetric coefficient tensor: K_IJ = int grad B_I . C grad B_J.
+//
+// Section 2 takes the map from the parameter space to the background mesh to be the identity
+// and notes that no generality is lost; a geometry map F enters the Laplacian stiffness as
+// the tensor C = |det DF| DF^-1 DF^-T (times a material coefficient), so the nine terms
+// C_de d_d B_I d_e B_J replace the three diagonal ones of the scalar matrices.
+//
+// Regular part (interior rows; the DWQ box of cut rows, Section 2.2): weighted quadrature
+// folds the test function into 1D weights per direction, so term (d, e) uses in direction x
+// the rule family (x == d, x == e): (0, 0), (1, 1), and the mixed (1, 0) in direction d and
+// (0, 1) in direction e when d != e (built by the rule build under WQ_OPT_TENSOR, each table
+// already multiplied by the trial values or derivatives).  k_tensor_rows: one workgroup per
+// row, sum factorization split direction first (A), then B, then C point by point: per point
+// of C, stage A contracts the six tensor components over A for the nine terms, stage B over
+// B, and stage C adds the point's share into per-thread accumulators of the row window; the
+// row is then stored (interior rows: the clipped window in CSR order; cut rows through their
+// position map; cut rows without a box are zeroed).
+//
+// Element parts of cut rows (element Gauss on the remainder elements, the cut rule on the cut
+// elements; Eq. (1)): k_tensor_elems, one workgroup per cut row, walks the row's elements
+// and, per tensor block of points (an element's Gauss points, an octree leaf, or a fitted
+// element), forms the flux F_e(q) = w_q sum_d C_de(q) d_d B_I(x_q) at every point and
+// contracts it with the trial derivatives direction by direction (3, 2, 1) into the row's
+// window in LDS; the window is added into the values at the end (row-owned, no atomics).
+#include "rows.h"
+
+namespace {
+
+template <typename T> __device__ inline const T* wt_tab(const DevRules& R, int d);
+template <> __device__ inline const double* wt_tab<double>(const DevRules& R, int d) { return R.Wt64[d]; }
+template <> __device__ inline const float* wt_tab<float>(const DevRules& R, int d) { return R.Wt32[d]; }
+template <typename T> __device__ inline const T* wtx_tab(const DevRules& R, int d);
+template <> __device__ inline const double* wtx_tab<double>(const DevRules& R, int d) { return R.Wtx64[d]; }
+template <> __device__ inline const float* wtx_tab<float>(const DevRules& R, int d) { return R.Wtx32[d]; }
+template <typename T> __device__ inline const T* dwq_tab(const DevRules& R);
+template <> __device__ inline const double* dwq_tab<double>(const DevRules& R) { return R.dwq_Wt64; }
+template <> __device__ inline const float* dwq_tab<float>(const DevRules& R) { return R.dwq_Wt32; }
+template <typename T> __device__ inline const T* dwqx_tab(const DevRules& R);
+template <> __device__ inline const double* dwqx_tab<double>(const DevRules& R) { return R.dwq_Wtx64; }
+template <> __device__ inline const float* dwqx_tab<float>(const DevRules& R) { return R.dwq_Wtx32; }
+template <typename T> __device__ inline const T* octw_tab(const DevRules& R);
+template <> __device__ inline const double* octw_tab<double>(const DevRules& R) { return R.oct_w; }
+template <> __device__ inline const float* octw_tab<float>(const DevRules& R) { return R.oct_w32; }
+
+// family of direction slot x in term (u, v): 0 = (0, 0), 1 = (1, 1), 2 = (1, 0), 3 = (0, 1)
+__device__ inline int tfam(int x, int u, int v) { return x == u ? (x == v ? 1 : 2) : (x == v ? 3 : 0); }
+// storage index of C_de: C11, C22, C33, C12, C13, C23
+__device__ inline int tcomp(int d, int e) {
+    if (d == e) return d;
+    const int a = d < e ? d : e, b = d < e ? e : d;
+    return a == 0 ? (b == 1 ? 3 : 4) : 5;
+}
+
+template <int P>
+struct TenCfg {
+    static constexpr int P1 = P + 1, M = 2 * P + 1, MM = M * M, M3 = MM * M;
+    static constexpr int NW = 4 * P, NDQ = P * (P + 1), NA = NDQ > NW ? NDQ : NW;
+    static constexpr int NN = 2 * P + 1;                // points per direction of a block (fitted rule: 2p+1)
+    static constexpr int NT = 256;
+    static constexpr int NACC = (M3 + NT - 1) / NT;
+};
+
+// ---------------------------------------------------------------------------------------
+// regular part: one workgroup per active row
+// ---------------------------------------------------------------------------------------
+template <typename T, int P>
+__global__ void __launch_bounds__(256)
+k_tensor_rows(DevRules R, const T* __restrict__ C, int64_t ldc, const int32_t* __restrict__ act2cut,
+              T* __restrict__ vk) {
+    using Cf = TenCfg<P>;
+    constexpr int M = Cf::M, MM = Cf::MM, M3 = Cf::M3, NW = Cf::NW, NDQ = Cf::NDQ, NA = Cf::NA, NT = Cf::NT;
+    __shared__ T s_w[3][4 * M * NA];                  // [slot][family][jj][q]
+    __shared__ int s_y[3][NA];
+    __shared__ int s_n[3];
+    __shared__ T s_c[6][NW * NA];                     // tensor components at one C point, [qB][qA]
+    __shared__ T s_t1[9][NW * M];                     // [term][qB][jA]
+    __shared__ T s_t2[9][MM];                         // [term][jB jA]
+    const int ra = blockIdx.x;
+    const int t = threadIdx.x;
+    const int cr = act2cut[ra];
+    const int4 sp = cr >= 0 ? R.split[cr] : make_int4(-1, 0, 0, -1);
+    const int64_t rb = R.row_ptr[ra], re = R.row_ptr[ra + 1];
+    if (cr >= 0 && sp.x < 0) {                        // cut row without a box: element parts only
+        for (int64_t k = rb + t; k < re; k += NT) vk[k] = 0;
+        return;
+    }
+    int I[3];
+    {
+        const int lex = R.act2lex[ra];
+        I[2] = lex % R.nfun[2]; I[1] = (lex / R.nfun[2]) % R.nfun[1]; I[0] = lex / (R.nfun[1] * R.nfun[2]);
+    }
+    const int dA = sp.x >= 0 ? sp.x : 0, dB = dA == 0 ? 1 : 0, dC = dA == 2 ? 1 : 2;
+    const int dirs[3] = {dA, dB, dC};
+    for (int sl = 0; sl < 3; ++sl) {
+        const int d = dirs[sl];
+        if (sl == 0 && sp.x >= 0) {
+            const int r = sp.w;
+            const int np = R.dwq_np[r];
+            const T* W0 = dwq_tab<T>(R) + (int64_t)r * 2 * M * NDQ;
+            const T* W1 = dwqx_tab<T>(R) + (int64_t)r * 2 * M * NDQ;
+            for (int k = t; k < 4 * M * NA; k += NT) {
+                const int q = k % NA, row = k / NA;       // row = family * M + jj
+                const T* W = row < 2 * M ? W0 : W1;
+                const int rr = row < 2 * M ? row : row - 2 * M;
+                s_w[sl][k] = q < NDQ ? W[rr * NDQ + q] : (T)0;
+            }
+            for (int q = t; q < NA; q += NT) s_y[sl][q] = q < np ? R.dwq_y[(int64_t)r * NDQ + q] : 0;
+            if (t == 0) s_n[sl] = np;
+        } else {
+            const int i = I[d];
+            const int xs = R.xs[d][i], nw = R.nwin[d][i];
+            const T* W0 = wt_tab<T>(R, d) + (int64_t)i * 2 * M * NW;
+            const T* W1 = wtx_tab<T>(R, d) + (int64_t)i * 2 * M * NW;
+            for (int k = t; k < 4 * M * NA; k += NT) {
+                const int q = k % NA, row = k / NA;
+                const T* W = row < 2 * M ? W0 : W1;
+                const int rr = row < 2 * M ? row : row - 2 * M;
+                s_w[sl][k] = q < NW ? W[rr * NW + q] : (T)0;
+            }
+            for (int q = t; q < NA; q += NT) s_y[sl][q] = q < nw ? R.x2y[d][xs + q] : 0;
+            if (t == 0) s_n[sl] = nw;
+        }
+    }
+    __syncthreads();
+    const int nA = s_n[0], nB = s_n[1], nC = s_n[2];
+    T acc[Cf::NACC];
+#pragma unroll
+    for (int i = 0; i < Cf::NACC; ++i) acc[i] = 0;
+    for (int qC = 0; qC < nC; ++qC) {
+        const int yC = s_y[2][qC];
+        for (int k = t; k < 6 * nB * nA; k += NT) {   // tensor components at the points (qA, qB, qC)
+            const int comp = k / (nB * nA), qB = (k / nA) % nB, qA = k % nA;
+            const int yA = s_y[0][qA], yB = s_y[1][qB];
+            const int64_t slot = slot_of(R, pick3(0, dA, dB, yA, yB, yC), pick3(1, dA, dB, yA, yB, yC),
+                                         pick3(2, dA, dB, yA, yB, yC));
+            s_c[comp][qB * NA + qA] = C[comp * ldc + slot];
+        }
+        __syncthreads();
+        // stage A: T1[term][qB][jA] = sum_qA W_A^f[jA][qA] C_term(qA, qB)
+        for (int it = t; it < 9 * nB * M; it += NT) {
+            const int term = it / (nB * M), qB = (it / M) % nB, jA = it % M;
+            const int u = term / 3, v = term % 3;
+            const T* w = s_w[0] + (tfam(0, u, v) * M + jA) * NA;
+            const T* c = s_c[tcomp(dirs[u], dirs[v])] + qB * NA;
+            T a = 0;
+            for (int qA = 0; qA < nA; ++qA) a = fmat(w[qA], c[qA], a);
+            s_t1[term][qB * M + jA] = a;
+        }
+        __syncthreads();
+        // stage B: T2[term][jB jA] = sum_qB W_B^f[jB][qB] T1[term][qB][jA]
+        for (int it = t; it < 9 * MM; it += NT) {
+            const int term = it / MM, jB = (it / M) % M, jA = it % M;
+            const int u = term / 3, v = term % 3;
+            const T* w = s_w[1] + (tfam(1, u, v) * M + jB) * NA;
+            T a = 0;
+            for (int qB = 0; qB < nB; ++qB) a = fmat(w[qB], s_t1[term][qB * M + jA], a);
+            s_t2[term][jB * M + jA] = a;
+        }
+        __syncthreads();
+        // stage C: acc[jC][jB jA] += sum_term W_C^f[jC][qC] T2[term][jB jA]
+#pragma unroll
+        for (int i = 0; i < Cf::NACC; ++i) {
+            const int it = t + i * NT;
+            if (it < M3) {
+                const int jC = it / MM, jBA = it % MM;
+                T a = acc[i];
+#pragma unroll
+                for (int term = 0; term < 9; ++term)
+                    a = fmat(s_w[2][(tfam(2, term / 3, term % 3) * M + jC) * NA + qC], s_t2[term][jBA], a);
+                acc[i] = a;
+            }
+        }
+    }
+    // store: window entry j (0..2p per direction) is function I - p + j
+    int lo[3], n[3];
+    for (int d = 0; d < 3; ++d) {
+        const int a = I[d] - P < 0 ? 0 : I[d] - P, b = I[d] + P > R.nfun[d] - 1 ? R.nfun[d] - 1 : I[d] + P;
+        lo[d] = a - (I[d] - P);
+        n[d] = b - a + 1;
+    }
+    const int32_t* pos = cr >= 0 ? R.pos_map + (int64_t)cr * M3 : nullptr;
+#pragma unroll
+    for (int i = 0; i < Cf::NACC; ++i) {
+        const int it = t + i * NT;
+        if (it >= M3) continue;
+        const int jC = it / MM, jB = (it / M) % M, jA = it % M;
+        const int j0 = pick3(0, dA, dB, jA, jB, jC), j1 = pick3(1, dA, dB, jA, jB, jC), j2 = pick3(2, dA, dB, jA, jB, jC);
+        if (pos) {
+            const int o = pos[(j0 * M + j1) * M + j2];
+            if (o >= 0) vk[rb + o] = acc[i];
+        } else {
+            const int a0 = j0 - lo[0], a1 = j1 - lo[1], a2 = j2 - lo[2];
+            if (a0 >= 0 && a0 < n[0] && a1 >= 0 && a1 < n[1] && a2 >= 0 && a2 < n[2])
+                vk[rb + ((int64_t)a0 * n[1] + a1) * n[2] + a2] = acc[i];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// element parts of the cut rows: one workgroup per cut row
+// ---------------------------------------------------------------------------------------
+// B_{e+k} and B'_{e+k}, k = 0..p, at x inside element e of direction d
+__device__ inline void elem_basis(const DevRules& R, int d, int e, double x, double* N, double* dN) {
+    const int p = R.p;
+    double Tk[2 * WQ_PMAX + 2];
+    for (int k = 0; k < 2 * p + 2; ++k) {
+        int kk = e + k - p;
+        kk = kk < 0 ? 0 : (kk > R.nel[d] ? R.nel[d] : kk);
+        Tk[k] = R.lo[d] + (double)kk * R.h[d];
+    }
+    basis_funs(Tk, p, p, x, N, dN);
+}
+
+template <typename T, int P>
+__global__ void __launch_bounds__(256)
+k_tensor_elems(DevRules R, const T* __restrict__ C, int64_t ldc, const double* __restrict__ xyz,
+               T* __restrict__ vk) {
+    using Cf = TenCfg<P>;
+    constexpr int P1 = Cf::P1, M = Cf::M, M3 = Cf::M3, NN = Cf::NN, NT = Cf::NT;
+    constexpr int NN3 = NN * NN * NN;
+    __shared__ T s_acc[M3];
+    __shared__ T s_f[3][NN3];                         // flux components at the block's points
+    __shared__ T s_t1[3][NN * NN * P1];               // [e][g1 g2][k3]
+    __shared__ T s_t2[3][NN * P1 * P1];               // [e][g1][k2 k3]
+    __shared__ T s_b[3][2][P1][NN];                   // [d][value / derivative][k][g]
+    const int64_t cr = blockIdx.x;
+    const int t = threadIdx.x;
+    const int ra = R.cut_rows[cr];
+    int I[3];
+    {
+        const int lex = R.act2lex[ra];
+        I[2] = lex % R.nfun[2]; I[1] = (lex / R.nfun[2]) % R.nfun[1]; I[0] = lex / (R.nfun[1] * R.nfun[2]);
+    }
+    for (int k = t; k < M3; k += NT) s_acc[k] = 0;
+    const int nrem = R.rem_ptr[cr + 1] - R.rem_ptr[cr];
+    const int ncut = R.rcut_ptr[cr + 1] - R.rcut_ptr[cr];
+    const int64_t oct0 = R.n_grid + R.n_block;
+    const int nkf = 2 * P + 1, nkf3 = nkf * nkf * nkf;
+    for (int el = 0; el < nrem + ncut; ++el) {
+        int e[3];
+        int nblk, n;
+        int64_t base = 0;                             // first slot of the block's points (octree / fitted)
+        int2 en;
+        bool rem = el < nrem;
+        if (rem) {
+            en = R.rem_list[R.rem_ptr[cr] + el];
+            const int pk = en.x;
+            e[0] = I[0] - (pk & 15); e[1] = I[1] - ((pk >> 4) & 15); e[2] = I[2] - ((pk >> 8) & 15);
+            nblk = 1; n = P1;
+        } else {
+            en = R.rcut_list[R.rcut_ptr[cr] + el - nrem];
+            const int pk = en.y;
+            e[0] = I[0] - (pk & 15); e[1] = I[1] - ((pk >> 4) & 15); e[2] = I[2] - ((pk >> 8) & 15);
+            if (R.fit) { nblk = 1; n = nkf; base = oct0 + (int64_t)en.x * nkf3; }
+            else { nblk = R.cell_begin[en.x + 1] - R.cell_begin[en.x]; n = P1; }
+        }
+        const int kI[3] = {I[0] - e[0], I[1] - e[1], I[2] - e[2]};
+        const int n3 = n * n * n;
+        for (int blk = 0; blk < nblk; ++blk) {
+            int64_t cell = -1;
+            if (!rem && !R.fit) { cell = R.cell_begin[en.x] + blk; base = oct0 + cell * (P1 * P1 * P1); }
+            // slot of point (g1, g2, g3) of the block
+            auto slot_at = [&](int g1, int g2, int g3) -> int64_t {
+                if (rem) return slot_of(R, e[0] * P1 + g1, e[1] * P1 + g2, e[2] * P1 + g3);
+                return base + (g1 * n + g2) * n + g3;
+            };
+            __syncthreads();                          // the previous block's tables are no longer read
+            // 1D basis values at the block's nodes (coordinates read from the slot layout)
+            for (int k = t; k < 3 * n; k += NT) {
+                const int d = k / n, g = k % n;
+                const int64_t s = slot_at(d == 0 ? g : 0, d == 1 ? g : 0, d == 2 ? g : 0);
+                double N[WQ_PMAX + 1], dN[WQ_PMAX + 1];
+                elem_basis(R, d, e[d], xyz[s * 3 + d], N, dN);
+                for (int kk = 0; kk < P1; ++kk) { s_b[d][0][kk][g] = (T)N[kk]; s_b[d][1][kk][g] = (T)dN[kk]; }
+            }
+            __syncthreads();
+            // flux F_e = w sum_d C_de d_d B_I at every point
+            for (int q = t; q < n3; q += NT) {
+                const int g1 = q / (n * n), g2 = (q / n) % n, g3 = q % n;
+                const int64_t s = slot_at(g1, g2, g3);
+                T w;
+                if (rem) w = (T)(R.gw[g1] * R.gw[g2] * R.gw[g3] * (R.h[0] * R.h[1] * R.h[2] / 8.0));
+                else w = octw_tab<T>(R)[s - oct0];
+                const T v0 = s_b[0][0][kI[0]][g1], v1 = s_b[1][0][kI[1]][g2], v2 = s_b[2][0][kI[2]][g3];
+                const T gt[3] = {s_b[0][1][kI[0]][g1] * v1 * v2, v0 * s_b[1][1][kI[1]][g2] * v2, v0 * v1 * s_b[2][1][kI[2]][g3]};
+                T c[6];
+#pragma unroll
+                for (int k = 0; k < 6; ++k) c[k] = C[k * ldc + s];
+#pragma unroll
+                for (int ee = 0; ee < 3; ++ee) {
+                    T f = c[tcomp(0, ee)] * gt[0];
+                    f = fmat(c[tcomp(1, ee)], gt[1], f);
+                    f = fmat(c[tcomp(2, ee)], gt[2], f);
+                    s_f[ee][q] = w * f;
+                }
+            }
+            __syncthreads();
+            // stage 1: T1[e][g1 g2][k3] = sum_g3 D3^e[k3][g3] F_e
+            for (int it = t; it < 3 * n * n * P1; it += NT) {
+                const int ee = it / (n * n * P1), g12 = (it / P1) % (n * n), k3 = it % P1;
+                const T* bz = s_b[2][ee == 2][k3];
+                T a = 0;
+                for (int g3 = 0; g3 < n; ++g3) a = fmat(bz[g3], s_f[ee][g12 * n + g3], a);
+                s_t1[ee][g12 * P1 + k3] = a;
+            }
+            __syncthreads();
+            // stage 2: T2[e][g1][k2 k3] = sum_g2 D2^e[k2][g2] T1[e][g1 g2][k3]
+            for (int it = t; it < 3 * n * P1 * P1; it += NT) {
+                const int ee = it / (n * P1 * P1), g1 = (it / (P1 * P1)) % n, k2 = (it / P1) % P1, k3 = it % P1;
+                const T* by = s_b[1][ee == 1][k2];
+                T a = 0;
+                for (int g2 = 0; g2 < n; ++g2) a = fmat(by[g2], s_t1[ee][(g1 * n + g2) * P1 + k3], a);
+                s_t2[ee][(g1 * P1 + k2) * P1 + k3] = a;
+            }
+            __syncthreads();
+            // stage 3: window[k] += sum_e sum_g1 D1^e[k1][g1] T2[e][g1][k2 k3]
+            for (int it = t; it < P1 * P1 * P1; it += NT) {
+                const int k1 = it / (P1 * P1), k2 = (it / P1) % P1, k3 = it % P1;
+                T a = 0;
+#pragma unroll
+                for (int ee = 0; ee < 3; ++ee) {
+                    const T* bx = s_b[0][ee == 0][k1];
+                    for (int g1 = 0; g1 < n; ++g1) a = fmat(bx[g1], s_t2[ee][(g1 * P1 + k2) * P1 + k3], a);
+                }
+                const int j0 = e[0] + k1 - (I[0] - P), j1 = e[1] + k2 - (I[1] - P), j2 = e[2] + k3 - (I[2] - P);
+                s_acc[(j0 * M + j1) * M + j2] += a;
+            }
+        }
+    }
+    __syncthreads();
+    const int64_t rb = R.row_ptr[ra];
+    const int32_t* pos = R.pos_map + cr * M3;
+    for (int k = t; k < M3; k += NT) {
+        const int o = pos[k];
+        if (o >= 0) vk[rb + o] += s_acc[k];
+    }
+}
+
+template <typename T, int P>
+void launch_tensor_p(const wq_rules* H, const T* C, int64_t ldc, T* vk, hipStream_t s) {
+    const DevRules& R = H->R;
+    if (H->n_active > 0)
+        hipLaunchKernelGGL((k_tensor_rows<T, P>), dim3((unsigned)H->n_active), dim3(256), 0, s, R, C, ldc,
+                           (const int32_t*)H->act2cut, vk);
+    if (H->n_cut > 0)
+        hipLaunchKernelGGL((k_tensor_elems<T, P>), dim3((unsigned)H->n_cut), dim3(256), 0, s, R, C, ldc,
+                           (const double*)H->kappa_xyz, vk);
+}
+
+}  // namespace
+
+template <typename T>
+int launch_tensor(const wq_rules* H, const T* C, T* vk, hipStream_t s) {
+    const int64_t ldc = H->R.n_kappa;
+    switch (H->R.p) {
+        case 1: launch_tensor_p<T, 1>(H, C, ldc, vk, s); break;
+        case 2: launch_tensor_p<T, 2>(H, C, ldc, vk, s); break;
+        case 3: launch_tensor_p<T, 3>(H, C, ldc, vk, s); break;
+        case 4: launch_tensor_p<T, 4>(H, C, ldc, vk, s); break;
+        default: return WQ_EUNSUPPORTED;
+    }
+    return WQ_OK;
+}
+
+#ifndef WQ_ONLY_F32
+template int launch_tensor<double>(const wq_rules*, const double*, double*, hipStream_t);
+#endif
+#ifndef WQ_ONLY_F64
+template int launch_tensor<float>(const wq_rules*, const float*, float*, hipStream_t);
+#endif

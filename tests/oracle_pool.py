@@ -115,3 +115,44 @@ def load_vector(wl, f_name, n_active=None, rows=None):
         else:
             _CACHE[key] = np.sum(_map(_load_share, [(wl, f_name, k, n, rows) for k in range(n)]), axis=0)
     return _CACHE[key]
+
+
+def _tensor_share(args):
+    wl, field, mag, k, n = args
+    import numpy as np
+
+    import workloads as W
+    from oracle import tensor as OT
+    from oracle.assemble import Problem
+    from oracle.domain import octree_points
+    from oracle.spline import gauss_legendre
+    P = Problem(wl)
+    C_fn = W.TENSOR_FIELDS[field] if isinstance(field, str) else (lambda x, C0=np.asarray(field): np.broadcast_to(C0, (x.shape[0], 3, 3)))
+    if mag:
+        # rounding scale of a fitted cut rule: |w_g| + vol_e W_g / |e| on the cut elements, |C|
+        sl = P.slots(with_octree=False)
+        if sl.fit:
+            nk = 2 * wl.degree + 1
+            _, gw = gauss_legendre(nk)
+            gw3 = np.einsum("a,b,c->abc", gw, gw, gw).ravel() / 8.0
+            for e in sl.cut:
+                xf, wf = sl.octree(e)
+                vol = np.abs(octree_points(P.lines, P.dom.ls, e, sl.levels)[1]).sum()
+                sl._oct[e] = (xf, np.abs(wf) + vol * gw3)
+        base = C_fn
+        C_fn = lambda x: np.abs(base(x))
+    return OT.assemble(P, C_fn, share=(k, n))
+
+
+def tensor(wl, field, n_active=None, mag=False):
+    """Oracle stiffness with a coefficient tensor: field is a name of workloads.TENSOR_FIELDS
+    or a constant 3x3 tensor (as a tuple of tuples).  mag=True: the same sums with |C| and,
+    for a fitted cut rule, the weights |w| + vol_e W_g / |e| (the rounding scale)."""
+    key = ("tensor", wl, field, mag)
+    if key not in _CACHE:
+        n = _workers(n_active or 64)
+        if n == 1:
+            _CACHE[key] = _tensor_share((wl, field, mag, 0, 1))
+        else:
+            _CACHE[key] = sum(_map(_tensor_share, [(wl, field, mag, k, n) for k in range(n)]))
+    return _CACHE[key]
