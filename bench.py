@@ -57,6 +57,9 @@ def parse():
                     help="the paper's accuracy and timing experiment instead of the benchmark: L2 projection of "
                          "sin(2xz)cos(3yz) on [-1,1]^3 below the inclined plane, schemes Ref / Hybrid / DWQ, one JSON "
                          "line per (h, p)")
+    ap.add_argument("--tensor", choices=["fit", "octree"], default=None,
+                    help="only the stiffness with the map's coefficient tensor (wq_assemble_tensor) on the workload, "
+                         "cut elements by the fitted rule or the octree; one JSON line")
     ap.add_argument("--sweep-h", default="4,8,16,32,64")
     ap.add_argument("--sweep-p", default="2,3,4,5,6")
     return ap.parse_args()
@@ -304,10 +307,36 @@ def paper_sweep(args):
             print(json.dumps(rec), flush=True)
 
 
+def tensor_only(args):
+    """K steps of wq_assemble_tensor (the map's coefficient tensor at the slots, resident in
+    HBM) after W warm-ups; prints nnz/s and the mean step time."""
+    import torch
+
+    import workloads as W
+    from paper_2211_06427_amd import Rules
+    wl = W.with_cut_rule(W.workload(args.workload), args.tensor)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    R = Rules.from_workload(wl, tensor=True)
+    dt = torch.float32 if args.dtype == "f32" else torch.float64
+    Cm = W.tensor_components(W.map_tensor(R.kappa_xyz())).to(dt).contiguous()
+    vk = torch.empty(R.nnz, dtype=dt, device=dev)
+    for _ in range(args.warmup):
+        R.assemble_tensor(Cm, vk)
+    ms = timed(lambda: R.assemble_tensor(Cm, vk), args.steps, torch)
+    print(json.dumps({"metric": "tensor stiffness nnz/s", "value": R.nnz / (ms * 1e-3), "unit": "nnz/s",
+                      "ms_per_step": ms, "steps": args.steps, "warmup": args.warmup, "dtype": args.dtype,
+                      "config": {"workload": wl.name, "cut_rule": args.tensor, "field": "map pull-back tensor",
+                                 "nnz": R.nnz, "n_kappa": R.n_kappa}}), flush=True)
+
+
 def main():
     args = parse()
     if args.copy_probe:
         copy_probe()
+        return
+    if args.tensor:
+        tensor_only(args)
         return
     if args.paper_sweep:
         paper_sweep(args)
@@ -464,6 +493,29 @@ def main():
         schemes[k]["dwq_fit_ms"] = timed(step_f, nrep, torch)
     schemes["fit_kappa_slots"] = {"octree": R.n_kappa, "fit": Rf.n_kappa}
     del Rf, kf_slots
+    # stiffness with the coefficient tensor of a geometry map (wq_assemble_tensor), beside the
+    # scalar stiffness of the same rules; cut elements by the octree and by the fitted rule
+    if wl.degree <= 4:
+        tens = {}
+        for rule in ("octree", "fit"):
+            Rt = Rules.from_workload(W.with_cut_rule(wl, rule), tensor=True)
+            Cm = W.tensor_components(W.map_tensor(Rt.kappa_xyz()))
+            ks = W.kappa_at(wl, Rt.kappa_xyz())
+            for k in ("f64", "f32"):
+                Ck = Cm.to(dt[k]).contiguous()
+                vk_t = torch.empty(Rt.nnz, dtype=dt[k], device=dev)
+                Rt.assemble_tensor(Ck, vk_t)
+                kk = ks.to(dt[k])
+
+                def step_s():
+                    Rt.assemble_rows(kk, None, vk_t, which=2)
+                    Rt.cut_assemble(kk, None, vk_t, which=2)
+
+                tens.setdefault(rule, {})[k + "_ms"] = timed(lambda: Rt.assemble_tensor(Ck, vk_t), 3, torch)
+                tens[rule][k + "_scalar_stiff_ms"] = timed(step_s, 3, torch)
+                del vk_t, Ck, kk
+            del Rt, Cm, ks
+        schemes["tensor_stiffness"] = tens
 
     # --- rooflines (durations from the timed region) -----------------------------------
     esz = 8 if main_dt == "f64" else 4

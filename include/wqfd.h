@@ -122,7 +122,7 @@ typedef struct {
     int64_t n_kappa;         /* kappa slots = n_grid + n_block + n_octree */
     int64_t n_grid;          /* WQ tensor grid X1 x X2 x X3, lexicographic */
     int64_t n_block;         /* element Gauss blocks, (p+1)^3 per block element */
-    int64_t n_octree;        /* octree points, (p+1)^3 per octree leaf */
+    int64_t n_octree;        /* octree points, (p+1)^3 per octree leaf (fitted rule: (2p+1)^3 per cut element) */
     int64_t n_block_elems;   /* elements carrying a Gauss block */
     int64_t n_cut_elems;     /* cut elements */
     int64_t n_cells;         /* octree leaves */
@@ -137,7 +137,7 @@ typedef struct {
     const int32_t* col_idx;        /* (nnz) active column indices, ascending per row */
     const int32_t* active_to_lex;  /* (n_active) lexicographic function index, first index slowest */
     const double* kappa_xyz;       /* (n_kappa, 3) slot coordinates */
-    const double* octree_w;        /* (n_octree) octree weights (0 outside Omega) */
+    const double* octree_w;        /* (n_octree) octree weights (0 outside Omega; fitted weights under WQ_OPT_MOMENT_FIT) */
     const int32_t* block_elems;    /* (n_block_elems) lexicographic element index per block */
     const int8_t* fun_class;       /* (nfun product) 0 exterior, 1 interior, 2 cut */
     const int8_t* elem_class;      /* (nel product) 0 exterior, 1 interior, 2 cut */
@@ -226,12 +226,15 @@ int wq_gauss_coords(const wq_rules* rules, double* xyz, void* stream);
  * of a target function f, extended B-splines for a well-conditioned system; Section 3.2:
  * relative L2 error).  FP64 only.  The paper refers to other works for the extension; the
  * library reads it as follows.  Inner functions: active functions with an interior element in
- * their support; the others are outer.  The array of an outer function j is the block
- * l + {0..p}^3 of inner functions whose centre l + p/2 is nearest to j (Euclidean; the
- * lexicographically first l on ties); j enters the basis through its array with the
- * coefficients prod_d L_{i_d - l_d}(j_d - l_d), L_a the Lagrange polynomials on the nodes
- * 0..p.  E (n_active x n_inner) maps the coefficients of the extended basis to those of the
- * active functions; the projection solves E^T M E c = E^T b and returns u = E c.
+ * their support; the others are outer.  The root element l of an outer function j is the
+ * interior element whose centre is nearest to the centre of supp B_j (|l + p/2 - j| in
+ * element units, Euclidean; the lexicographically first l on ties); its array is the block
+ * l + {0..p}^3 of inner functions.  j enters the basis through its array with the
+ * coefficients e_ij = lambda_j(P_i), P_i the polynomial piece of B_i on l and lambda_j the
+ * dual functional of B_j (a product over the directions; on uniform knots the Lagrange
+ * extrapolation weights in the index).  E (n_active x n_inner) maps the coefficients of the
+ * extended basis to those of the active functions; the projection solves E^T M E c = E^T b
+ * and returns u = E c.
  * --------------------------------------------------------------------------------------- */
 typedef struct wq_extension wq_extension;   /* opaque; owns its device buffers */
 
