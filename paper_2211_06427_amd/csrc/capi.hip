@@ -214,7 +214,8 @@ int wq_assemble_tensor(const wq_rules* r, int dtype, const void* C, void* vals_s
     if (r->nnz == 0) return WQ_OK;
     int st = dtype == WQ_F64 ? launch_tensor<double>(r, (const double*)C, (double*)vals_stiff, (hipStream_t)stream)
                              : launch_tensor<float>(r, (const float*)C, (float*)vals_stiff, (hipStream_t)stream);
-    if (st) return wq_set_error(st, "wq_assemble_tensor: unsupported degree %d", r->R.p);
+    if (st == WQ_EUNSUPPORTED) return wq_set_error(st, "wq_assemble_tensor: unsupported degree %d", r->R.p);
+    if (st) return st;                                  // the message is set where the error arose
     return check_launch("wq_assemble_tensor");
 }
 

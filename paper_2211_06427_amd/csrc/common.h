@@ -84,6 +84,8 @@ struct DevRules {
     const float* oct_w32;               // the same rounded once to FP32
     const double* bern_q64[3];          // per direction [e][v][a][b][k]: Bernstein coefficients of basis products
     const float* bern_q32[3];
+    const double* bern_qx64[3];         // WQ_OPT_TENSOR: per direction [e][a][b][k], phi_a' phi_b
+    const float* bern_qx32[3];
     const double* bern_i64;             // [interval][k][g]: degree-2p Bernstein values at octree Gauss points
     const float* bern_i32;
     // fitted cut-element rule (WQ_OPT_MOMENT_FIT): the NK^3 tensor Gauss points of every cut

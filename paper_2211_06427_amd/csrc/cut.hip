@@ -1448,6 +1448,148 @@ static int launch_cut_w(const wq_rules* H, uint32_t which, uint32_t parts, const
     return launch_cut_p<T, P, 3>(H, parts, kappa, vm, vk, s, buf, cap);
 }
 
+// ----------------------------------------------------------------------------------------
+// Cut elements of the coefficient-tensor stiffness (wq_assemble_tensor): the moments of each
+// of the six components C_c of the tensor (w C_c in place of w kappa, octree or fitted points),
+// then per element the local stiffness rows
+//   K[a][b] = sum_{d,e} sum_k Q1^f(x=0)[a1 b1][k1] Q2^f(x=1)[a2 b2][k2] Q3^f(x=2)[a3 b3][k3] Mom_{C_de}[k],
+// with the family f of direction x in term (d, e): phi_a phi_b (x not d, e), phi_a' phi_b'
+// (x = d = e), phi_a' phi_b (x = d only), phi_a phi_b' (x = e only), all as degree-2p
+// Bernstein coefficients; the row gather of the scalar path then adds them into the cut rows.
+// ----------------------------------------------------------------------------------------
+template <typename T> __device__ inline const T* bern_qx(const DevRules& R, int d);
+template <> __device__ inline const double* bern_qx<double>(const DevRules& R, int d) { return R.bern_qx64[d]; }
+template <> __device__ inline const float* bern_qx<float>(const DevRules& R, int d) { return R.bern_qx32[d]; }
+
+// one workgroup per (cut element, a3); mom: [component][cut element][k]; loc: the gather's
+// layout, stiffness half (v = 1)
+template <typename T, int P>
+__global__ void __launch_bounds__(256)
+k_tensor_local(DevRules R, const T* __restrict__ mom, int64_t n, T* __restrict__ loc) {
+    using C = MomCfg<P>;
+    constexpr int P1 = C::P1, P2 = C::P2, NP = C::NP, NK = C::NK, NK3 = C::NK3, NT = 256;
+    constexpr int NBLK = P2 * NP, NI = P2 * P2 * P1, KR = (NI + NT - 1) / NT;
+    __shared__ T s_m[NK3];
+    __shared__ T s_q[3][4][P2][NK];                  // [direction][family][a b][k]
+    __shared__ T s_t1[NK * NK * P1];                 // [k1 k2][b3]
+    __shared__ T s_t2[NK * P1 * P2];                 // [k1][a2 b2 b3]
+    const int64_t ce = blockIdx.x / P1;
+    const int a3 = blockIdx.x % P1;
+    const int t = threadIdx.x;
+    const int64_t eid = R.cut_elems[ce];
+    const int el[3] = {(int)(eid / ((int64_t)R.nel[1] * R.nel[2])), (int)((eid / R.nel[2]) % R.nel[1]), (int)(eid % R.nel[2])};
+    for (int i = t; i < 3 * 4 * P2 * NK; i += NT) {
+        const int d = i / (4 * P2 * NK), f = (i / (P2 * NK)) % 4, ab = (i / NK) % P2, k = i % NK;
+        const int a = ab / P1, b = ab % P1;
+        T v;
+        if (f < 2) v = bern_q<T>(R, d)[(((int64_t)el[d] * 2 + f) * P2 + ab) * NK + k];
+        else if (f == 2) v = bern_qx<T>(R, d)[(((int64_t)el[d] * P1 + a) * P1 + b) * NK + k];
+        else v = bern_qx<T>(R, d)[(((int64_t)el[d] * P1 + b) * P1 + a) * NK + k];
+        s_q[d][f][ab][k] = v;
+    }
+    T acc[KR];
+#pragma unroll
+    for (int r = 0; r < KR; ++r) acc[r] = 0;
+    for (int c = 0; c < 6; ++c) {
+        __syncthreads();
+        for (int k = t; k < NK3; k += NT) s_m[k] = mom[((int64_t)c * n + ce) * NK3 + k];
+        const int nterm = c < 3 ? 1 : 2;
+        for (int tm = 0; tm < nterm; ++tm) {
+            int d, e;
+            if (c < 3) { d = c; e = c; }
+            else {
+                const int lo = c == 5 ? 1 : 0, hi = c == 3 ? 1 : 2;
+                d = tm == 0 ? lo : hi; e = tm == 0 ? hi : lo;
+            }
+            const int f1 = d == 0 ? (e == 0 ? 1 : 2) : (e == 0 ? 3 : 0);
+            const int f2 = d == 1 ? (e == 1 ? 1 : 2) : (e == 1 ? 3 : 0);
+            const int f3 = d == 2 ? (e == 2 ? 1 : 2) : (e == 2 ? 3 : 0);
+            __syncthreads();
+            for (int i = t; i < NK * NK * P1; i += NT) {     // [k1 k2][b3] = sum_k3 Q3[a3 b3][k3] Mom[k1 k2 k3]
+                const int k12 = i / P1, b3 = i % P1;
+                const T* q = s_q[2][f3][a3 * P1 + b3];
+                T v = 0;
+#pragma unroll
+                for (int k3 = 0; k3 < NK; ++k3) v = fmat(q[k3], s_m[k12 * NK + k3], v);
+                s_t1[i] = v;
+            }
+            __syncthreads();
+            for (int i = t; i < NK * P1 * P2; i += NT) {     // [k1][a2 b2 b3] = sum_k2 Q2[a2 b2][k2] T1[k1 k2][b3]
+                const int k1 = i / (P1 * P2), ab2 = (i / P1) % P2, b3 = i % P1;
+                const T* q = s_q[1][f2][ab2];
+                T v = 0;
+#pragma unroll
+                for (int k2 = 0; k2 < NK; ++k2) v = fmat(q[k2], s_t1[(k1 * NK + k2) * P1 + b3], v);
+                s_t2[i] = v;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < KR; ++r) {                   // [a1 b1][a2 b2 b3] += sum_k1 Q1[a1 b1][k1] T2[k1][..]
+                const int i = t + r * NT;
+                if (i < NI) {
+                    const int ab1 = i / (P2 * P1), rest = i % (P2 * P1);
+                    const T* q = s_q[0][f1][ab1];
+                    T v = acc[r];
+#pragma unroll
+                    for (int k1 = 0; k1 < NK; ++k1) v = fmat(q[k1], s_t2[k1 * P2 * P1 + rest], v);
+                    acc[r] = v;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < KR; ++r) {
+        const int i = t + r * NT;
+        if (i < NI) {
+            const int a1 = i / (P1 * P2 * P1), b1 = (i / (P2 * P1)) % P1, a2 = (i / P2) % P1, b2 = (i / P1) % P1, b3 = i % P1;
+            loc[((ce * P1 + a3) * 2 + 1) * NBLK + (a1 * P1 + a2) * NP + (b1 * P1 + b2) * P1 + b3] = acc[r];
+        }
+    }
+}
+
+template <typename T, int P>
+static int launch_tensor_cut_p(const wq_rules* H, const T* Cc, int64_t ldc, T* vk, hipStream_t s) {
+    const DevRules& R = H->R;
+    const int64_t n = R.n_cut_elems;
+    using C = MomCfg<P>;
+    const int64_t nloc = n * C::P1 * 2 * C::P2 * C::NP;
+    T* mom = nullptr;
+    hipError_t err = H->scratch_alloc((void**)&mom, sizeof(T) * (size_t)(6 * n * C::NK3 + nloc), s);
+    if (err != hipSuccess)
+        return wq_set_error(WQ_ENOMEM, "wq_assemble_tensor: scratch allocation failed: %s", hipGetErrorString(err));
+    T* loc = mom + 6 * n * C::NK3;
+    for (int c = 0; c < 6; ++c) launch_moments<T, P>(H, Cc + c * ldc, mom + c * n * C::NK3, 0, n, s);
+    hipLaunchKernelGGL((k_tensor_local<T, P>), dim3((unsigned)(n * C::P1)), dim3(256), 0, s, R, (const T*)mom, n, loc);
+    hipLaunchKernelGGL((k_cut_gather<T, P, 2>), dim3((unsigned)R.n_cut), dim3(RemCfg<P>::NT), 0, s, R, (const T*)loc,
+                       (T*)nullptr, vk, 0, (int)n, (int64_t)0);
+    err = hipFreeAsync(mom, s);
+    if (err != hipSuccess) return wq_set_error(WQ_EHIP, "wq_assemble_tensor: scratch release failed: %s", hipGetErrorString(err));
+    return WQ_OK;
+}
+
+// returns WQ_EUNSUPPORTED when the moment form does not apply (octree depth > 3): the caller
+// then integrates the cut elements row by row
+template <typename T>
+int launch_tensor_cut(const wq_rules* H, const T* Cc, T* vk, hipStream_t s) {
+    const DevRules& R = H->R;
+    if (R.levels > 3 || R.p > 4) return WQ_EUNSUPPORTED;
+    if (R.n_cut_elems == 0 || R.n_cut == 0) return WQ_OK;
+    const int64_t ldc = R.n_kappa;
+    switch (R.p) {
+        case 1: return launch_tensor_cut_p<T, 1>(H, Cc, ldc, vk, s);
+        case 2: return launch_tensor_cut_p<T, 2>(H, Cc, ldc, vk, s);
+        case 3: return launch_tensor_cut_p<T, 3>(H, Cc, ldc, vk, s);
+        default: return launch_tensor_cut_p<T, 4>(H, Cc, ldc, vk, s);
+    }
+}
+
+#ifndef WQ_ONLY_F32
+template int launch_tensor_cut<double>(const wq_rules*, const double*, double*, hipStream_t);
+#endif
+#ifndef WQ_ONLY_F64
+template int launch_tensor_cut<float>(const wq_rules*, const float*, float*, hipStream_t);
+#endif
+
 template <typename T>
 int launch_cut(const wq_rules* H, uint32_t which, uint32_t parts, const T* kappa, T* vm, T* vk, hipStream_t s, void* buf,
                size_t cap) {

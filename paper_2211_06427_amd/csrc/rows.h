@@ -17,6 +17,8 @@ int launch_gauss(const wq_rules* H, uint32_t which, const T* kg, const T* kappa,
 int launch_gauss_coords(const wq_rules* H, double* xyz, hipStream_t s);
 template <typename T>
 int launch_tensor(const wq_rules* H, const T* C, T* vk, hipStream_t s);   // tensor.hip
+template <typename T>
+int launch_tensor_cut(const wq_rules* H, const T* C, T* vk, hipStream_t s);   // cut.hip: cut elements, moment form
 
 // L2 projection (projection.hip)
 int projection_load_vector(const wq_rules* H, const double* f, double* b, hipStream_t s);

@@ -919,6 +919,59 @@ __device__ inline double bernstein(int n, int k, double t) {
     return r;
 }
 
+// Bernstein coefficients cb[a][i] of phi_a (degree p) and db[a][i] of phi_a' (degree p - 1) on
+// element e of direction d.
+__device__ void elem_bernstein(const DevRules& R, int d, int e, double cb[][WQ_PMAX + 1], double db[][WQ_PMAX + 1]) {
+    const int p = R.p;
+    const double h = R.h[d];
+    double kn[2 * WQ_PMAX + 2];
+    for (int j = 0; j < 2 * p + 2; ++j) kn[j] = knot_at(e + j, p, R.nel[d], R.lo[d], h);
+    for (int a = 0; a <= p; ++a)
+        for (int i = 0; i <= p; ++i) {
+            double dv[WQ_PMAX + 1];
+            for (int j = 0; j <= p; ++j) dv[j] = j == a ? 1.0 : 0.0;
+            for (int rr = 1; rr <= p; ++rr) {
+                const double u = rr <= p - i ? kn[p] : kn[p + 1];
+                for (int j = p; j >= rr; --j) {
+                    const double al = (u - kn[j]) / (kn[j + 1 + p - rr] - kn[j]);
+                    dv[j] = (1.0 - al) * dv[j - 1] + al * dv[j];
+                }
+            }
+            cb[a][i] = dv[p];
+        }
+    for (int a = 0; a <= p; ++a)
+        for (int i = 0; i < p; ++i) db[a][i] = p * (cb[a][i + 1] - cb[a][i]) / h;
+}
+
+// Qx[((e * P1 + a) * P1 + b) * (2p+1) + k]: degree-2p Bernstein coefficients of phi_a' phi_b
+// (degree 2p - 1 raised once), the mixed products of the coefficient-tensor stiffness.
+__global__ void k_bern_mixed(DevRules R, int d, double* Qx) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= R.nel[d]) return;
+    const int p = R.p, p1 = p + 1, nk = 2 * p + 1;
+    double cb[WQ_PMAX + 1][WQ_PMAX + 1], db[WQ_PMAX + 1][WQ_PMAX + 1];
+    elem_bernstein(R, d, e, cb, db);
+    const int n = 2 * p - 1;
+    for (int a = 0; a <= p; ++a)
+        for (int b = 0; b <= p; ++b) {
+            double r[2 * WQ_PMAX + 1];
+            for (int k = 0; k <= n; ++k) {
+                double s = 0.0;
+                for (int i = 0; i < p; ++i) {
+                    const int j = k - i;
+                    if (j < 0 || j > p) continue;
+                    s += db[a][i] * cb[b][j] * binom(p - 1, i) * binom(p, j);
+                }
+                r[k] = s / binom(n, k);
+            }
+            double* q = Qx + (((int64_t)e * p1 + a) * p1 + b) * nk;
+            for (int k = 0; k <= n + 1; ++k) {              // degree n -> n + 1
+                const double lo = k > 0 ? r[k - 1] : 0.0, hi = k <= n ? r[k] : 0.0;
+                q[k] = (double)k / (n + 1) * lo + (1.0 - (double)k / (n + 1)) * hi;
+            }
+        }
+}
+
 __global__ void k_bern_products(DevRules R, int d, double* Q) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= R.nel[d]) return;
@@ -1529,6 +1582,16 @@ int build_rules(const wq_mesh* mesh, const wq_levelset* ls, const wq_options* op
                 hipLaunchKernelGGL(k_bern_products, grid_for(R.nel[d], 64), dim3(64), 0, stream, R, d, q);
                 hipLaunchKernelGGL(k_convert<float>, grid_for(n), dim3(256), 0, stream, q, q32, n);
                 R.bern_q64[d] = q; R.bern_q32[d] = q32;
+                R.bern_qx64[d] = nullptr; R.bern_qx32[d] = nullptr;
+                if (tensor) {
+                    const int64_t nx = (int64_t)R.nel[d] * p1 * p1 * nk;
+                    double* qx = B.keep<double>(nx);
+                    float* qx32 = B.keep<float>(nx);
+                    if (!qx || !qx32) return B.fail();
+                    hipLaunchKernelGGL(k_bern_mixed, grid_for(R.nel[d], 64), dim3(64), 0, stream, R, d, qx);
+                    hipLaunchKernelGGL(k_convert<float>, grid_for(nx), dim3(256), 0, stream, qx, qx32, nx);
+                    R.bern_qx64[d] = qx; R.bern_qx32[d] = qx32;
+                }
             }
             const int64_t n = (int64_t)ni * nk * p1;
             double* bi = B.keep<double>(n);

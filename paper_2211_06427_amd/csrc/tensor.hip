@@ -16,12 +16,14 @@
 // row is then stored (interior rows: the clipped window in CSR order; cut rows through their
 // position map; cut rows without a box are zeroed).
 //
-// Element parts of cut rows (element Gauss on the remainder elements, the cut rule on the cut
-// elements; Eq. (1)): k_tensor_elems, one workgroup per cut row, walks the row's elements
-// and, per tensor block of points (an element's Gauss points, an octree leaf, or a fitted
-// element), forms the flux F_e(q) = w_q sum_d C_de(q) d_d B_I(x_q) at every point and
-// contracts it with the trial derivatives direction by direction (3, 2, 1) into the row's
-// window in LDS; the window is added into the values at the end (row-owned, no atomics).
+// Element parts of cut rows (Eq. (1)): k_tensor_elems, one workgroup per cut row, walks the
+// row's element Gauss remainder and, per tensor block of points (an element's Gauss points;
+// for octrees deeper than three levels also every leaf of its cut elements), forms the flux
+// F_e(q) = w_q sum_d C_de(q) d_d B_I(x_q) at every point and contracts it with the trial
+// derivatives direction by direction (3, 2, 1) into the row's window in LDS; the window is
+// added into the values at the end (row-owned, no atomics).  Cut elements otherwise go through
+// the moment form in cut.hip: moments of the six components, local rows once per element, the
+// row gather of the scalar path.
 #include "rows.h"
 
 namespace {
@@ -213,7 +215,7 @@ __device__ inline void elem_basis(const DevRules& R, int d, int e, double x, dou
 
 template <typename T, int P>
 __global__ void __launch_bounds__(256)
-k_tensor_elems(DevRules R, const T* __restrict__ C, int64_t ldc, const double* __restrict__ xyz,
+k_tensor_elems(DevRules R, const T* __restrict__ C, int64_t ldc, const double* __restrict__ xyz, int with_cut,
                T* __restrict__ vk) {
     using Cf = TenCfg<P>;
     constexpr int P1 = Cf::P1, M = Cf::M, M3 = Cf::M3, NN = Cf::NN, NT = Cf::NT;
@@ -233,7 +235,7 @@ k_tensor_elems(DevRules R, const T* __restrict__ C, int64_t ldc, const double* _
     }
     for (int k = t; k < M3; k += NT) s_acc[k] = 0;
     const int nrem = R.rem_ptr[cr + 1] - R.rem_ptr[cr];
-    const int ncut = R.rcut_ptr[cr + 1] - R.rcut_ptr[cr];
+    const int ncut = with_cut ? R.rcut_ptr[cr + 1] - R.rcut_ptr[cr] : 0;
     const int64_t oct0 = R.n_grid + R.n_block;
     const int nkf = 2 * P + 1, nkf3 = nkf * nkf * nkf;
     for (int el = 0; el < nrem + ncut; ++el) {
@@ -337,28 +339,33 @@ k_tensor_elems(DevRules R, const T* __restrict__ C, int64_t ldc, const double* _
 }
 
 template <typename T, int P>
-void launch_tensor_p(const wq_rules* H, const T* C, int64_t ldc, T* vk, hipStream_t s) {
+void launch_tensor_p(const wq_rules* H, const T* C, int64_t ldc, int with_cut, T* vk, hipStream_t s) {
     const DevRules& R = H->R;
     if (H->n_active > 0)
         hipLaunchKernelGGL((k_tensor_rows<T, P>), dim3((unsigned)H->n_active), dim3(256), 0, s, R, C, ldc,
                            (const int32_t*)H->act2cut, vk);
     if (H->n_cut > 0)
         hipLaunchKernelGGL((k_tensor_elems<T, P>), dim3((unsigned)H->n_cut), dim3(256), 0, s, R, C, ldc,
-                           (const double*)H->kappa_xyz, vk);
+                           (const double*)H->kappa_xyz, with_cut, vk);
 }
 
 }  // namespace
 
+// Regular part and remainder row by row; the cut elements in moment form, element by element
+// with the row gather (cut.hip), or row by row in k_tensor_elems when the octree is deeper than
+// the moment form's three levels.
 template <typename T>
 int launch_tensor(const wq_rules* H, const T* C, T* vk, hipStream_t s) {
     const int64_t ldc = H->R.n_kappa;
+    const int with_cut = H->R.levels > 3 ? 1 : 0;
     switch (H->R.p) {
-        case 1: launch_tensor_p<T, 1>(H, C, ldc, vk, s); break;
-        case 2: launch_tensor_p<T, 2>(H, C, ldc, vk, s); break;
-        case 3: launch_tensor_p<T, 3>(H, C, ldc, vk, s); break;
-        case 4: launch_tensor_p<T, 4>(H, C, ldc, vk, s); break;
+        case 1: launch_tensor_p<T, 1>(H, C, ldc, with_cut, vk, s); break;
+        case 2: launch_tensor_p<T, 2>(H, C, ldc, with_cut, vk, s); break;
+        case 3: launch_tensor_p<T, 3>(H, C, ldc, with_cut, vk, s); break;
+        case 4: launch_tensor_p<T, 4>(H, C, ldc, with_cut, vk, s); break;
         default: return WQ_EUNSUPPORTED;
     }
+    if (!with_cut) return launch_tensor_cut<T>(H, C, vk, s);
     return WQ_OK;
 }
 
