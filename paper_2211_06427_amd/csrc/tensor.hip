@@ -16,9 +16,10 @@
 // row is then stored (interior rows: the clipped window in CSR order; cut rows through their
 // position map; cut rows without a box are zeroed).
 //
-// Element parts of cut rows (Eq. (1)): k_tensor_elems, one workgroup per cut row, walks the
-// row's element Gauss remainder and, per tensor block of points (an element's Gauss points;
-// for octrees deeper than three levels also every leaf of its cut elements), forms the flux
+// Element parts of cut rows (Eq. (1)): k_tensor_rem (the element Gauss remainder, several
+// elements in flight) or, for octrees deeper than three levels, k_tensor_elems, one workgroup
+// per cut row, walks the row's remainder and cut elements and, per tensor block of points (an
+// element's Gauss points, every leaf of its cut elements), forms the flux
 // F_e(q) = w_q sum_d C_de(q) d_d B_I(x_q) at every point and contracts it with the trial
 // derivatives direction by direction (3, 2, 1) into the row's window in LDS; the window is
 // added into the values at the end (row-owned, no atomics).  Cut elements otherwise go through
@@ -40,9 +41,6 @@ template <> __device__ inline const float* dwq_tab<float>(const DevRules& R) { r
 template <typename T> __device__ inline const T* dwqx_tab(const DevRules& R);
 template <> __device__ inline const double* dwqx_tab<double>(const DevRules& R) { return R.dwq_Wtx64; }
 template <> __device__ inline const float* dwqx_tab<float>(const DevRules& R) { return R.dwq_Wtx32; }
-template <typename T> __device__ inline const T* octw_tab(const DevRules& R);
-template <> __device__ inline const double* octw_tab<double>(const DevRules& R) { return R.oct_w; }
-template <> __device__ inline const float* octw_tab<float>(const DevRules& R) { return R.oct_w32; }
 
 // family of direction slot x in term (u, v): 0 = (0, 0), 1 = (1, 1), 2 = (1, 0), 3 = (0, 1)
 __device__ inline int tfam(int x, int u, int v) { return x == u ? (x == v ? 1 : 2) : (x == v ? 3 : 0); }
@@ -220,11 +218,14 @@ k_tensor_elems(DevRules R, const T* __restrict__ C, int64_t ldc, const double* _
     using Cf = TenCfg<P>;
     constexpr int P1 = Cf::P1, M = Cf::M, M3 = Cf::M3, NN = Cf::NN, NT = Cf::NT;
     constexpr int NN3 = NN * NN * NN;
-    __shared__ T s_acc[M3];
-    __shared__ T s_f[3][NN3];                         // flux components at the block's points
-    __shared__ T s_t1[3][NN * NN * P1];               // [e][g1 g2][k3]
-    __shared__ T s_t2[3][NN * P1 * P1];               // [e][g1][k2 k3]
-    __shared__ T s_b[3][2][P1][NN];                   // [d][value / derivative][k][g]
+    // FP64 throughout for both dtypes (this path sums over thousands of leaves per element;
+    // the inputs are read in T and the row is rounded to T once)
+    using A = double;
+    __shared__ A s_acc[M3];
+    __shared__ A s_f[3][NN3];                         // flux components at the block's points
+    __shared__ A s_t1[3][NN * NN * P1];               // [e][g1 g2][k3]
+    __shared__ A s_t2[3][NN * P1 * P1];               // [e][g1][k2 k3]
+    __shared__ A s_b[3][2][P1][NN];                   // [d][value / derivative][k][g]
     const int64_t cr = blockIdx.x;
     const int t = threadIdx.x;
     const int ra = R.cut_rows[cr];
@@ -273,24 +274,24 @@ k_tensor_elems(DevRules R, const T* __restrict__ C, int64_t ldc, const double* _
                 const int64_t s = slot_at(d == 0 ? g : 0, d == 1 ? g : 0, d == 2 ? g : 0);
                 double N[WQ_PMAX + 1], dN[WQ_PMAX + 1];
                 elem_basis(R, d, e[d], xyz[s * 3 + d], N, dN);
-                for (int kk = 0; kk < P1; ++kk) { s_b[d][0][kk][g] = (T)N[kk]; s_b[d][1][kk][g] = (T)dN[kk]; }
+                for (int kk = 0; kk < P1; ++kk) { s_b[d][0][kk][g] = N[kk]; s_b[d][1][kk][g] = dN[kk]; }
             }
             __syncthreads();
             // flux F_e = w sum_d C_de d_d B_I at every point
             for (int q = t; q < n3; q += NT) {
                 const int g1 = q / (n * n), g2 = (q / n) % n, g3 = q % n;
                 const int64_t s = slot_at(g1, g2, g3);
-                T w;
-                if (rem) w = (T)(R.gw[g1] * R.gw[g2] * R.gw[g3] * (R.h[0] * R.h[1] * R.h[2] / 8.0));
-                else w = octw_tab<T>(R)[s - oct0];
-                const T v0 = s_b[0][0][kI[0]][g1], v1 = s_b[1][0][kI[1]][g2], v2 = s_b[2][0][kI[2]][g3];
-                const T gt[3] = {s_b[0][1][kI[0]][g1] * v1 * v2, v0 * s_b[1][1][kI[1]][g2] * v2, v0 * v1 * s_b[2][1][kI[2]][g3]};
-                T c[6];
+                A w;
+                if (rem) w = R.gw[g1] * R.gw[g2] * R.gw[g3] * (R.h[0] * R.h[1] * R.h[2] / 8.0);
+                else w = R.oct_w[s - oct0];
+                const A v0 = s_b[0][0][kI[0]][g1], v1 = s_b[1][0][kI[1]][g2], v2 = s_b[2][0][kI[2]][g3];
+                const A gt[3] = {s_b[0][1][kI[0]][g1] * v1 * v2, v0 * s_b[1][1][kI[1]][g2] * v2, v0 * v1 * s_b[2][1][kI[2]][g3]};
+                A c[6];
 #pragma unroll
-                for (int k = 0; k < 6; ++k) c[k] = C[k * ldc + s];
+                for (int k = 0; k < 6; ++k) c[k] = (A)C[k * ldc + s];
 #pragma unroll
                 for (int ee = 0; ee < 3; ++ee) {
-                    T f = c[tcomp(0, ee)] * gt[0];
+                    A f = c[tcomp(0, ee)] * gt[0];
                     f = fmat(c[tcomp(1, ee)], gt[1], f);
                     f = fmat(c[tcomp(2, ee)], gt[2], f);
                     s_f[ee][q] = w * f;
@@ -300,8 +301,8 @@ k_tensor_elems(DevRules R, const T* __restrict__ C, int64_t ldc, const double* _
             // stage 1: T1[e][g1 g2][k3] = sum_g3 D3^e[k3][g3] F_e
             for (int it = t; it < 3 * n * n * P1; it += NT) {
                 const int ee = it / (n * n * P1), g12 = (it / P1) % (n * n), k3 = it % P1;
-                const T* bz = s_b[2][ee == 2][k3];
-                T a = 0;
+                const A* bz = s_b[2][ee == 2][k3];
+                A a = 0;
                 for (int g3 = 0; g3 < n; ++g3) a = fmat(bz[g3], s_f[ee][g12 * n + g3], a);
                 s_t1[ee][g12 * P1 + k3] = a;
             }
@@ -309,8 +310,8 @@ k_tensor_elems(DevRules R, const T* __restrict__ C, int64_t ldc, const double* _
             // stage 2: T2[e][g1][k2 k3] = sum_g2 D2^e[k2][g2] T1[e][g1 g2][k3]
             for (int it = t; it < 3 * n * P1 * P1; it += NT) {
                 const int ee = it / (n * P1 * P1), g1 = (it / (P1 * P1)) % n, k2 = (it / P1) % P1, k3 = it % P1;
-                const T* by = s_b[1][ee == 1][k2];
-                T a = 0;
+                const A* by = s_b[1][ee == 1][k2];
+                A a = 0;
                 for (int g2 = 0; g2 < n; ++g2) a = fmat(by[g2], s_t1[ee][(g1 * n + g2) * P1 + k3], a);
                 s_t2[ee][(g1 * P1 + k2) * P1 + k3] = a;
             }
@@ -318,10 +319,10 @@ k_tensor_elems(DevRules R, const T* __restrict__ C, int64_t ldc, const double* _
             // stage 3: window[k] += sum_e sum_g1 D1^e[k1][g1] T2[e][g1][k2 k3]
             for (int it = t; it < P1 * P1 * P1; it += NT) {
                 const int k1 = it / (P1 * P1), k2 = (it / P1) % P1, k3 = it % P1;
-                T a = 0;
+                A a = 0;
 #pragma unroll
                 for (int ee = 0; ee < 3; ++ee) {
-                    const T* bx = s_b[0][ee == 0][k1];
+                    const A* bx = s_b[0][ee == 0][k1];
                     for (int g1 = 0; g1 < n; ++g1) a = fmat(bx[g1], s_t2[ee][(g1 * P1 + k2) * P1 + k3], a);
                 }
                 const int j0 = e[0] + k1 - (I[0] - P), j1 = e[1] + k2 - (I[1] - P), j2 = e[2] + k3 - (I[2] - P);
@@ -334,7 +335,118 @@ k_tensor_elems(DevRules R, const T* __restrict__ C, int64_t ldc, const double* _
     const int32_t* pos = R.pos_map + cr * M3;
     for (int k = t; k < M3; k += NT) {
         const int o = pos[k];
-        if (o >= 0) vk[rb + o] += s_acc[k];
+        if (o >= 0) vk[rb + o] += (T)s_acc[k];
+    }
+}
+
+// Element Gauss remainder of the cut rows (the path when the cut elements go through the
+// moment form): one workgroup per cut row, NS remainder elements in flight (one thread slot
+// each, private LDS buffers and window accumulators summed in slot order at the end), the
+// basis values at the element's Gauss points read from the direction tables.
+template <typename T, int P, int NS>
+__global__ void __launch_bounds__(256)
+k_tensor_rem(DevRules R, const T* __restrict__ C, int64_t ldc, T* __restrict__ vk) {
+    using Cf = TenCfg<P>;
+    constexpr int P1 = Cf::P1, M = Cf::M, M3 = Cf::M3, NP = P1 * P1 * P1, NT = 256, NTS = NT / NS;
+    __shared__ T s_acc[NS][M3];
+    __shared__ T s_f[NS][3][NP];
+    __shared__ T s_t1[NS][3][NP];                     // [e][g1 g2][k3]
+    __shared__ T s_t2[NS][3][NP];                     // [e][g1][k2 k3]
+    __shared__ T s_b[NS][3][2][P1][P1];               // [d][value / derivative][k][g]
+    const int64_t cr = blockIdx.x;
+    const int t = threadIdx.x, sl = t / NTS, u = t % NTS;
+    const int ra = R.cut_rows[cr];
+    int I[3];
+    {
+        const int lex = R.act2lex[ra];
+        I[2] = lex % R.nfun[2]; I[1] = (lex / R.nfun[2]) % R.nfun[1]; I[0] = lex / (R.nfun[1] * R.nfun[2]);
+    }
+    const int l0 = R.rem_ptr[cr], nrem = R.rem_ptr[cr + 1] - l0;
+    if (nrem == 0) return;
+    for (int k = t; k < NS * M3; k += NT) s_acc[k / M3][k % M3] = 0;
+    const T wscale = (T)(R.h[0] * R.h[1] * R.h[2] / 8.0);
+    for (int r0 = 0; r0 < nrem; r0 += NS) {
+        const int r = r0 + sl;
+        const bool active = r < nrem;
+        int e[3] = {0, 0, 0}, kI[3] = {0, 0, 0};
+        if (active) {
+            const int pk = R.rem_list[l0 + r].x;
+            kI[0] = pk & 15; kI[1] = (pk >> 4) & 15; kI[2] = (pk >> 8) & 15;
+            for (int d = 0; d < 3; ++d) e[d] = I[d] - kI[d];
+        }
+        __syncthreads();                              // the previous round's buffers are no longer read
+        if (active)
+            for (int k = u; k < 3 * P1 * P1; k += NTS) {
+                const int d = k / (P1 * P1), g = (k / P1) % P1, kk = k % P1;
+                const int64_t y = (int64_t)e[d] * P1 + g;
+                s_b[sl][d][0][kk][g] = (T)R.Bval[d][y * P1 + kk];
+                s_b[sl][d][1][kk][g] = (T)R.dBval[d][y * P1 + kk];
+            }
+        __syncthreads();
+        if (active)
+            for (int q = u; q < NP; q += NTS) {      // flux F_e = w sum_d C_de d_d B_I
+                const int g1 = q / (P1 * P1), g2 = (q / P1) % P1, g3 = q % P1;
+                const int64_t s = slot_of(R, e[0] * P1 + g1, e[1] * P1 + g2, e[2] * P1 + g3);
+                const T w = (T)(R.gw[g1] * R.gw[g2] * R.gw[g3]) * wscale;
+                const T v0 = s_b[sl][0][0][kI[0]][g1], v1 = s_b[sl][1][0][kI[1]][g2], v2 = s_b[sl][2][0][kI[2]][g3];
+                const T gt[3] = {s_b[sl][0][1][kI[0]][g1] * v1 * v2, v0 * s_b[sl][1][1][kI[1]][g2] * v2,
+                                 v0 * v1 * s_b[sl][2][1][kI[2]][g3]};
+                T c[6];
+#pragma unroll
+                for (int k = 0; k < 6; ++k) c[k] = C[k * ldc + s];
+#pragma unroll
+                for (int ee = 0; ee < 3; ++ee) {
+                    T f = c[tcomp(0, ee)] * gt[0];
+                    f = fmat(c[tcomp(1, ee)], gt[1], f);
+                    f = fmat(c[tcomp(2, ee)], gt[2], f);
+                    s_f[sl][ee][q] = w * f;
+                }
+            }
+        __syncthreads();
+        if (active)
+            for (int it = u; it < 3 * NP; it += NTS) {   // T1[e][g1 g2][k3] = sum_g3 D3^e[k3][g3] F_e
+                const int ee = it / NP, g12 = (it / P1) % (P1 * P1), k3 = it % P1;
+                const T* bz = s_b[sl][2][ee == 2][k3];
+                T a = 0;
+#pragma unroll
+                for (int g3 = 0; g3 < P1; ++g3) a = fmat(bz[g3], s_f[sl][ee][g12 * P1 + g3], a);
+                s_t1[sl][ee][g12 * P1 + k3] = a;
+            }
+        __syncthreads();
+        if (active)
+            for (int it = u; it < 3 * NP; it += NTS) {   // T2[e][g1][k2 k3] = sum_g2 D2^e[k2][g2] T1[e][g1 g2][k3]
+                const int ee = it / NP, g1 = (it / (P1 * P1)) % P1, k2 = (it / P1) % P1, k3 = it % P1;
+                const T* by = s_b[sl][1][ee == 1][k2];
+                T a = 0;
+#pragma unroll
+                for (int g2 = 0; g2 < P1; ++g2) a = fmat(by[g2], s_t1[sl][ee][(g1 * P1 + g2) * P1 + k3], a);
+                s_t2[sl][ee][(g1 * P1 + k2) * P1 + k3] = a;
+            }
+        __syncthreads();
+        if (active)
+            for (int it = u; it < NP; it += NTS) {       // window += sum_e sum_g1 D1^e[k1][g1] T2[e][g1][k2 k3]
+                const int k1 = it / (P1 * P1), k2 = (it / P1) % P1, k3 = it % P1;
+                T a = 0;
+#pragma unroll
+                for (int ee = 0; ee < 3; ++ee) {
+                    const T* bx = s_b[sl][0][ee == 0][k1];
+#pragma unroll
+                    for (int g1 = 0; g1 < P1; ++g1) a = fmat(bx[g1], s_t2[sl][ee][(g1 * P1 + k2) * P1 + k3], a);
+                }
+                const int j0 = e[0] + k1 - (I[0] - P), j1 = e[1] + k2 - (I[1] - P), j2 = e[2] + k3 - (I[2] - P);
+                s_acc[sl][(j0 * M + j1) * M + j2] += a;
+            }
+    }
+    __syncthreads();
+    const int64_t rb = R.row_ptr[ra];
+    const int32_t* pos = R.pos_map + cr * M3;
+    for (int k = t; k < M3; k += NT) {
+        const int o = pos[k];
+        if (o < 0) continue;
+        T a = 0;
+#pragma unroll
+        for (int i = 0; i < NS; ++i) a += s_acc[i][k];
+        vk[rb + o] += a;
     }
 }
 
@@ -344,9 +456,14 @@ void launch_tensor_p(const wq_rules* H, const T* C, int64_t ldc, int with_cut, T
     if (H->n_active > 0)
         hipLaunchKernelGGL((k_tensor_rows<T, P>), dim3((unsigned)H->n_active), dim3(256), 0, s, R, C, ldc,
                            (const int32_t*)H->act2cut, vk);
-    if (H->n_cut > 0)
-        hipLaunchKernelGGL((k_tensor_elems<T, P>), dim3((unsigned)H->n_cut), dim3(256), 0, s, R, C, ldc,
-                           (const double*)H->kappa_xyz, with_cut, vk);
+    if (H->n_cut > 0) {
+        if (with_cut)
+            hipLaunchKernelGGL((k_tensor_elems<T, P>), dim3((unsigned)H->n_cut), dim3(256), 0, s, R, C, ldc,
+                               (const double*)H->kappa_xyz, with_cut, vk);
+        else
+            hipLaunchKernelGGL((k_tensor_rem<T, P, sizeof(T) == 8 ? 2 : 4>), dim3((unsigned)H->n_cut), dim3(256), 0, s, R,
+                               C, ldc, vk);
+    }
 }
 
 }  // namespace

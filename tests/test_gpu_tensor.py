@@ -28,6 +28,7 @@ CASES = {
     "ball6_p2": W.custom(6, 2, BALL, octree_levels=2),
     "plane6_p3": W.custom(6, 3, PLANE, octree_levels=1),
     "plane6_p4": W.custom(6, 4, PLANE, octree_levels=1),
+    "plane5_p2_o4": W.custom(5, 2, PLANE, octree_levels=4),   # cut elements row by row (depth > 3)
     "plane6_p3_fit": W.custom(6, 3, PLANE, cut_rule="fit"),
     "ball5_p4_fit": W.custom(5, 4, BALL, cut_rule="fit"),
 }
