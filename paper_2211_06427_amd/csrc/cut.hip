@@ -14,6 +14,10 @@
 //     row's local rows in a fixed order (one workgroup per row, no atomics).  Deeper
 //     octrees take k_cut_octree: one workgroup per (cut element, a3, group of a1), the
 //     local matrix contracted leaf by leaf and added into the CSR values with atomics.
+//     Under the fitted cut rule (WQ_OPT_MOMENT_FIT) the moments come from the element's
+//     (2p+1)^3 fitted points instead (k_cut_moments_fit); the rest is unchanged.
+// (iii) The coefficient-tensor stiffness reuses (ii): moments of each of the six tensor
+//     components, local stiffness rows per element (k_tensor_local), the same gather.
 #include <algorithm>
 #include <mutex>
 
