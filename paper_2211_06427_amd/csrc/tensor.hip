@@ -66,7 +66,7 @@ struct TenCfg {
 template <typename T, int P>
 __global__ void __launch_bounds__(256)
 k_tensor_rows(DevRules R, const T* __restrict__ C, int64_t ldc, const int32_t* __restrict__ act2cut,
-              T* __restrict__ vk) {
+              const int32_t* __restrict__ rows, T* __restrict__ vk) {
     using Cf = TenCfg<P>;
     constexpr int M = Cf::M, MM = Cf::MM, M3 = Cf::M3, NW = Cf::NW, NDQ = Cf::NDQ, NA = Cf::NA, NT = Cf::NT;
     __shared__ T s_w[3][4 * M * NA];                  // [slot][family][jj][q]
@@ -75,7 +75,7 @@ k_tensor_rows(DevRules R, const T* __restrict__ C, int64_t ldc, const int32_t* _
     __shared__ T s_c[6][NW * NA];                     // tensor components at one C point, [qB][qA]
     __shared__ T s_t1[9][NW * M];                     // [term][qB][jA]
     __shared__ T s_t2[9][MM];                         // [term][jB jA]
-    const int ra = blockIdx.x;
+    const int ra = rows ? rows[blockIdx.x] : (int)blockIdx.x;   // rows: the cut rows only
     const int t = threadIdx.x;
     const int cr = act2cut[ra];
     const int4 sp = cr >= 0 ? R.split[cr] : make_int4(-1, 0, 0, -1);
@@ -193,6 +193,164 @@ k_tensor_rows(DevRules R, const T* __restrict__ C, int64_t ldc, const int32_t* _
             if (a0 >= 0 && a0 < n[0] && a1 >= 0 && a1 < n[1] && a2 >= 0 && a2 < n[2])
                 vk[rb + ((int64_t)a0 * n[1] + a1) * n[2] + a2] = acc[i];
         }
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// interior rows in line blocks: one workgroup per block of up to RB consecutive interior rows
+// along direction 1 (fixed i2, i3; SPLIT workgroups share a block of up to 8 rows)
+// ---------------------------------------------------------------------------------------
+// Directions 3 and 2 have the same rules for all rows of the block, so per term (d, e) the
+// slab S[q1][j2 j3] = sum_q2 W2^f[j2][q2] sum_q3 W3^f[j3][q3] C_de(q1, q2, q3) is formed once
+// over the union of the rows' direction-1 windows (stage 1: one thread per (q1, q2) with its
+// C line in registers; stage 2: one thread per (q1, j2, j3)), and each row contracts it with
+// its own direction-1 rule of the term's family into per-thread accumulators (stage 3).  The
+// terms run one after another, so LDS holds one term's slab.
+// the nine terms of a line block; QB bounds the points per direction of every window (2p+2
+// for blocks of regular windows, 4p otherwise)
+template <typename T, int P, int RB, int QB>
+__device__ __forceinline__ void tensor_block_terms(const DevRules& R, const T* __restrict__ C, int64_t ldc, int i1s,
+                                                   int nr, int xs1, int nu, int xs2, int n2, int xs3, int n3,
+                                                   T* s_t1, T* s_s, T (*s_wa)[TenCfg<P>::M * TenCfg<P>::NW],
+                                                   T (*s_wb)[TenCfg<P>::M * TenCfg<P>::NW],
+                                                   T (*s_wc)[TenCfg<P>::M * TenCfg<P>::NW], const int* s_off,
+                                                   const int* s_nw, bool own, int pr, int pj1, int lane, T* acc) {
+    using Cf = TenCfg<P>;
+    constexpr int M = Cf::M, MM = Cf::MM, NW = Cf::NW, NT = Cf::NT;
+    constexpr int NPAIR = RB * M, L = NT / NPAIR, NJ = (MM + L - 1) / L;
+    (void)NPAIR;
+    const int t = threadIdx.x;
+    for (int term = 0; term < 9; ++term) {
+        const int d = term / 3, e = term % 3;
+        const int comp = tcomp(d, e), fA = tfam(0, d, e), fB = tfam(1, d, e), fC = tfam(2, d, e);
+        __syncthreads();                              // the previous term's slab and rules are no longer read
+        for (int k = t; k < nr * M * NW; k += NT) {
+            const int r = k / (M * NW), rr = k % (M * NW);
+            const int i1 = i1s + r;
+            s_wa[r][rr] = fA < 2 ? wt_tab<T>(R, 0)[((int64_t)i1 * 2 + fA) * M * NW + rr]
+                                 : wtx_tab<T>(R, 0)[((int64_t)i1 * 2 + fA - 2) * M * NW + rr];
+        }
+        // stage 1: T1[q1][q2][j3] = sum_q3 W3^fC[j3][q3] C_comp(q1, q2, q3), the C line in registers
+        const T* Ck = C + comp * ldc;
+        for (int it = t; it < nu * n2; it += NT) {
+            const int q1 = it / n2, q2 = it % n2;
+            const int64_t base = ((int64_t)(xs1 + q1) * R.nx[1] + (xs2 + q2)) * R.nx[2] + xs3;
+            T cl[QB];
+#pragma unroll
+            for (int q3 = 0; q3 < QB; ++q3) cl[q3] = q3 < n3 ? Ck[base + q3] : (T)0;
+#pragma unroll
+            for (int j3 = 0; j3 < M; ++j3) {
+                const T* w = s_wc[fC] + j3 * NW;
+                T a = 0;
+#pragma unroll
+                for (int q3 = 0; q3 < QB; ++q3) a = fmat(w[q3], cl[q3], a);
+                s_t1[(q1 * NW + q2) * M + j3] = a;
+            }
+        }
+        __syncthreads();
+        // stage 2: S[q1][j2 j3] = sum_q2 W2^fB[j2][q2] T1[q1][q2][j3], one thread per (q1, j3) with
+        // the T1 column in registers
+        for (int it = t; it < nu * M; it += NT) {
+            const int q1 = it / M, j3 = it % M;
+            T col[QB];
+#pragma unroll
+            for (int q2 = 0; q2 < QB; ++q2) col[q2] = q2 < n2 ? s_t1[(q1 * NW + q2) * M + j3] : (T)0;
+#pragma unroll
+            for (int j2 = 0; j2 < M; ++j2) {
+                const T* w = s_wb[fB] + j2 * NW;
+                T a = 0;
+#pragma unroll
+                for (int q2 = 0; q2 < QB; ++q2) a = fmat(w[q2], col[q2], a);
+                s_s[q1 * MM + j2 * M + j3] = a;
+            }
+        }
+        __syncthreads();
+        // stage 3: row r, acc[j1][j2 j3] += sum_q W1^fA[r][j1][q] S[off_r + q][j2 j3]
+        if (own) {
+            T w[QB];
+            const int nw = s_nw[pr];
+#pragma unroll
+            for (int q = 0; q < QB; ++q) w[q] = q < nw ? s_wa[pr][pj1 * NW + q] : (T)0;
+            const T* sl = s_s + s_off[pr] * MM;
+#pragma unroll
+            for (int i = 0; i < NJ; ++i) {
+                const int j23 = lane + i * L;
+                if (j23 < MM) {
+                    T a = acc[i];
+#pragma unroll
+                    for (int q = 0; q < QB; ++q)
+                        if (q < nw) a = fmat(w[q], sl[q * MM + j23], a);
+                    acc[i] = a;
+                }
+            }
+        }
+    }
+}
+
+template <typename T, int P, int RB, int SPLIT>
+__global__ void __launch_bounds__(256)
+k_tensor_block(DevRules R, const T* __restrict__ C, int64_t ldc, T* __restrict__ vk) {
+    using Cf = TenCfg<P>;
+    constexpr int M = Cf::M, MM = Cf::MM, M3 = Cf::M3, NW = Cf::NW, NT = Cf::NT;
+    constexpr int NU = NW + 2 * (RB - 1) + P + 1;     // bound of the union of the rows' direction-1 windows
+    // stage 3: thread -> (row, j1) pair and a lane among L that share it; the lane takes the
+    // columns j23 = lane, lane + L, ... with the pair's weights in registers
+    constexpr int NPAIR = RB * M, L = NT / NPAIR, NJ = (MM + L - 1) / L;
+    __shared__ T s_t1[NU * NW * M];                   // [q1][q2][j3]
+    __shared__ T s_s[NU * MM];                        // [q1][j2 j3]
+    __shared__ T s_wa[RB][M * NW];                    // the rows' direction-1 rules of the term's family
+    __shared__ T s_wb[4][M * NW], s_wc[4][M * NW];    // directions 2 and 3, all four families
+    __shared__ int s_off[RB], s_nw[RB];
+    const int4 blk = R.fblocks[blockIdx.x / SPLIT];
+    const int r0 = (blockIdx.x % SPLIT) * RB;
+    const int nr = blk.w - r0 < RB ? blk.w - r0 : RB;
+    if (nr <= 0) return;
+    const int t = threadIdx.x;
+    const int i1s = blk.x + r0, i2 = blk.y, i3 = blk.z;
+    const int xs1 = R.xs[0][i1s];
+    const int nu = R.xs[0][i1s + nr - 1] + R.nwin[0][i1s + nr - 1] - xs1;
+    const int xs2 = R.xs[1][i2], n2 = R.nwin[1][i2], xs3 = R.xs[2][i3], n3 = R.nwin[2][i3];
+    if (nu > NU) return;                              // cannot happen for a direction with >= p + 2 elements
+    if (t < nr) { s_off[t] = R.xs[0][i1s + t] - xs1; s_nw[t] = R.nwin[0][i1s + t]; }
+    for (int k = t; k < 4 * M * NW; k += NT) {
+        const int f = k / (M * NW), r = k % (M * NW);
+        s_wb[f][r] = f < 2 ? wt_tab<T>(R, 1)[((int64_t)i2 * 2 + f) * M * NW + r] : wtx_tab<T>(R, 1)[((int64_t)i2 * 2 + f - 2) * M * NW + r];
+        s_wc[f][r] = f < 2 ? wt_tab<T>(R, 2)[((int64_t)i3 * 2 + f) * M * NW + r] : wtx_tab<T>(R, 2)[((int64_t)i3 * 2 + f - 2) * M * NW + r];
+    }
+    const int pair = t / L, lane = t % L;
+    const int pr = pair / M, pj1 = pair % M;           // row and j1 of this thread's stage-3 items
+    const bool own = pair < NPAIR && pr < nr;
+    T acc[NJ];
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) acc[i] = 0;
+    __syncthreads();                                  // s_off / s_nw
+    bool regular = n2 == 2 * P + 2 && n3 == 2 * P + 2;
+    for (int r = 0; r < nr; ++r) regular = regular && s_nw[r] == 2 * P + 2;
+    if (regular)
+        tensor_block_terms<T, P, RB, 2 * P + 2>(R, C, ldc, i1s, nr, xs1, nu, xs2, n2, xs3, n3, s_t1, s_s, s_wa, s_wb, s_wc,
+                                                s_off, s_nw, own, pr, pj1, lane, acc);
+    else
+        tensor_block_terms<T, P, RB, NW>(R, C, ldc, i1s, nr, xs1, nu, xs2, n2, xs3, n3, s_t1, s_s, s_wa, s_wb, s_wc, s_off,
+                                         s_nw, own, pr, pj1, lane, acc);
+    // store the clipped windows in CSR order
+    if (!own) return;
+    const int I[3] = {i1s + pr, i2, i3};
+    int lo[3], n[3];
+    for (int dd = 0; dd < 3; ++dd) {
+        const int a = I[dd] - P < 0 ? 0 : I[dd] - P, b = I[dd] + P > R.nfun[dd] - 1 ? R.nfun[dd] - 1 : I[dd] + P;
+        lo[dd] = a - (I[dd] - P);
+        n[dd] = b - a + 1;
+    }
+    const int a0 = pj1 - lo[0];
+    if (a0 < 0 || a0 >= n[0]) return;
+    const int64_t rb = R.row_ptr[R.lex2act[((int64_t)I[0] * R.nfun[1] + I[1]) * R.nfun[2] + I[2]]];
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) {
+        const int j23 = lane + i * L;
+        if (j23 >= MM) continue;
+        const int a1 = j23 / M - lo[1], a2 = j23 % M - lo[2];
+        if (a1 < 0 || a1 >= n[1] || a2 < 0 || a2 >= n[2]) continue;
+        vk[rb + ((int64_t)a0 * n[1] + a1) * n[2] + a2] = acc[i];
     }
 }
 
@@ -453,9 +611,21 @@ k_tensor_rem(DevRules R, const T* __restrict__ C, int64_t ldc, T* __restrict__ v
 template <typename T, int P>
 void launch_tensor_p(const wq_rules* H, const T* C, int64_t ldc, int with_cut, T* vk, hipStream_t s) {
     const DevRules& R = H->R;
-    if (H->n_active > 0)
+    // interior rows by line blocks when every direction has p + 2 elements (the blocks' window
+    // bound), the cut rows (and otherwise every row) one per workgroup
+    const bool blocks = R.n_fblocks > 0 && R.nel[0] >= P + 2 && R.nel[1] >= P + 2 && R.nel[2] >= P + 2;
+    if (blocks) {
+        if constexpr (sizeof(T) == 4)
+            hipLaunchKernelGGL((k_tensor_block<T, P, 8, 1>), dim3((unsigned)R.n_fblocks), dim3(256), 0, s, R, C, ldc, vk);
+        else
+            hipLaunchKernelGGL((k_tensor_block<T, P, 4, 2>), dim3((unsigned)(2 * R.n_fblocks)), dim3(256), 0, s, R, C, ldc, vk);
+        if (H->n_cut > 0)
+            hipLaunchKernelGGL((k_tensor_rows<T, P>), dim3((unsigned)H->n_cut), dim3(256), 0, s, R, C, ldc,
+                               (const int32_t*)H->act2cut, (const int32_t*)R.cut_rows, vk);
+    } else if (H->n_active > 0) {
         hipLaunchKernelGGL((k_tensor_rows<T, P>), dim3((unsigned)H->n_active), dim3(256), 0, s, R, C, ldc,
-                           (const int32_t*)H->act2cut, vk);
+                           (const int32_t*)H->act2cut, (const int32_t*)nullptr, vk);
+    }
     if (H->n_cut > 0) {
         if (with_cut)
             hipLaunchKernelGGL((k_tensor_elems<T, P>), dim3((unsigned)H->n_cut), dim3(256), 0, s, R, C, ldc,

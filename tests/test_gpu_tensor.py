@@ -23,6 +23,7 @@ PLANE = W.LevelSet(W.LS_PLANE, n=(1.0, 1.0, 1.0), r0=1.6)
 CASES = {
     "uncut4_p1": W.custom(4, 1),
     "uncut5_p3": W.custom((5, 4, 6), 3),
+    "uncut20x6x6_p2": W.custom((20, 6, 6), 2),   # line blocks of regular windows (rows 8..15 along x)
     "plane6_p1": W.custom(6, 1, PLANE, octree_levels=2),
     "plane6_p2": W.custom(6, 2, PLANE, octree_levels=2),
     "ball6_p2": W.custom(6, 2, BALL, octree_levels=2),
@@ -102,3 +103,25 @@ def test_tensor_errors():
     with pytest.raises(L.WqError) as ex:
         Rules.from_workload(W.custom(7, 5), tensor=True)
     assert ex.value.code == -5
+
+
+def test_tensor_plane48_sampled_interior_rows():
+    """48^3 p = 4 (the benchmark's workload): 40 seeded interior rows, most of them in line
+    blocks of regular windows, against the oracle's rows (FP64 1e-12, FP32 2e-6 row-scaled)."""
+    from oracle import tensor as OT
+    wl = W.workload("plane48_p4")
+    print("case tensor plane48 sampled", flush=True)
+    R = _rules(wl)
+    P = Problem(wl)
+    dom = P.dom
+    interior = np.nonzero(dom.fcls.reshape(-1)[dom.active_lex] == 1)[0]
+    rng = np.random.default_rng(48)
+    pick = np.sort(rng.choice(interior, 40, replace=False))
+    ref = OT.assemble(P, W.map_tensor, rows=pick)
+    rp = R.row_ptr().cpu().numpy()
+    for dtype in (torch.float64, torch.float32):
+        vk = R.assemble_tensor(_field(R, "map", dtype)).cpu().numpy()
+        for r in pick:
+            a, b = rp[r], rp[r + 1]
+            e = np.abs(vk[a:b] - ref[a:b]).max() / np.abs(ref[a:b]).max()
+            assert e <= TOL[dtype], (dtype, int(r), e)
