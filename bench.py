@@ -501,10 +501,12 @@ def main():
             Rt = Rules.from_workload(W.with_cut_rule(wl, rule), tensor=True)
             Cm = W.tensor_components(W.map_tensor(Rt.kappa_xyz()))
             ks = W.kappa_at(wl, Rt.kappa_xyz())
+            vt = {}
             for k in ("f64", "f32"):
                 Ck = Cm.to(dt[k]).contiguous()
                 vk_t = torch.empty(Rt.nnz, dtype=dt[k], device=dev)
                 Rt.assemble_tensor(Ck, vk_t)
+                vt[k] = vk_t.clone()
                 kk = ks.to(dt[k])
 
                 def step_s():
@@ -514,7 +516,8 @@ def main():
                 tens.setdefault(rule, {})[k + "_ms"] = timed(lambda: Rt.assemble_tensor(Ck, vk_t), 3, torch)
                 tens[rule][k + "_scalar_stiff_ms"] = timed(step_s, 3, torch)
                 del vk_t, Ck, kk
-            del Rt, Cm, ks
+            tens[rule]["fp32_rel_err_vs_fp64"] = row_scaled_err(vt["f32"], vt["f64"], Rt.row_ptr(), torch)
+            del Rt, Cm, ks, vt
         schemes["tensor_stiffness"] = tens
 
     # --- rooflines (durations from the timed region) -----------------------------------

@@ -694,29 +694,28 @@ k_cut_moments(DevRules R, const T* __restrict__ kappa, T* __restrict__ mom, int 
     }
 }
 
-template <typename T> __device__ inline const T* fit_v(const DevRules& R);
-template <> __device__ inline const double* fit_v<double>(const DevRules& R) { return R.fit_V64; }
-template <> __device__ inline const float* fit_v<float>(const DevRules& R) { return R.fit_V32; }
 
 // Moments of one cut element on its fitted rule: Mom[k1 k2 k3] = sum_g w_g kappa_g
 // B_k1(tau_g1) B_k2(tau_g2) B_k3(tau_g3) over the NK^3 tensor points, contracted direction by
-// direction (3, then 2, then 1).  One workgroup per cut element from ce0 on.
+// direction (3, then 2, then 1).  One workgroup per cut element from ce0 on.  The fitted
+// weights have both signs, so these sums cancel; they run in FP64 for both dtypes (FP64
+// weights and Bernstein values, kappa read in T) and the moments are rounded to T once.
 template <typename T, int P>
 __global__ void __launch_bounds__(256)
 k_cut_moments_fit(DevRules R, const T* __restrict__ kappa, T* __restrict__ mom, int ce0) {
     using C = MomCfg<P>;
     constexpr int NK = C::NK, NK2 = C::NK2, NK3 = C::NK3, NT = C::NT;
-    __shared__ T s_a[NK3], s_b[NK3];
-    __shared__ T s_v[NK * NK];
+    __shared__ double s_a[NK3], s_b[NK3];
+    __shared__ double s_v[NK * NK];
     const int64_t ce = (int64_t)ce0 + blockIdx.x;
     const int t = threadIdx.x;
     const int64_t s0 = R.n_grid + R.n_block + ce * NK3;
-    for (int i = t; i < NK * NK; i += NT) s_v[i] = fit_v<T>(R)[i];
-    for (int i = t; i < NK3; i += NT) s_a[i] = oct_wt<T>(R)[ce * NK3 + i] * kappa[s0 + i];
+    for (int i = t; i < NK * NK; i += NT) s_v[i] = R.fit_V64[i];
+    for (int i = t; i < NK3; i += NT) s_a[i] = R.oct_w[ce * NK3 + i] * (double)kappa[s0 + i];
     __syncthreads();
     for (int i = t; i < NK3; i += NT) {             // [g1 g2][k3]
         const int g12 = i / NK, k3 = i % NK;
-        T v = 0;
+        double v = 0;
 #pragma unroll
         for (int g3 = 0; g3 < NK; ++g3) v += s_v[k3 * NK + g3] * s_a[g12 * NK + g3];
         s_b[i] = v;
@@ -724,7 +723,7 @@ k_cut_moments_fit(DevRules R, const T* __restrict__ kappa, T* __restrict__ mom, 
     __syncthreads();
     for (int i = t; i < NK3; i += NT) {             // [g1][k2 k3]
         const int g1 = i / NK2, k2 = (i / NK) % NK, k3 = i % NK;
-        T v = 0;
+        double v = 0;
 #pragma unroll
         for (int g2 = 0; g2 < NK; ++g2) v += s_v[k2 * NK + g2] * s_b[(g1 * NK + g2) * NK + k3];
         s_a[i] = v;
@@ -732,10 +731,10 @@ k_cut_moments_fit(DevRules R, const T* __restrict__ kappa, T* __restrict__ mom, 
     __syncthreads();
     for (int i = t; i < NK3; i += NT) {             // [k1][k2 k3]
         const int k1 = i / NK2, k23 = i % NK2;
-        T v = 0;
+        double v = 0;
 #pragma unroll
         for (int g1 = 0; g1 < NK; ++g1) v += s_v[k1 * NK + g1] * s_a[g1 * NK2 + k23];
-        mom[(int64_t)blockIdx.x * NK3 + i] = v;
+        mom[(int64_t)blockIdx.x * NK3 + i] = (T)v;
     }
 }
 
