@@ -310,7 +310,10 @@ k_tensor_block(DevRules R, const T* __restrict__ C, int64_t ldc, T* __restrict__
     const int xs1 = R.xs[0][i1s];
     const int nu = R.xs[0][i1s + nr - 1] + R.nwin[0][i1s + nr - 1] - xs1;
     const int xs2 = R.xs[1][i2], n2 = R.nwin[1][i2], xs3 = R.xs[2][i3], n3 = R.nwin[2][i3];
-    if (nu > NU) return;                              // cannot happen for a direction with >= p + 2 elements
+    // The rows' windows cover the elements i1s - p .. i1s + nr - 1 (at most p + nr of them), two
+    // points each plus p - 1 more in each of at most two boundary elements: nu <= 4p + 2 nr - 2
+    // <= NW + 2 (RB - 1) < NU.  The check only guards the LDS bound.
+    if (nu > NU) return;
     if (t < nr) { s_off[t] = R.xs[0][i1s + t] - xs1; s_nw[t] = R.nwin[0][i1s + t]; }
     for (int k = t; k < 4 * M * NW; k += NT) {
         const int f = k / (M * NW), r = k % (M * NW);
