@@ -493,6 +493,14 @@ def main():
         schemes[k]["dwq_fit_ms"] = timed(step_f, nrep, torch)
     schemes["fit_kappa_slots"] = {"octree": R.n_kappa, "fit": Rf.n_kappa}
     del Rf, kf_slots
+    # the same step through wq_assemble (rows, remainder and the cut elements' element work on
+    # three streams, then the gather): bitwise the values of the timed step
+    fused = {}
+    for k in ("f64", "f32"):
+        vm, vk = vals[k]
+        R.assemble_fused(kap[k], vm, vk)
+        fused[k] = timed(lambda: R.assemble_fused(kap[k], vm, vk), nrep, torch)
+    schemes["fused_step_ms"] = fused
     # stiffness with the coefficient tensor of a geometry map (wq_assemble_tensor), beside the
     # scalar stiffness of the same rules; cut elements by the octree and by the fitted rule
     if wl.degree <= 4:

@@ -173,6 +173,18 @@ int wq_assemble_rows(const wq_rules* rules, int dtype, uint32_t which, const voi
 int cut_assemble(const wq_rules* rules, int dtype, uint32_t which, const void* kappa,
                  void* vals_mass, void* vals_stiff, void* stream);
 
+/* Rows and the whole cut part in one call (Section 1 row loop, Section 2.2 DWQ rows, Eq. (1)
+ * cut part): the same values as wq_assemble_rows followed by cut_assemble on the same stream,
+ * bitwise (every row is summed in the same order), with the work spread over three streams:
+ * the interior rows on the caller's stream, the cut rows and then the element Gauss remainder
+ * on the handle's second stream, the cut elements' moments and local rows on a third; the
+ * gather of the local rows follows on the caller's stream once all three are done.  All nnz
+ * entries of each requested matrix are OVERWRITTEN.  dtype WQ_F64 or WQ_F32.  Uses the
+ * stream-ordered scratch of cut_assemble.  Without the moment form (octree depth > 3), cut
+ * elements or the extra streams it runs the two calls in turn.  Asynchronous on stream. */
+int wq_assemble(const wq_rules* rules, int dtype, uint32_t which, const void* kappa,
+                void* vals_mass, void* vals_stiff, void* stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc): cut_assemble with the same arguments,
  * results and error behaviour, whose scratch (the moments and local rows of the cut

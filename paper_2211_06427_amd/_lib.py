@@ -16,7 +16,7 @@ STATUS = {0: "WQ_OK", -1: "WQ_EINVAL", -2: "WQ_ENOMEM", -3: "WQ_EHIP", -4: "WQ_E
 EXPORTS = ["wq_build_rules", "wq_rules_info_get", "wq_assemble_rows", "cut_assemble", "wq_assemble_adjoint",
            "wq_rules_free", "wq_last_error", "gauss_assemble", "wq_gauss_coords", "cut_assemble_noalloc",
            "wq_load_vector", "wq_extension_build", "wq_extension_info_get", "wq_extension_free", "wq_project",
-           "wq_l2_error", "wq_assemble_tensor"]
+           "wq_l2_error", "wq_assemble_tensor", "wq_assemble"]
 
 
 class WqMesh(C.Structure):
@@ -69,7 +69,7 @@ def load(path: str = LIB_PATH):
     vp, i32, u32 = C.c_void_p, C.c_int, C.c_uint32
     lib.wq_build_rules.argtypes = [C.POINTER(WqMesh), C.POINTER(WqLevelset), C.POINTER(WqOptions), vp, C.POINTER(vp)]
     lib.wq_rules_info_get.argtypes = [vp, C.POINTER(WqRulesInfo)]
-    for f in (lib.wq_assemble_rows, lib.cut_assemble, lib.cut_assemble_noalloc):
+    for f in (lib.wq_assemble_rows, lib.cut_assemble, lib.cut_assemble_noalloc, lib.wq_assemble):
         f.argtypes = [vp, i32, u32, vp, vp, vp, vp]
     lib.wq_assemble_adjoint.argtypes = [vp, i32, u32, vp, vp, vp, vp]
     lib.gauss_assemble.argtypes = [vp, i32, u32, vp, vp, vp, vp, vp]
@@ -88,7 +88,7 @@ def load(path: str = LIB_PATH):
     lib.wq_last_error.restype = C.c_char_p
     for name in ("wq_build_rules", "wq_rules_info_get", "wq_assemble_rows", "cut_assemble", "wq_assemble_adjoint",
                  "cut_assemble_noalloc", "gauss_assemble", "wq_gauss_coords", "wq_load_vector", "wq_extension_build",
-                 "wq_extension_info_get", "wq_project", "wq_l2_error", "wq_assemble_tensor"):
+                 "wq_extension_info_get", "wq_project", "wq_l2_error", "wq_assemble_tensor", "wq_assemble"):
         getattr(lib, name).restype = i32
     _lib = lib
     return lib

@@ -168,6 +168,13 @@ class Rules:
             (L.WQ_STIFF if vals_stiff is not None else 0)
         self._call(L.load().cut_assemble_noalloc, kappa, vals_mass, vals_stiff, which | parts)
 
+    def assemble_fused(self, kappa, vals_mass=None, vals_stiff=None, which=None):
+        """Rows and both cut parts in one call over three streams (wq_assemble); overwrites the
+        values, bitwise equal to assemble_rows followed by cut_assemble."""
+        which = which if which is not None else (L.WQ_MASS if vals_mass is not None else 0) | \
+            (L.WQ_STIFF if vals_stiff is not None else 0)
+        self._call(L.load().wq_assemble, kappa, vals_mass, vals_stiff, which)
+
     def assemble(self, kappa, which=L.WQ_MASS | L.WQ_STIFF, bf16x3=False):
         """Whole matrices: rows, then the cut part. Returns (M values or None, K values or None)."""
         vm = torch.empty(self.nnz, dtype=kappa.dtype, device=self.device) if which & L.WQ_MASS else None

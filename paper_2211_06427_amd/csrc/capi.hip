@@ -68,6 +68,47 @@ static int scratch_address(void** out) {
     return WQ_OK;
 }
 
+// rows + both cut parts over three streams (see wq_assemble in the header)
+template <typename T>
+static int assemble_fused(const wq_rules* r, uint32_t which, const T* kappa, T* vm, T* vk, hipStream_t s) {
+    const size_t bytes = cut_fused_scratch_bytes<T>(r);
+    if (bytes == 0 || !r->side || !r->side2 || !r->ev_join2) {
+        launch_rows<T>(r, which, kappa, vm, vk, s);
+        return launch_cut<T>(r, which, WQ_CUT_REMAINDER | WQ_CUT_OCTREE, kappa, vm, vk, s);
+    }
+    void* scratch = nullptr;
+    hipError_t err = r->scratch_alloc(&scratch, bytes, s);
+    if (err != hipSuccess)
+        return wq_set_error(WQ_ENOMEM, "wq_assemble: scratch allocation failed: %s", hipGetErrorString(err));
+    int st = WQ_OK;
+    {
+        std::lock_guard<std::mutex> lock(*r->side_mu);
+        const bool forked = hipEventRecord(r->ev_fork, s) == hipSuccess &&
+                            hipStreamWaitEvent(r->side, r->ev_fork, 0) == hipSuccess &&
+                            hipStreamWaitEvent(r->side2, r->ev_fork, 0) == hipSuccess;
+        if (!forked) {
+            (void)hipGetLastError();
+            launch_rows_split<T>(r, which, kappa, vm, vk, s, s);
+            st = launch_cut_prep<T>(r, which, kappa, vm, vk, s, s, scratch);
+        } else {
+            // interior rows on s; cut rows then the remainder on side; moments and local rows on side2
+            launch_rows_split<T>(r, which, kappa, vm, vk, s, r->side);
+            st = launch_cut_prep<T>(r, which, kappa, vm, vk, r->side, r->side2, scratch);
+            if (hipEventRecord(r->ev_join, r->side) != hipSuccess || hipEventRecord(r->ev_join2, r->side2) != hipSuccess ||
+                hipStreamWaitEvent(s, r->ev_join, 0) != hipSuccess || hipStreamWaitEvent(s, r->ev_join2, 0) != hipSuccess) {
+                (void)hipGetLastError();
+                (void)hipStreamSynchronize(r->side);     // the join failed: finish the side streams' work here
+                (void)hipStreamSynchronize(r->side2);
+            }
+        }
+    }
+    if (st == WQ_OK) launch_cut_finish<T>(r, which, scratch, vm, vk, s);
+    err = hipFreeAsync(scratch, s);
+    if (st) return st;
+    if (err != hipSuccess) return wq_set_error(WQ_EHIP, "wq_assemble: scratch release failed: %s", hipGetErrorString(err));
+    return WQ_OK;
+}
+
 extern "C" {
 
 const char* wq_last_error(void) { return g_err; }
@@ -203,6 +244,17 @@ int wq_assemble_adjoint(const wq_rules* r, int dtype, uint32_t which, const void
         st = launch_adjoint<float>(r, which, (const float*)gm, (const float*)gk, (float*)dk, (hipStream_t)stream);
     if (st) return st;
     return check_launch("wq_assemble_adjoint");
+}
+
+int wq_assemble(const wq_rules* r, int dtype, uint32_t which, const void* kappa, void* vm, void* vk, void* stream) {
+    int st = check_values(r, dtype, which, kappa, vm, vk, "wq_assemble");
+    if (st) return st;
+    if (dtype == WQ_BF16X3) return wq_set_error(WQ_EUNSUPPORTED, "wq_assemble: dtype must be F64 or F32");
+    if (r->nnz == 0) return WQ_OK;
+    st = dtype == WQ_F64 ? assemble_fused<double>(r, which, (const double*)kappa, (double*)vm, (double*)vk, (hipStream_t)stream)
+                         : assemble_fused<float>(r, which, (const float*)kappa, (float*)vm, (float*)vk, (hipStream_t)stream);
+    if (st) return st;
+    return check_launch("wq_assemble");
 }
 
 int wq_assemble_tensor(const wq_rules* r, int dtype, const void* C, void* vals_stiff, void* stream) {

@@ -1593,6 +1593,110 @@ template int launch_tensor_cut<double>(const wq_rules*, const double*, double*, 
 template int launch_tensor_cut<float>(const wq_rules*, const float*, float*, hipStream_t);
 #endif
 
+// Fused assembly (wq_assemble): cut_prep enqueues the octree part's element work (moments and
+// local rows into stream-ordered scratch allocated on s_alloc) on s_oct and the remainder on
+// s_rem; after the caller has joined both streams into s, cut_finish adds the local rows into
+// the cut rows (the gather) on s and releases the scratch.  Moment form only (octree depth <= 3).
+template <typename T, int P, int WHICH>
+static int launch_cut_prep_p(const wq_rules* H, const T* kappa, T* vm, T* vk, hipStream_t s_rem, hipStream_t s_oct,
+                             T* mom) {
+    const DevRules& R = H->R;
+    using C = MomCfg<P>;
+    const int64_t n = R.n_cut_elems;
+    T* loc = mom + n * C::NK3;
+    launch_moments<T, P>(H, kappa, mom, 0, n, s_oct);
+    if constexpr (P <= 4)
+        hipLaunchKernelGGL((k_cut_local<T, P, WHICH>), dim3((unsigned)(n * (P + 1))), dim3(256), 0, s_oct, R, R.cut_elems,
+                           (const T*)mom, loc, nullptr, nullptr, nullptr, 0);
+    else
+        hipLaunchKernelGGL((k_cut_local_a2<T, P, WHICH>), dim3((unsigned)(n * (P + 1) * (P + 1))), dim3(256), 0, s_oct, R,
+                           R.cut_elems, (const T*)mom, loc, 0);
+    launch_remainder<T, P, WHICH>(H, kappa, vm, vk, s_rem);
+    return WQ_OK;
+}
+
+template <typename T, int P, int WHICH>
+static void launch_cut_finish_p(const wq_rules* H, const T* mom, T* vm, T* vk, hipStream_t s) {
+    const DevRules& R = H->R;
+    using C = MomCfg<P>;
+    const int64_t n = R.n_cut_elems;
+    hipLaunchKernelGGL((k_cut_gather<T, P, WHICH>), dim3((unsigned)R.n_cut), dim3(RemCfg<P>::NT), 0, s, R,
+                       mom + n * C::NK3, vm, vk, 0, (int)n, (int64_t)0);
+}
+
+template <typename T, int P>
+static int launch_cut_prep_w(const wq_rules* H, uint32_t which, const T* kappa, T* vm, T* vk, hipStream_t s_rem,
+                             hipStream_t s_oct, T* mom) {
+    if (which == 1) return launch_cut_prep_p<T, P, 1>(H, kappa, vm, vk, s_rem, s_oct, mom);
+    if (which == 2) return launch_cut_prep_p<T, P, 2>(H, kappa, vm, vk, s_rem, s_oct, mom);
+    return launch_cut_prep_p<T, P, 3>(H, kappa, vm, vk, s_rem, s_oct, mom);
+}
+
+template <typename T, int P>
+static void launch_cut_finish_w(const wq_rules* H, uint32_t which, const T* mom, T* vm, T* vk, hipStream_t s) {
+    if (which == 1) launch_cut_finish_p<T, P, 1>(H, mom, vm, vk, s);
+    else if (which == 2) launch_cut_finish_p<T, P, 2>(H, mom, vm, vk, s);
+    else launch_cut_finish_p<T, P, 3>(H, mom, vm, vk, s);
+}
+
+// bytes of scratch of the fused assembly, 0 when it does not apply (no cut elements or rows,
+// octree deeper than three levels)
+template <typename T>
+size_t cut_fused_scratch_bytes(const wq_rules* H) {
+    const DevRules& R = H->R;
+    if (R.levels > 3 || R.n_cut_elems == 0 || R.n_cut == 0) return 0;
+    int64_t per = 0;
+    switch (R.p) {
+        case 1: per = moment_form_per_elem<1>(); break;
+        case 2: per = moment_form_per_elem<2>(); break;
+        case 3: per = moment_form_per_elem<3>(); break;
+        case 4: per = moment_form_per_elem<4>(); break;
+        case 5: per = moment_form_per_elem<5>(); break;
+        default: per = moment_form_per_elem<6>(); break;
+    }
+    return sizeof(T) * (size_t)(per * R.n_cut_elems);
+}
+
+template <typename T>
+int launch_cut_prep(const wq_rules* H, uint32_t which, const T* kappa, T* vm, T* vk, hipStream_t s_rem, hipStream_t s_oct,
+                    void* scratch) {
+    T* mom = (T*)scratch;
+    switch (H->R.p) {
+        case 1: return launch_cut_prep_w<T, 1>(H, which, kappa, vm, vk, s_rem, s_oct, mom);
+        case 2: return launch_cut_prep_w<T, 2>(H, which, kappa, vm, vk, s_rem, s_oct, mom);
+        case 3: return launch_cut_prep_w<T, 3>(H, which, kappa, vm, vk, s_rem, s_oct, mom);
+        case 4: return launch_cut_prep_w<T, 4>(H, which, kappa, vm, vk, s_rem, s_oct, mom);
+        case 5: return launch_cut_prep_w<T, 5>(H, which, kappa, vm, vk, s_rem, s_oct, mom);
+        default: return launch_cut_prep_w<T, 6>(H, which, kappa, vm, vk, s_rem, s_oct, mom);
+    }
+}
+
+template <typename T>
+void launch_cut_finish(const wq_rules* H, uint32_t which, const void* scratch, T* vm, T* vk, hipStream_t s) {
+    const T* mom = (const T*)scratch;
+    switch (H->R.p) {
+        case 1: launch_cut_finish_w<T, 1>(H, which, mom, vm, vk, s); break;
+        case 2: launch_cut_finish_w<T, 2>(H, which, mom, vm, vk, s); break;
+        case 3: launch_cut_finish_w<T, 3>(H, which, mom, vm, vk, s); break;
+        case 4: launch_cut_finish_w<T, 4>(H, which, mom, vm, vk, s); break;
+        case 5: launch_cut_finish_w<T, 5>(H, which, mom, vm, vk, s); break;
+        default: launch_cut_finish_w<T, 6>(H, which, mom, vm, vk, s); break;
+    }
+}
+
+#ifndef WQ_ONLY_F32
+template size_t cut_fused_scratch_bytes<double>(const wq_rules*);
+template int launch_cut_prep<double>(const wq_rules*, uint32_t, const double*, double*, double*, hipStream_t, hipStream_t,
+                                     void*);
+template void launch_cut_finish<double>(const wq_rules*, uint32_t, const void*, double*, double*, hipStream_t);
+#endif
+#ifndef WQ_ONLY_F64
+template size_t cut_fused_scratch_bytes<float>(const wq_rules*);
+template int launch_cut_prep<float>(const wq_rules*, uint32_t, const float*, float*, float*, hipStream_t, hipStream_t,
+                                    void*);
+template void launch_cut_finish<float>(const wq_rules*, uint32_t, const void*, float*, float*, hipStream_t);
+#endif
+
 template <typename T>
 int launch_cut(const wq_rules* H, uint32_t which, uint32_t parts, const T* kappa, T* vm, T* vk, hipStream_t s, void* buf,
                size_t cap) {

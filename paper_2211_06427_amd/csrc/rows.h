@@ -17,6 +17,17 @@ int launch_gauss(const wq_rules* H, uint32_t which, const T* kg, const T* kappa,
 int launch_gauss_coords(const wq_rules* H, double* xyz, hipStream_t s);
 template <typename T>
 int launch_tensor(const wq_rules* H, const T* C, T* vk, hipStream_t s);   // tensor.hip
+// fused assembly (wq_assemble): rows split over two streams (rows.hip); the cut part's element
+// work and remainder on two streams, then the gather (cut.hip)
+template <typename T>
+void launch_rows_split(const wq_rules* H, uint32_t which, const T* kappa, T* vm, T* vk, hipStream_t s_int, hipStream_t s_cut);
+template <typename T>
+size_t cut_fused_scratch_bytes(const wq_rules* H);
+template <typename T>
+int launch_cut_prep(const wq_rules* H, uint32_t which, const T* kappa, T* vm, T* vk, hipStream_t s_rem, hipStream_t s_oct,
+                    void* scratch);
+template <typename T>
+void launch_cut_finish(const wq_rules* H, uint32_t which, const void* scratch, T* vm, T* vk, hipStream_t s);
 template <typename T>
 int launch_tensor_cut(const wq_rules* H, const T* C, T* vk, hipStream_t s);   // cut.hip: cut elements, moment form
 

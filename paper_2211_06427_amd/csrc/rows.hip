@@ -1248,6 +1248,44 @@ void launch_rows(const wq_rules* H, uint32_t which, const T* kappa, T* vm, T* vk
     }
 }
 
+// interior rows on s_int and cut rows on s_cut, with no fork or join (the fused assembly orders
+// the streams itself)
+template <typename T, int P>
+static void launch_rows_split_p(const wq_rules* H, uint32_t which, const T* kappa, T* vm, T* vk, hipStream_t s_int,
+                                hipStream_t s_cut) {
+    if (which == 1) {
+        launch_cut_rows<T, P, 1>(H, kappa, vm, vk, s_cut);
+        launch_interior_rows<T, P, 1>(H, kappa, vm, vk, s_int);
+    } else if (which == 2) {
+        launch_cut_rows<T, P, 2>(H, kappa, vm, vk, s_cut);
+        launch_interior_rows<T, P, 2>(H, kappa, vm, vk, s_int);
+    } else {
+        launch_cut_rows<T, P, 3>(H, kappa, vm, vk, s_cut);
+        launch_interior_rows<T, P, 3>(H, kappa, vm, vk, s_int);
+    }
+}
+
+template <typename T>
+void launch_rows_split(const wq_rules* H, uint32_t which, const T* kappa, T* vm, T* vk, hipStream_t s_int,
+                       hipStream_t s_cut) {
+    switch (H->R.p) {
+        case 1: launch_rows_split_p<T, 1>(H, which, kappa, vm, vk, s_int, s_cut); break;
+        case 2: launch_rows_split_p<T, 2>(H, which, kappa, vm, vk, s_int, s_cut); break;
+        case 3: launch_rows_split_p<T, 3>(H, which, kappa, vm, vk, s_int, s_cut); break;
+        case 4: launch_rows_split_p<T, 4>(H, which, kappa, vm, vk, s_int, s_cut); break;
+        case 5: launch_rows_split_p<T, 5>(H, which, kappa, vm, vk, s_int, s_cut); break;
+        case 6: launch_rows_split_p<T, 6>(H, which, kappa, vm, vk, s_int, s_cut); break;
+    }
+}
+
+#ifndef WQ_ONLY_F32
+template void launch_rows_split<double>(const wq_rules*, uint32_t, const double*, double*, double*, hipStream_t,
+                                        hipStream_t);
+#endif
+#ifndef WQ_ONLY_F64
+template void launch_rows_split<float>(const wq_rules*, uint32_t, const float*, float*, float*, hipStream_t, hipStream_t);
+#endif
+
 #ifndef WQ_ONLY_F32
 template void launch_rows<double>(const wq_rules*, uint32_t, const double*, double*, double*, hipStream_t);
 #endif

@@ -39,9 +39,15 @@ struct wq_rules {
     // mutex keeps one call's record / wait sequence from interleaving with another's
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // third stream of the fused assembly (wq_assemble): the cut elements' moments and local
+    // rows run on it beside the rows and the remainder
+    hipStream_t side2 = nullptr;
+    hipEvent_t ev_join2 = nullptr;
     std::mutex* side_mu = nullptr;
     ~wq_rules() {
         if (side) (void)hipStreamDestroy(side);
+        if (side2) (void)hipStreamDestroy(side2);
+        if (ev_join2) (void)hipEventDestroy(ev_join2);
         if (ev_fork) (void)hipEventDestroy(ev_fork);
         if (ev_join) (void)hipEventDestroy(ev_join);
         delete side_mu;

@@ -1737,6 +1737,13 @@ int build_rules(const wq_mesh* mesh, const wq_levelset* ls, const wq_options* op
         H->side = nullptr; H->ev_fork = H->ev_join = nullptr;
     } else {
         H->side_mu = new std::mutex;
+        if (hipStreamCreateWithFlags(&H->side2, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&H->ev_join2, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            if (H->side2) (void)hipStreamDestroy(H->side2);
+            if (H->ev_join2) (void)hipEventDestroy(H->ev_join2);
+            H->side2 = nullptr; H->ev_join2 = nullptr;
+        }
     }
     *out = H;
     return WQ_OK;

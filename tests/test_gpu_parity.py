@@ -666,6 +666,43 @@ def test_fitted_cut_rule_plane48():
         assert float((a - b).norm() / b.norm()) <= 1e-3
 
 
+@pytest.mark.parametrize("name", ["plane6_p3", "ball5_p4", "ball4_p6", "plane48_p4", "ball4_p2_o4", "plane6_p3_rows"])
+def test_fused_assembly_bitwise(name):
+    """wq_assemble (rows, remainder and the cut elements' element work on three streams, then
+    the gather) equals wq_assemble_rows followed by cut_assemble, bitwise; also where it falls
+    back to the two calls (octree depth 4) and with every row on the cut path (Gauss rows)."""
+    print("case fused", name, flush=True)
+    from paper_2211_06427_amd import Rules
+    if name == "ball4_p2_o4":
+        wl = W.custom(4, 2, BALL, kappa="rf", seed=7, octree_levels=4)
+        R = rules_for(wl)
+    elif name == "plane6_p3_rows":
+        wl = SMALL["plane6_p3"]
+        R = Rules.from_workload(wl, gauss_rows=True)
+    else:
+        wl = SMALL.get(name) or HIGH.get(name) or W.workload(name)
+        R = rules_for(wl)
+    for dtype in (torch.float64, torch.float32):
+        k = kappa_slots(R, wl, dtype)
+        a = [torch.full((R.nnz,), float("nan"), dtype=dtype, device=R.device) for _ in range(2)]
+        b = [torch.empty(R.nnz, dtype=dtype, device=R.device) for _ in range(2)]
+        R.assemble_fused(k, *a)
+        R.assemble_rows(k, *b)
+        R.cut_assemble(k, *b)
+        m1 = torch.full((R.nnz,), float("nan"), dtype=dtype, device=R.device)
+        R.assemble_fused(k, m1, None)                   # one matrix
+        torch.cuda.synchronize()
+        if name == "ball4_p2_o4":
+            # deeper octrees add their leaves with atomics (order varies between calls)
+            rp = R.row_ptr().cpu().numpy()
+            for x, y in ((a[0], b[0]), (a[1], b[1]), (m1, b[0])):
+                assert row_errors(x.cpu().numpy(), y.cpu().numpy(), rp)[0] <= TOL[dtype], dtype
+        else:
+            assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]), dtype
+            assert torch.equal(m1, b[0])
+        del a, b, m1
+
+
 @pytest.mark.parametrize("name", ["plane6_p3", "ball4_p6", "plane48_p4"])
 def test_cut_parts_in_one_call(name):
     """cut_assemble with both parts in one call (the remainder beside the octree moments and
