@@ -530,8 +530,11 @@ k_tensor_rem(DevRules R, const T* __restrict__ C, int64_t ldc, T* __restrict__ v
         const int r = r0 + sl;
         const bool active = r < nrem;
         int e[3] = {0, 0, 0}, kI[3] = {0, 0, 0};
+        int64_t blk = 0;
         if (active) {
-            const int pk = R.rem_list[l0 + r].x;
+            const int2 en = R.rem_list[l0 + r];
+            const int pk = en.x;
+            blk = en.y;
             kI[0] = pk & 15; kI[1] = (pk >> 4) & 15; kI[2] = (pk >> 8) & 15;
             for (int d = 0; d < 3; ++d) e[d] = I[d] - kI[d];
         }
@@ -547,7 +550,7 @@ k_tensor_rem(DevRules R, const T* __restrict__ C, int64_t ldc, T* __restrict__ v
         if (active)
             for (int q = u; q < NP; q += NTS) {      // flux F_e = w sum_d C_de d_d B_I
                 const int g1 = q / (P1 * P1), g2 = (q / P1) % P1, g3 = q % P1;
-                const int64_t s = slot_of(R, e[0] * P1 + g1, e[1] * P1 + g2, e[2] * P1 + g3);
+                const int64_t s = R.blk_slot[blk * NP + q];   // canonical slot of the Gauss point
                 const T w = (T)(R.gw[g1] * R.gw[g2] * R.gw[g3]) * wscale;
                 const T v0 = s_b[sl][0][0][kI[0]][g1], v1 = s_b[sl][1][0][kI[1]][g2], v2 = s_b[sl][2][0][kI[2]][g3];
                 const T gt[3] = {s_b[sl][0][1][kI[0]][g1] * v1 * v2, v0 * s_b[sl][1][1][kI[1]][g2] * v2,
