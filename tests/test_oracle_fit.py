@@ -1,4 +1,4 @@
-"""CPU pins of the fitted cut-element rule (the survey's cheaper cut integration): NK^3 =
+"""CPU pins of the fitted cut-element rule (a cheaper cut-element integration): NK^3 =
 (2p+1)^3 tensor Gauss points per cut element whose weights reproduce the octree rule on every
 polynomial of degree <= 2p in each variable.
 
