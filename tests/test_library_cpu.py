@@ -66,6 +66,17 @@ def test_invalid_arguments_rejected_before_device_work():
     ls.kind = 0
     opts = _lib.WqOptions(9, 0)
     assert lib.wq_build_rules(ctypes.byref(mesh), ctypes.byref(ls), ctypes.byref(opts), None, ctypes.byref(h)) == -1
+    opts = _lib.WqOptions(3, 0x10)                      # unknown option bit
+    assert lib.wq_build_rules(ctypes.byref(mesh), ctypes.byref(ls), ctypes.byref(opts), None, ctypes.byref(h)) == -1
+    opts = _lib.WqOptions(4, _lib.WQ_OPT_MOMENT_FIT)     # the fitted rule needs depth <= 3
+    assert lib.wq_build_rules(ctypes.byref(mesh), ctypes.byref(ls), ctypes.byref(opts), None, ctypes.byref(h)) == -5
+    mesh.degree = 5
+    opts = _lib.WqOptions(3, _lib.WQ_OPT_TENSOR)         # the coefficient tensor: degrees 1..4
+    assert lib.wq_build_rules(ctypes.byref(mesh), ctypes.byref(ls), ctypes.byref(opts), None, ctypes.byref(h)) == -5
+    assert b"degrees 1..4" in lib.wq_last_error()
+    mesh.degree = 2
+    assert lib.wq_assemble(None, 0, 3, None, None, None, None) == -1
+    assert lib.wq_assemble_tensor(None, 0, None, None, None) == -1
     assert lib.wq_assemble_rows(None, 0, 3, None, None, None, None) == -1
     assert lib.cut_assemble(None, 0, 3, None, None, None, None) == -1
     assert lib.wq_assemble_adjoint(None, 0, 3, None, None, None, None) == -1
