@@ -128,12 +128,16 @@ k_tensor_rows(DevRules R, const T* __restrict__ C, int64_t ldc, const int32_t* _
     for (int i = 0; i < Cf::NACC; ++i) acc[i] = 0;
     for (int qC = 0; qC < nC; ++qC) {
         const int yC = s_y[2][qC];
-        for (int k = t; k < 6 * nB * nA; k += NT) {   // tensor components at the points (qA, qB, qC)
-            const int comp = k / (nB * nA), qB = (k / nA) % nB, qA = k % nA;
+        for (int k = t; k < nB * nA; k += NT) {       // tensor components at the points (qA, qB, qC)
+            const int qB = k / nA, qA = k % nA;
             const int yA = s_y[0][qA], yB = s_y[1][qB];
             const int64_t slot = slot_of(R, pick3(0, dA, dB, yA, yB, yC), pick3(1, dA, dB, yA, yB, yC),
                                          pick3(2, dA, dB, yA, yB, yC));
-            s_c[comp][qB * NA + qA] = C[comp * ldc + slot];
+            T c[6];
+#pragma unroll
+            for (int comp = 0; comp < 6; ++comp) c[comp] = C[comp * ldc + slot];
+#pragma unroll
+            for (int comp = 0; comp < 6; ++comp) s_c[comp][qB * NA + qA] = c[comp];
         }
         __syncthreads();
         // stage A: T1[term][qB][jA] = sum_qA W_A^f[jA][qA] C_term(qA, qB)
